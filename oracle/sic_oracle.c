@@ -1,0 +1,344 @@
+/*
+ * sic_oracle.c - plain, slow, FP64 CPU reference of one simplex-in-cell (SIC)
+ * 1D1V Vlasov-Poisson step (Kates-Harbeck, Totorica, Zrake & Abel,
+ * arXiv:1506.07207).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity oracle for the GPU
+ * library: it shares no code, header, table or helper with it, and only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It is written for a reader checking it against the paper, not for
+ * speed: no blocking, no fusion, no vectorisation.  Build with IEEE semantics
+ * (-O2 -ffp-contract=off, no fast-math).
+ *
+ * Units and conventions (paper section 2.1, eqs. 1-3 with C = 1):
+ *   - the Vlasov equation accelerates a tracer by -dPhi/dx, written E here, so
+ *     the Poisson equation d2Phi/dx2 = -rho becomes dE/dx = rho;
+ *   - rho = n - nbar: the mean density is removed (periodic box);
+ *   - the mesh has nc cells [j dx, (j+1) dx), dx = L / nc, with mesh values at
+ *     the cell centres X_j = (j + 1/2) dx (the grid points of section 2.4).
+ *
+ * Step (section 2.3 and the "solve, gather, move" paragraph after it):
+ *   deposit: rho_j = (1/dx) sum_i o_ji q_i, with o_ji the overlap of the box
+ *            function of segment i (height 1/|length|) with cell j
+ *            (eqs. "overlap" and "rho_sum");
+ *   solve:   3-point finite-difference Poisson equation on the periodic mesh,
+ *            E_j = -(Phi_{j+1} - Phi_{j-1}) / (2 dx); solved here exactly in
+ *            the discrete Fourier basis that diagonalises it;
+ *   gather:  linear (first-order, W_1) weighting from the grid points
+ *            (section 2.4 and the gather remark of section 2.3);
+ *   move:    leapfrog, v^{n+1/2} = v^{n-1/2} + dt E^n(x^n),
+ *            x^{n+1} = x^n + dt v^{n+1/2}, wrapped into [0, L).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - a point exactly on a face belongs to the lower cell (the tie rule of
+ *     the zero-order weight W_0, section 2.4); this decides where a
+ *     zero-length segment puts its charge;
+ *   - a zero-length segment deposits all of its charge into that one cell
+ *     (footnote on equal tracer positions, section 2.3: any handling that
+ *     keeps the total charge is acceptable);
+ *   - a segment joins its tracers along the shorter way round the periodic
+ *     box (minimum image); a separation of exactly L/2 is taken downwards;
+ *   - every segment of sheet s carries the same charge q_s; a tracer carries
+ *     mass q_s for kinetic energy and momentum;
+ *   - KE^n = 1/2 sum q v^{n-1/2} v^{n+1/2} (the leapfrog-centred product),
+ *     W_E^n = 1/2 dx sum_j E_j^2.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_ROW 8 /* step, t, W_E, KE, momentum, total_charge, max_segment, flags */
+#define ORC_FLAG_NONFINITE 1.0
+#define ORC_FLAG_LONG_SEGMENT 2.0
+
+/* Reduce a position into [0, L).  One period either way is handled by a
+ * single add or subtract (x - L is exact for x in [L, 2L)); a sum that rounds
+ * up to L is the point 0 of the periodic box. */
+double orc_wrap(double x, double L)
+{
+    if (x >= 0.0 && x < L) return x;
+    if (x >= L && x < 2.0 * L) return x - L;
+    if (x < 0.0 && x >= -L) {
+        double y = x + L;
+        return (y >= L) ? 0.0 : y;
+    }
+    {
+        double y = x - L * floor(x / L);
+        if (y < 0.0) y += L;
+        if (y >= L) y = 0.0;
+        return y;
+    }
+}
+
+/* Signed separation from a to b along the shorter way round the box. */
+double orc_min_image(double a, double b, double L)
+{
+    double d = b - a;
+    if (d >= 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+    return d;
+}
+
+static int mod_cell(long j, int nc)
+{
+    long r = j % nc;
+    return (int)(r < 0 ? r + nc : r);
+}
+
+/* Cell that owns a point, with a point on a face assigned to the lower cell
+ * (the W_0 tie rule). */
+int orc_point_cell(double x, double L, int nc)
+{
+    double dx = L / nc;
+    long j = (long)ceil(x / dx) - 1;
+    return mod_cell(j, nc);
+}
+
+static double face(int j, int nc, double dx, double L)
+{
+    return (j >= nc) ? L : (double)j * dx;
+}
+
+/* Add w * |[lo, hi] ∩ cell_j| for every cell, 0 <= lo <= hi <= L. */
+static void add_interval(double lo, double hi, double w, double L, int nc, double *Q)
+{
+    double dx = L / nc;
+    /* one extra cell either side guards against lo/dx or hi/dx rounding
+     * across a face; cells that do not meet [lo, hi] add nothing */
+    int j0 = (int)floor(lo / dx) - 1;
+    int j1 = (int)floor(hi / dx) + 1;
+    if (j0 < 0) j0 = 0;
+    if (j1 > nc - 1) j1 = nc - 1;
+    for (int j = j0; j <= j1; ++j) {
+        double a = face(j, nc, dx, L);
+        double b = face(j + 1, nc, dx, L);
+        double left = lo > a ? lo : a;
+        double right = hi < b ? hi : b;
+        if (right > left) Q[j] += w * (right - left);
+    }
+}
+
+/* Deposit one segment from tracer position a to tracer position b (both in
+ * [0, L)) carrying charge q: the box function of height 1/length is
+ * integrated over every cell it overlaps (eqs. "overlap" and "rho_sum",
+ * multiplied by the cell volume).  Returns the segment length. */
+double orc_deposit_segment(double a, double b, double q, double L, int nc, double *Q)
+{
+    double d = orc_min_image(a, b, L);
+    if (d == 0.0) {
+        Q[orc_point_cell(a, L, nc)] += q;
+        return 0.0;
+    }
+    /* The segment as a set of at most two non-wrapping intervals. */
+    double lo1, hi1, lo2 = 0.0, hi2 = 0.0;
+    int two = 0;
+    if (d > 0.0) {
+        if (b > a) { lo1 = a; hi1 = b; }
+        else { lo1 = a; hi1 = L; lo2 = 0.0; hi2 = b; two = 1; }
+    } else {
+        if (b < a) { lo1 = b; hi1 = a; }
+        else { lo1 = b; hi1 = L; lo2 = 0.0; hi2 = a; two = 1; }
+    }
+    double len = (hi1 - lo1) + (two ? (hi2 - lo2) : 0.0);
+    if (!(len > 0.0)) { /* a sub-rounding separation: treat as a point */
+        Q[orc_point_cell(a, L, nc)] += q;
+        return fabs(d);
+    }
+    double w = q / len;
+    add_interval(lo1, hi1, w, L, nc, Q);
+    if (two) add_interval(lo2, hi2, w, L, nc, Q);
+    return fabs(d);
+}
+
+/* Charge per cell Q_j = dx * rho_j (before the mean is removed) for all
+ * sheets.  Sheets are stored one after another; a closed sheet also joins its
+ * last tracer to its first (section 2.3, periodic closure).  Q is zeroed. */
+void orc_deposit(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                 const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    double maxseg = 0.0;
+    memset(Q, 0, sizeof(double) * (size_t)nc);
+    int64_t base = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        int nt = n_tracers[s];
+        int nseg = closed[s] ? nt : nt - 1;
+        for (int t = 0; t < nseg; ++t) {
+            int u = (t + 1 == nt) ? 0 : t + 1;
+            double len = orc_deposit_segment(x[base + t], x[base + u], q[s], L, nc, Q);
+            if (len > maxseg) maxseg = len;
+        }
+        base += nt;
+    }
+    if (max_segment) *max_segment = maxseg;
+}
+
+/* Solve the periodic 3-point Poisson equation
+ *     (Phi_{j+1} - 2 Phi_j + Phi_{j-1}) / dx^2 = -rho_j,  rho_j = Q_j/dx - nbar,
+ * and return the centred-difference field E_j = -(Phi_{j+1} - Phi_{j-1})/(2 dx)
+ * and W_E = 1/2 dx sum E_j^2.  The discrete Fourier modes exp(2 pi i j m / nc)
+ * diagonalise both operators: Phi_m = dx^2 rho_m / (4 sin^2(pi m / nc)) and
+ * E_m = -i sin(2 pi m / nc) Phi_m / dx; mode 0 (the mean) is zero.  Plain
+ * O(nc^2) transforms. */
+void orc_solve(double L, int nc, const double *Q, double *E, double *W_E, double *total_charge)
+{
+    double dx = L / nc;
+    double qtot = 0.0;
+    for (int j = 0; j < nc; ++j) qtot += Q[j];
+    double nbar = qtot / L;
+    double *rho = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *cs = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *er = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *ei = (double *)malloc(sizeof(double) * (size_t)nc);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int j = 0; j < nc; ++j) {
+        rho[j] = Q[j] / dx - nbar;
+        cs[j] = cos(two_pi * (double)j / (double)nc);
+        sn[j] = sin(two_pi * (double)j / (double)nc);
+    }
+    if (nc % 2 == 0) { sn[nc / 2] = 0.0; cs[nc / 2] = -1.0; }
+    if (nc % 4 == 0) { cs[nc / 4] = 0.0; sn[nc / 4] = 1.0; cs[3 * nc / 4] = 0.0; sn[3 * nc / 4] = -1.0; }
+    sn[0] = 0.0; cs[0] = 1.0;
+    er[0] = 0.0; ei[0] = 0.0;
+    for (int m = 1; m < nc; ++m) {
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int j = 0; j < nc; ++j) {
+            re += rho[j] * cs[idx];
+            im -= rho[j] * sn[idx];
+            idx += m;
+            if (idx >= nc) idx -= nc;
+        }
+        double s = sin(0.5 * two_pi * (double)m / (double)nc);
+        double lap = 4.0 * s * s / (dx * dx);
+        double pr = re / lap, pi = im / lap;
+        double g = sn[m] / dx;
+        er[m] = g * pi;   /* (-i g)(pr + i pi) = g pi - i g pr */
+        ei[m] = -g * pr;
+    }
+    double w = 0.0;
+    for (int j = 0; j < nc; ++j) {
+        double acc = 0.0;
+        int idx = 0;
+        for (int m = 0; m < nc; ++m) {
+            acc += er[m] * cs[idx] - ei[m] * sn[idx];
+            idx += j;
+            if (idx >= nc) idx -= nc;
+        }
+        E[j] = acc / (double)nc;
+        w += E[j] * E[j];
+    }
+    if (W_E) *W_E = 0.5 * dx * w;
+    if (total_charge) *total_charge = qtot;
+    free(rho); free(cs); free(sn); free(er); free(ei);
+}
+
+/* Field at a tracer: first-order weighting W_1(x - X_j) = 1 - |x - X_j|/dx
+ * from the two grid points X_j = (j + 1/2) dx around x (periodic). */
+double orc_gather(double L, int nc, const double *E, double x)
+{
+    double dx = L / nc;
+    long j0 = (long)floor(x / dx - 0.5);
+    double X0 = ((double)j0 + 0.5) * dx;
+    double X1 = ((double)j0 + 1.5) * dx;
+    double w0 = 1.0 - fabs(x - X0) / dx;
+    double w1 = 1.0 - fabs(x - X1) / dx;
+    return w0 * E[mod_cell(j0, nc)] + w1 * E[mod_cell(j0 + 1, nc)];
+}
+
+void orc_gather_many(double L, int nc, const double *E, int64_t n, const double *x, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_gather(L, nc, E, x[i]);
+}
+
+/* Per-tracer mass: every tracer of sheet s carries q_s. */
+static void sheet_of_tracers(int n_sheets, const int32_t *n_tracers, const double *q, double *mass)
+{
+    int64_t base = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        for (int t = 0; t < n_tracers[s]; ++t) mass[base + t] = q[s];
+        base += n_tracers[s];
+    }
+}
+
+/* One leapfrog move with the field E^n: kick then drift.  Returns KE^n and
+ * momentum^n through the pointers (centred on x^n). */
+void orc_push(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
+              const double *E, double *x, double *v, double *ke, double *mom)
+{
+    int64_t n = 0;
+    for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
+    double *mass = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    sheet_of_tracers(n_sheets, n_tracers, q, mass);
+    double k = 0.0, p = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double e = orc_gather(L, nc, E, x[i]);
+        double vn = v[i] + dt * e;
+        k += 0.5 * mass[i] * v[i] * vn;
+        p += mass[i] * 0.5 * (v[i] + vn);
+        x[i] = orc_wrap(x[i] + dt * vn, L);
+        v[i] = vn;
+    }
+    free(mass);
+    if (ke) *ke = k;
+    if (mom) *mom = p;
+}
+
+static double row_flags(double L, int nc, const double *E, double maxseg)
+{
+    double f = 0.0;
+    for (int j = 0; j < nc; ++j)
+        if (!isfinite(E[j])) { f += ORC_FLAG_NONFINITE; break; }
+    if (!isfinite(maxseg)) { if (f == 0.0) f += ORC_FLAG_NONFINITE; }
+    else if (maxseg > 0.45 * L) f += ORC_FLAG_LONG_SEGMENT;
+    return f;
+}
+
+/* Full run.  With init_kick = 1, (x0, v0) are the initial positions and
+ * velocities: x0 is wrapped into [0, L), the field E^0 is computed and the
+ * velocities are moved back half a step, v^{-1/2} = v^0 - dt/2 E^0(x^0).
+ * With init_kick = 0, v0 is already v^{-1/2} at step step0 (a resumed state).
+ * hist holds (n_steps + 1) rows of ORC_ROW doubles; the KE and momentum of
+ * the last row need the next push and are NaN.  Final positions, v^{N-1/2},
+ * charge per cell and field are returned when the pointers are non-null. */
+int orc_run(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
+            const int32_t *closed, const double *x0, const double *v0, int64_t step0, int init_kick,
+            int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out, double *E_out)
+{
+    int64_t n = 0;
+    for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
+    double *x = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *Q = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *E = (double *)malloc(sizeof(double) * (size_t)nc);
+    if (!x || !v || !Q || !E) { free(x); free(v); free(Q); free(E); return 1; }
+    for (int64_t i = 0; i < n; ++i) { x[i] = orc_wrap(x0[i], L); v[i] = v0[i]; }
+
+    double W, qt, ms;
+    orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
+    orc_solve(L, nc, Q, E, &W, &qt);
+    if (init_kick) {
+        for (int64_t i = 0; i < n; ++i) v[i] = v[i] - 0.5 * dt * orc_gather(L, nc, E, x[i]);
+    }
+    double *row = hist;
+    row[0] = (double)step0; row[1] = (double)step0 * dt; row[2] = W; row[3] = NAN; row[4] = NAN;
+    row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
+    for (int64_t it = 0; it < n_steps; ++it) {
+        double ke, mom;
+        orc_push(L, nc, dt, n_sheets, n_tracers, q, E, x, v, &ke, &mom);
+        hist[it * ORC_ROW + 3] = ke;
+        hist[it * ORC_ROW + 4] = mom;
+        orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
+        orc_solve(L, nc, Q, E, &W, &qt);
+        row = hist + (it + 1) * ORC_ROW;
+        row[0] = (double)(step0 + it + 1); row[1] = (double)(step0 + it + 1) * dt; row[2] = W;
+        row[3] = NAN; row[4] = NAN; row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
+    }
+    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);
+    if (v_out) memcpy(v_out, v, sizeof(double) * (size_t)n);
+    if (Q_out) memcpy(Q_out, Q, sizeof(double) * (size_t)nc);
+    if (E_out) memcpy(E_out, E, sizeof(double) * (size_t)nc);
+    free(x); free(v); free(Q); free(E);
+    return 0;
+}
