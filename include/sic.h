@@ -1,0 +1,252 @@
+/*
+ * sic.h - C ABI of libsic: the simplex-in-cell (SIC) 1D1V Vlasov-Poisson
+ * step on MI355X (gfx950).
+ *
+ * Method (Kates-Harbeck, Totorica, Zrake & Abel, arXiv:1506.07207):
+ *   - section 2.1, eqs. 1-3: Vlasov-Poisson with C = 1 and the mean density
+ *     removed on a periodic box; the acceleration E = -dPhi/dx obeys
+ *     dE/dx = rho = n - nbar (units: plasma frequency 1, mean density 1);
+ *   - section 2.2-2.3: the plasma is a set of sheets of ordered tracers; each
+ *     pair of adjacent tracers bounds a segment (a "particle") carrying a fixed
+ *     charge spread uniformly between them (the box function); a closed sheet
+ *     also joins its last tracer to its first;
+ *   - section 2.3, eqs. "overlap" and "rho_sum": the charge of every segment is
+ *     deposited onto the periodic mesh by its exact overlap with each cell;
+ *   - the paragraph after eq. "j_sum": solve for the field, gather it to the
+ *     tracers with linear (first-order) weighting (section 2.4) and move the
+ *     tracers as PIC particles - here with a leapfrog.
+ *
+ * Mesh: n_cells cells [j dx, (j+1) dx), dx = L / n_cells; charge, density and
+ * field values sit at the cell centres (j + 1/2) dx.  The field solve is the
+ * 3-point periodic Poisson equation with a centred-difference field.
+ *
+ * Conventions shared by every call:
+ *   - Tracer arrays (x, v) hold the tracers of sheet 0, then sheet 1, ... as
+ *     contiguous float64 values (sheet-major).
+ *   - mem_kind says where a caller pointer lives: SIC_MEM_HOST (ordinary or
+ *     pinned host memory) or SIC_MEM_DEVICE (device memory on the current HIP
+ *     device, e.g. a torch CUDA tensor's data pointer).
+ *   - The library copies what it is given and never keeps a caller pointer;
+ *     caller buffers only need to stay valid for the duration of the call.
+ *   - All device work is ordered on the hipStream_t given at creation (NULL =
+ *     the default stream).  Calls marked "async" return before the GPU has
+ *     finished; calls that return data synchronise that stream first.
+ *   - Errors are returned as sic_status; nothing is thrown across the ABI.
+ *     sic_last_error() gives a message for the last failing call on a handle.
+ *   - A handle must not be used from two host threads at once.
+ */
+#ifndef SIC_H
+#define SIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIC_ABI_VERSION 1
+#define SIC_MAX_CELLS 4096
+
+typedef enum sic_status {
+    SIC_OK = 0,
+    SIC_EINVAL = 1,   /* invalid argument (sizes, pointers, non-finite inputs) */
+    SIC_ENOMEM = 2,   /* device or host allocation failed */
+    SIC_EDEVICE = 3,  /* a HIP runtime call failed */
+    SIC_ESTATE = 4,   /* call out of order (e.g. push before solve) */
+    SIC_EBUSY = 5,    /* batch: no free slot or over the tracer budget */
+    SIC_ENOTSUP = 6   /* valid but unsupported request (e.g. deposit_order != 0) */
+} sic_status;
+
+/* Position storage.
+ *   SIC_FP64:      x in float64; mesh charge accumulated with float64 atomics.
+ *   SIC_SPLIT_F32: x as int32 cell index + float32 offset in [0, 1) cell;
+ *   SIC_SPLIT_U32: x as int32 cell index + uint32 fraction of a cell.
+ * Both split forms keep v in float64, deposit into int64 fixed point (bitwise
+ * reproducible, order independent) and solve in float64. */
+typedef enum sic_precision { SIC_FP64 = 0, SIC_SPLIT_F32 = 1, SIC_SPLIT_U32 = 2 } sic_precision;
+
+enum { SIC_MEM_HOST = 0, SIC_MEM_DEVICE = 1 };
+
+/* sic_diag.flags bits (sticky per simulation). */
+enum {
+    SIC_DIAG_NONFINITE = 1,    /* a non-finite field value was produced */
+    SIC_DIAG_LONG_SEGMENT = 2  /* some segment longer than 0.45 L (segments join
+                                  tracers the shorter way round the box, so a
+                                  segment cannot be longer than L/2) */
+};
+
+typedef struct sic_config {
+    int32_t abi_version;   /* SIC_ABI_VERSION */
+    int32_t n_cells;       /* 1 .. SIC_MAX_CELLS */
+    double L;              /* box length, > 0 */
+    double dt;             /* time step, > 0 */
+    int32_t precision;     /* sic_precision */
+    int32_t deposit_order; /* 0: piecewise-constant segments (section 2.3); others SIC_ENOTSUP */
+    int64_t history_rows;  /* capacity of the per-simulation diagnostics ring; 0: 65536 */
+} sic_config;
+
+typedef struct sic_sheet {
+    int32_t n_tracers; /* >= 2 */
+    int32_t closed;    /* 1: segment from the last tracer back to the first; 0: open chain */
+    double q_seg;      /* charge carried by every segment of the sheet (tracer mass too) */
+} sic_sheet;
+
+/* One row of diagnostics, at step n (positions x^n, time t = n dt):
+ *   W_E          = 1/2 dx sum_j E_j^2 (field energy, section 3 "E_pot");
+ *   KE           = 1/2 sum q v^{n-1/2} v^{n+1/2}, momentum = sum q (v^{n-1/2}+v^{n+1/2})/2;
+ *                  both need the push from step n, so the newest row has them
+ *                  as NaN;
+ *   total_charge = sum_j Q_j (charge conservation check);
+ *   max_segment  = longest segment at x^n. */
+typedef struct sic_diag {
+    int64_t step;
+    double t;
+    double W_E;
+    double KE;
+    double momentum;
+    double total_charge;
+    double max_segment;
+    int64_t flags;
+} sic_diag;
+
+typedef struct sic_sim sic_sim;
+
+/* Creates a simulation and ingests its initial state: x0 is reduced into
+ * [0, L), the charge Q^0 is deposited, the field E^0 solved, and the
+ * velocities are moved back half a step, v^{-1/2} = v0 - dt/2 E^0(x0)
+ * (leapfrog start).  On return the simulation is at step 0 with its field
+ * current.  x0 and v0 hold sum(n_tracers) values.  hip_stream: hipStream_t or
+ * NULL.  Synchronous (returns after the ingest has run). */
+sic_status sic_init(const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
+                    const double *v0, int32_t mem_kind, void *hip_stream, sic_sim **out);
+
+/* Deposit (section 2.3): Q <- charge of every segment at the current
+ * positions x^n, by exact box-cell overlap.  Allowed in any state.  Async. */
+sic_status sic_deposit(sic_sim *sim);
+
+/* Solve: E^n and W_E^n from Q.  Requires a deposit of the current positions
+ * since the last push (else SIC_ESTATE).  Async. */
+sic_status sic_solve_field(sic_sim *sim);
+
+/* Gather + move: v^{n+1/2} = v^{n-1/2} + dt E^n(x^n), x^{n+1} = x^n + dt v^{n+1/2}
+ * wrapped into [0, L); the step becomes n + 1.  Requires the field of the
+ * current step (else SIC_ESTATE).  Async. */
+sic_status sic_push(sic_sim *sim);
+
+/* n_steps full steps.  Each step moves the tracers with the current field,
+ * deposits the new positions and solves the new field, so on return the field
+ * is current for the new step.  If the field is stale it is brought up to date
+ * first.  Steps run as captured HIP graphs.  Async. */
+sic_status sic_step(sic_sim *sim, int64_t n_steps);
+
+/* Synchronises the stream and reads diagnostics.  out (may be NULL) receives
+ * the newest row.  rho_out / E_out (NULL or n_cells doubles, host memory)
+ * receive the charge density n_j - nbar and the field of the newest solve.
+ * history_out (NULL or *history_len rows) receives the oldest-first rows still
+ * in the ring; *history_len is set to the number of rows written (or, when
+ * history_out is NULL, to the number available). */
+sic_status sic_diagnostics(sic_sim *sim, sic_diag *out, double *rho_out, double *E_out, sic_diag *history_out,
+                           int64_t *history_len);
+
+/* Checkpoint: x^n and v^{n-1/2} (sum(n_tracers) doubles each, in mem_kind
+ * memory) and the step n.  Synchronous. */
+sic_status sic_get_state(sic_sim *sim, double *x, double *v_half, int64_t *step, int32_t mem_kind);
+
+/* Resume: replaces positions and velocities with x^n (wrapped into [0, L)) and
+ * v^{n-1/2}, sets the step to n and marks the field stale (the next sic_step
+ * deposits and solves first).  Synchronous. */
+sic_status sic_set_state(sic_sim *sim, int64_t step, const double *x, const double *v_half, int32_t mem_kind);
+
+void sic_destroy(sic_sim *sim);
+const char *sic_status_str(sic_status s);
+/* Message of the last failing call on sim; with sim == NULL, of the last
+ * failing call on this host thread (e.g. a sic_init that returned no handle). */
+const char *sic_last_error(const sic_sim *sim);
+int32_t sic_abi_version(void);
+
+/* Launch shape of the tracer kernels (see sic_tune in the batch section).
+ *   tile_chunks:   64-tracer chunks per workgroup work item (one LDS mesh
+ *                  accumulation and flush per item); 0 = automatic;
+ *   block_threads: 64, 128, 256, 512 or 1024; 0 = automatic;
+ *   grid_blocks:   workgroups of the persistent tracer kernel; 0 = automatic. */
+typedef struct sic_tuning {
+    int32_t tile_chunks;
+    int32_t block_threads;
+    int32_t grid_blocks;
+    int32_t reserved;
+} sic_tuning;
+
+sic_status sic_set_tuning(sic_sim *sim, const sic_tuning *t);
+sic_status sic_get_tuning(const sic_sim *sim, sic_tuning *t);
+
+/* ------------------------------------------------------------------------
+ * Batch: many independent simulations resident on one GPU, advanced together
+ * (continuous batching).  Every slot follows exactly the single-simulation
+ * semantics above; the batch only shares launches.  All instances of a batch
+ * use the batch's precision.
+ * ---------------------------------------------------------------------- */
+typedef struct sic_batch sic_batch;
+
+/* budget_tracers: maximum resident tracers over all slots; max_slots: maximum
+ * resident simulations; max_cells: largest n_cells admitted (<= SIC_MAX_CELLS);
+ * history_rows: diagnostics rows kept per slot (ring; 0: 4096).  Synchronous. */
+sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t max_cells, int32_t precision,
+                            int64_t history_rows, void *hip_stream, sic_batch **out);
+
+/* Admits one simulation that will run n_steps steps (n_steps < 0: until
+ * released).  Ingests it as sic_init does.  Returns SIC_EBUSY when no slot is
+ * free or its tracers do not fit the budget.  *slot receives the slot index.
+ * Ordered on the batch stream; returns after the inputs have been copied. */
+sic_status sic_batch_admit(sic_batch *b, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets,
+                           const double *x0, const double *v0, int32_t mem_kind, int64_t n_steps,
+                           int32_t *slot);
+
+/* Advances every unfinished resident simulation by up to n_steps steps in
+ * shared launches (captured HIP graphs); a simulation stops when its own step
+ * count is reached.  Async. */
+sic_status sic_batch_step(sic_batch *b, int64_t n_steps);
+
+/* Synchronises the stream and lists slots whose simulation has finished and
+ * has not been reported before (at most cap entries). */
+sic_status sic_batch_poll(sic_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done);
+
+/* Synchronises and copies a slot's diagnostics as sic_diagnostics does. */
+sic_status sic_batch_result(sic_batch *b, int32_t slot, sic_diag *out, double *rho_out, double *E_out,
+                            sic_diag *history_out, int64_t *history_len);
+
+/* Checkpoint of one slot, as sic_get_state. */
+sic_status sic_batch_get_state(sic_batch *b, int32_t slot, double *x, double *v_half, int64_t *step,
+                               int32_t mem_kind);
+
+/* Frees a slot (finished or not) and its tracer budget.  Ordered on the stream. */
+sic_status sic_batch_release(sic_batch *b, int32_t slot);
+
+/* Resident tracers and simulations. */
+sic_status sic_batch_usage(const sic_batch *b, int64_t *tracers, int32_t *slots);
+
+sic_status sic_batch_set_tuning(sic_batch *b, const sic_tuning *t);
+sic_status sic_batch_get_tuning(const sic_batch *b, sic_tuning *t);
+void sic_batch_destroy(sic_batch *b);
+const char *sic_batch_last_error(const sic_batch *b);
+
+/* Average device time (milliseconds, from HIP events on the batch stream) of
+ * the last sic_batch_step call, per step, split into the tracer kernel and the
+ * field-solve kernel; 0 when not measured.  Enable with timing = 1 (adds
+ * events between launches, so graphs are not used while it is on). */
+sic_status sic_batch_set_timing(sic_batch *b, int32_t timing);
+sic_status sic_batch_last_timing(const sic_batch *b, double *tracer_ms, double *solve_ms);
+
+/* Single-simulation timing, as sic_batch_set_timing / sic_batch_last_timing. */
+sic_status sic_set_timing(sic_sim *sim, int32_t timing);
+sic_status sic_last_timing(const sic_sim *sim, double *tracer_ms, double *solve_ms);
+
+/* Device copy bandwidth in GB/s (bytes read + bytes written per second) of a
+ * plain streaming copy of n_bytes, best of iters runs, on the given stream.
+ * A calibration for the HBM roofline.  Synchronous. */
+sic_status sic_copy_bandwidth(int64_t n_bytes, int32_t iters, void *hip_stream, double *gbps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIC_H */

@@ -1,0 +1,1171 @@
+// sic_api.hip - host side of libsic: the C ABI declared in include/sic.h.
+//
+// One internal object, Pool, backs both handles.  A pool owns device memory
+// for a fixed number of simulation slots, a chunk-granular tracer arena, the
+// per-slot meshes and diagnostics rings, and the work-item list that the
+// tracer kernel walks.  A sic_sim is a pool with one slot; a sic_batch is a
+// pool with many slots whose simulations advance in shared launches.
+//
+// Per step the device runs two kernels: the tracer kernel (gather, leapfrog
+// move, deposit of the new positions into the mesh) and the field solve (one
+// workgroup per slot).  Runs of steps are captured once into HIP graphs on a
+// private stream and replayed on the caller's stream; the graphs read the
+// item list and slot table from device memory, so admitting or retiring a
+// simulation never needs a new capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sic.h"
+#include "sic_internal.h"
+
+using namespace sic;
+
+namespace {
+
+constexpr int kGraphSteps = 32;         // steps per captured graph
+constexpr int kDefaultGrid = 2048;      // persistent tracer workgroups (8 per CU)
+constexpr int kDefaultBlock = 256;
+constexpr int kMinTile = 4;             // chunks per work item, lower bound
+constexpr int kMaxTile = 256;
+
+enum SimState { kStale = 0, kDeposited = 1, kField = 2 };
+
+struct Range {
+  int64_t begin, end;
+};
+
+// First-fit allocator of contiguous chunk ranges.
+class ChunkAllocator {
+ public:
+  void init(int64_t n) {
+    free_.clear();
+    if (n > 0) free_.push_back({0, n});
+  }
+  int64_t alloc(int64_t n) {
+    for (size_t i = 0; i < free_.size(); ++i) {
+      if (free_[i].end - free_[i].begin >= n) {
+        const int64_t b = free_[i].begin;
+        free_[i].begin += n;
+        if (free_[i].begin == free_[i].end) free_.erase(free_.begin() + (long)i);
+        return b;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t b, int64_t n) {
+    if (n <= 0) return;
+    Range r{b, b + n};
+    auto it = std::lower_bound(free_.begin(), free_.end(), r,
+                               [](const Range &a, const Range &c) { return a.begin < c.begin; });
+    it = free_.insert(it, r);
+    // merge with neighbours
+    if (it + 1 != free_.end() && it->end == (it + 1)->begin) {
+      it->end = (it + 1)->end;
+      free_.erase(it + 1);
+    }
+    if (it != free_.begin() && (it - 1)->end == it->begin) {
+      (it - 1)->end = it->end;
+      free_.erase(it);
+    }
+  }
+
+ private:
+  std::vector<Range> free_;
+};
+
+struct SlotHost {
+  bool live = false;
+  int32_t n_cells = 0;
+  double L = 0.0, dt = 0.0;
+  int64_t n_tracers = 0;
+  int32_t chunk_begin = 0, n_chunks = 0;
+  std::vector<int64_t> chunk_in_off;
+  int64_t *d_in_off = nullptr;
+  int state = kStale;
+  bool pending_push = false, pending_dep = false;
+  bool reported = false;
+};
+
+}  // namespace
+
+struct Pool {
+  int prec = 0;
+  bool batch = false;
+  hipStream_t stream = nullptr;  // caller's stream
+  hipStream_t cap = nullptr;     // private capture stream
+  int32_t slot_cap = 0, max_cells = 0;
+  int64_t chunk_cap = 0, item_cap = 0, hist_rows = 0, budget = 0;
+  int64_t used_tracers = 0;
+  int32_t used_slots = 0;
+  size_t lds_bytes = 0;
+
+  uint64_t *xs = nullptr;
+  double *vs = nullptr;
+  double2 *halo[2] = {nullptr, nullptr};
+  ChunkDesc *chunks = nullptr;
+  Item *items = nullptr;
+  int32_t *n_items = nullptr;
+  InstDesc *inst = nullptr;
+  int2 *slot_items = nullptr;
+  Partial *partials = nullptr;
+  void *meshP = nullptr;
+  void *meshD = nullptr;
+  double *meshE = nullptr;
+  double *meshRho = nullptr;
+  DiagRow *hist = nullptr;
+  int32_t *done = nullptr;
+  int32_t *slot_ids = nullptr;
+
+  std::vector<SlotHost> slots;
+  ChunkAllocator alloc;
+  std::vector<Item> items_h;
+  std::vector<int2> slot_items_h;
+  int32_t n_items_h = 0;
+  int parity = 0;
+  sic_tuning tune{};  // requested (0 = automatic)
+  int block = kDefaultBlock, grid = kDefaultGrid, tile = kMinTile;
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_objs;
+  bool timing = false;
+  double t_tracer = 0.0, t_solve = 0.0;
+  std::string err;
+};
+
+struct sic_sim {
+  Pool *pool;
+};
+struct sic_batch {
+  Pool *pool;
+};
+
+namespace {
+
+// Message of the last failure on this host thread (reported through
+// sic_last_error(NULL) when no handle exists, e.g. after a failed sic_init).
+thread_local std::string g_last_error;
+
+sic_status fail(Pool *p, sic_status s, const std::string &msg) {
+  if (p) p->err = msg;
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPCHK(p, expr)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      return fail((p), SIC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    }                                                                                            \
+  } while (0)
+
+#define LAUNCHCHK(p, expr)                                                                       \
+  do {                                                                                           \
+    int e_ = (expr);                                                                             \
+    if (e_ != 0) {                                                                               \
+      return fail((p), SIC_EDEVICE,                                                              \
+                  std::string(#expr) + ": " + hipGetErrorString((hipError_t)e_));                \
+    }                                                                                            \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t n) {
+  if (n == 0) n = 1;
+  return hipMalloc((void **)p, n * sizeof(T));
+}
+
+size_t acc_size(int prec) { return prec == kFP64 ? sizeof(double) : sizeof(long long); }
+
+void destroy_graphs(Pool *p) {
+  for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  for (auto g : p->graph_objs) hipGraphDestroy(g);
+  p->graph_objs.clear();
+}
+
+void pool_free(Pool *p) {
+  if (!p) return;
+  if (p->stream || true) hipStreamSynchronize(p->stream);
+  destroy_graphs(p);
+  for (auto &s : p->slots)
+    if (s.d_in_off) hipFree(s.d_in_off);
+  void *bufs[] = {p->xs,         p->vs,       p->halo[0], p->halo[1], p->chunks, p->items,  p->n_items,
+                  p->inst,       p->slot_items, p->partials, p->meshP, p->meshD,  p->meshE,  p->meshRho,
+                  p->hist,       p->done,     p->slot_ids};
+  for (void *b : bufs)
+    if (b) hipFree(b);
+  if (p->cap) hipStreamDestroy(p->cap);
+  delete p;
+}
+
+sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells, int64_t chunk_cap,
+                       int64_t hist_rows, int64_t budget, void *stream, Pool **out, std::string *err) {
+  Pool *p = new Pool();
+  p->prec = prec;
+  p->batch = batch;
+  p->stream = (hipStream_t)stream;
+  p->slot_cap = slot_cap;
+  p->max_cells = max_cells;
+  p->chunk_cap = chunk_cap;
+  p->item_cap = chunk_cap / kMinTile + slot_cap + 1;
+  p->hist_rows = hist_rows;
+  p->budget = budget;
+  p->lds_bytes = 2 * (size_t)max_cells * acc_size(prec) + 48 * sizeof(double);
+  p->slots.resize(slot_cap);
+  p->slot_items_h.assign(slot_cap, make_int2(0, 0));
+  p->alloc.init(chunk_cap);
+
+  auto bail = [&](const std::string &m, sic_status s) {
+    if (err) *err = m;
+    g_last_error = m;
+    pool_free(p);
+    return s;
+  };
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, n)                                                                  \
+  e = dalloc(&(ptr), (n));                                                             \
+  if (e != hipSuccess) return bail(std::string("hipMalloc ") + #ptr + ": " + hipGetErrorString(e), SIC_ENOMEM);
+  const size_t slotsz = (size_t)chunk_cap * kChunk;
+  ALLOC(p->xs, slotsz);
+  ALLOC(p->vs, slotsz);
+  ALLOC(p->halo[0], (size_t)chunk_cap);
+  ALLOC(p->halo[1], (size_t)chunk_cap);
+  ALLOC(p->chunks, (size_t)chunk_cap);
+  ALLOC(p->items, (size_t)p->item_cap);
+  ALLOC(p->n_items, 1);
+  ALLOC(p->inst, (size_t)slot_cap);
+  ALLOC(p->slot_items, (size_t)slot_cap);
+  ALLOC(p->partials, (size_t)p->item_cap);
+  {
+    const size_t mc = (size_t)slot_cap * max_cells;
+    long long *mp = nullptr, *md = nullptr;
+    ALLOC(mp, mc);
+    p->meshP = mp;
+    ALLOC(md, mc);
+    p->meshD = md;
+    ALLOC(p->meshE, mc);
+    ALLOC(p->meshRho, mc);
+  }
+  ALLOC(p->hist, (size_t)slot_cap * hist_rows);
+  ALLOC(p->done, (size_t)slot_cap);
+  ALLOC(p->slot_ids, (size_t)slot_cap);
+#undef ALLOC
+  e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(std::string("hipStreamCreate: ") + hipGetErrorString(e), SIC_EDEVICE);
+  // zero-initialise everything the kernels accumulate into or read as tables
+  const size_t mc = (size_t)slot_cap * max_cells;
+  e = hipMemsetAsync(p->meshP, 0, mc * 8, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->meshD, 0, mc * 8, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->meshE, 0, mc * 8, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->meshRho, 0, mc * 8, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->inst, 0, sizeof(InstDesc) * (size_t)slot_cap, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->slot_items, 0, sizeof(int2) * (size_t)slot_cap, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->done, 0, sizeof(int32_t) * (size_t)slot_cap, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->n_items, 0, sizeof(int32_t), p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->partials, 0, sizeof(Partial) * (size_t)p->item_cap, p->stream);
+  if (e != hipSuccess) return bail(std::string("hipMemsetAsync: ") + hipGetErrorString(e), SIC_EDEVICE);
+  std::vector<int32_t> ids(slot_cap);
+  for (int32_t i = 0; i < slot_cap; ++i) ids[i] = i;
+  e = hipMemcpyAsync(p->slot_ids, ids.data(), sizeof(int32_t) * (size_t)slot_cap, hipMemcpyHostToDevice,
+                     p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return bail(std::string("init copy: ") + hipGetErrorString(e), SIC_EDEVICE);
+  if (p->lds_bytes > 65536) {
+    int le = set_tracer_lds_limit(prec, p->lds_bytes);
+    if (le != 0) return bail(std::string("LDS limit: ") + hipGetErrorString((hipError_t)le), SIC_ENOTSUP);
+  }
+  *out = p;
+  return SIC_OK;
+}
+
+// Work-item size in chunks for the pool's current contents.
+int auto_tile(const Pool *p, int64_t total_chunks) {
+  if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
+  // aim for about four work items per workgroup slot of the machine, with
+  // at least one chunk per wavefront of the workgroup
+  const int64_t per = (total_chunks + 2047) / 2048;
+  int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(64, per));
+  t = (t + 3) / 4 * 4;
+  return std::max(t, p->block / 64);
+}
+
+void apply_launch_shape(Pool *p) {
+  p->block = p->tune.block_threads > 0 ? p->tune.block_threads : kDefaultBlock;
+  if (p->tune.grid_blocks > 0) p->grid = p->tune.grid_blocks;
+  else if (p->batch) p->grid = kDefaultGrid;
+  else p->grid = std::max(1, std::min<int>(kDefaultGrid, p->n_items_h));
+}
+
+// Rebuilds the work-item list from the live slots and uploads it (stream
+// ordered; synchronises so host staging can be reused).
+sic_status rebuild_items(Pool *p) {
+  int64_t total = 0;
+  for (auto &s : p->slots)
+    if (s.live) total += s.n_chunks;
+  p->tile = auto_tile(p, total);
+  p->items_h.clear();
+  for (int32_t i = 0; i < p->slot_cap; ++i) {
+    SlotHost &s = p->slots[i];
+    const int32_t first = (int32_t)p->items_h.size();
+    if (s.live) {
+      for (int32_t c = 0; c < s.n_chunks; c += p->tile) {
+        Item it;
+        it.inst = i;
+        it.chunk_begin = s.chunk_begin + c;
+        it.chunk_end = s.chunk_begin + std::min(s.n_chunks, c + p->tile);
+        it.pad = 0;
+        p->items_h.push_back(it);
+      }
+    }
+    p->slot_items_h[i] = make_int2(first, (int32_t)p->items_h.size() - first);
+  }
+  if ((int64_t)p->items_h.size() > p->item_cap) return fail(p, SIC_ENOMEM, "work-item list over capacity");
+  p->n_items_h = (int32_t)p->items_h.size();
+  apply_launch_shape(p);
+  if (!p->items_h.empty())
+    HIPCHK(p, hipMemcpyAsync(p->items, p->items_h.data(), sizeof(Item) * p->items_h.size(), hipMemcpyHostToDevice,
+                             p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->n_items, &p->n_items_h, sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->slot_items, p->slot_items_h.data(), sizeof(int2) * p->slot_items_h.size(),
+                           hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return SIC_OK;
+}
+
+TracerArgs tracer_args(Pool *p, int mode, int slot) {
+  TracerArgs a;
+  const bool one = slot >= 0;
+  const int first = one ? p->slot_items_h[slot].x : 0;
+  a.items = p->items + first;
+  a.n_items = one ? &(p->slot_items + slot)->y : p->n_items;
+  a.inst = p->inst;
+  a.chunks = p->chunks;
+  a.xs = p->xs;
+  a.vs = p->vs;
+  if (mode == (kPush | kDeposit)) {
+    a.halo_in = p->halo[p->parity];
+    a.halo_out = p->halo[p->parity ^ 1];
+  } else {
+    a.halo_in = p->halo[p->parity];
+    a.halo_out = p->halo[p->parity];
+  }
+  a.meshP = p->meshP;
+  a.meshD = p->meshD;
+  a.meshE = p->meshE;
+  a.partials = p->partials + first;
+  a.mesh_cells = p->max_cells;
+  a.respect_active = (p->batch && !one) ? 1 : 0;
+  return a;
+}
+
+SolveArgs solve_args(Pool *p, int flags, int slot) {
+  SolveArgs a;
+  a.inst = p->inst;
+  a.slot_items = p->slot_items;
+  a.slot_list = slot >= 0 ? p->slot_ids + slot : nullptr;
+  a.partials = p->partials;
+  a.meshP = p->meshP;
+  a.meshD = p->meshD;
+  a.meshE = p->meshE;
+  a.meshRho = p->meshRho;
+  a.hist = p->hist;
+  a.done = p->done;
+  a.flags = flags;
+  a.respect_active = (p->batch && slot < 0) ? 1 : 0;
+  return a;
+}
+
+int grid_for(Pool *p, int slot) {
+  if (slot >= 0) return std::max(1, std::min(p->grid, p->slot_items_h[slot].y));
+  return p->grid;
+}
+
+sic_status launch_tracer_mode(Pool *p, int mode, int slot, hipStream_t st) {
+  TracerArgs a = tracer_args(p, mode, slot);
+  LAUNCHCHK(p, launch_tracers(p->prec, mode, a, grid_for(p, slot), p->block, p->lds_bytes, st));
+  return SIC_OK;
+}
+
+sic_status launch_solve_mode(Pool *p, int flags, int slot, hipStream_t st) {
+  SolveArgs a = solve_args(p, flags, slot);
+  LAUNCHCHK(p, launch_solve(p->prec, a, slot >= 0 ? 1 : p->slot_cap, st));
+  return SIC_OK;
+}
+
+// One fused step for the whole pool (every live slot; batch pools skip
+// finished slots): move + deposit, then solve.
+sic_status enqueue_fused(Pool *p, hipStream_t st) {
+  sic_status s = launch_tracer_mode(p, kPush | kDeposit, -1, st);
+  if (s != SIC_OK) return s;
+  int flags = kHavePush | kHaveDeposit | (p->batch ? kBatchStep : 0);
+  s = launch_solve_mode(p, flags, -1, st);
+  if (s != SIC_OK) return s;
+  p->parity ^= 1;
+  return SIC_OK;
+}
+
+sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
+  auto key = std::make_pair(k, p->parity);
+  auto it = p->graphs.find(key);
+  if (it != p->graphs.end()) {
+    *out = it->second;
+    return SIC_OK;
+  }
+  const int parity0 = p->parity;
+  HIPCHK(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+  sic_status s = SIC_OK;
+  for (int64_t i = 0; i < k && s == SIC_OK; ++i) s = enqueue_fused(p, p->cap);
+  p->parity = parity0;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap, &g);
+  if (s != SIC_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(p, SIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  p->graph_objs.push_back(g);
+  p->graphs[key] = ex;
+  *out = ex;
+  return SIC_OK;
+}
+
+sic_status run_fused(Pool *p, int64_t n) {
+  if (n <= 0) return SIC_OK;
+  if (p->timing) {
+    std::vector<hipEvent_t> ev(3 * (size_t)n);
+    for (auto &e : ev) HIPCHK(p, hipEventCreate(&e));
+    sic_status s = SIC_OK;
+    for (int64_t i = 0; i < n && s == SIC_OK; ++i) {
+      hipEventRecord(ev[3 * i], p->stream);
+      s = launch_tracer_mode(p, kPush | kDeposit, -1, p->stream);
+      if (s != SIC_OK) break;
+      hipEventRecord(ev[3 * i + 1], p->stream);
+      s = launch_solve_mode(p, kHavePush | kHaveDeposit | (p->batch ? kBatchStep : 0), -1, p->stream);
+      hipEventRecord(ev[3 * i + 2], p->stream);
+      p->parity ^= 1;
+    }
+    hipError_t e = hipStreamSynchronize(p->stream);
+    double tt = 0.0, ts = 0.0;
+    for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+      float a = 0.f, b = 0.f;
+      hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+      hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+      tt += a;
+      ts += b;
+    }
+    for (auto &x : ev) hipEventDestroy(x);
+    if (s != SIC_OK) return s;
+    if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("timed step: ") + hipGetErrorString(e));
+    p->t_tracer = tt / (double)n;
+    p->t_solve = ts / (double)n;
+    return SIC_OK;
+  }
+  while (n > 0) {
+    const int64_t k = std::min<int64_t>(n, kGraphSteps);
+    hipGraphExec_t ex;
+    sic_status s = get_graph(p, k, &ex);
+    if (s != SIC_OK) return s;
+    HIPCHK(p, hipGraphLaunch(ex, p->stream));
+    if (k & 1) p->parity ^= 1;
+    n -= k;
+  }
+  return SIC_OK;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+sic_status validate(Pool *p, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
+                    const double *v0) {
+  if (!cfg || !sheets || !x0 || !v0) return fail(p, SIC_EINVAL, "null argument");
+  if (cfg->abi_version != SIC_ABI_VERSION) return fail(p, SIC_EINVAL, "abi_version mismatch");
+  if (cfg->n_cells < 1 || cfg->n_cells > SIC_MAX_CELLS) return fail(p, SIC_EINVAL, "n_cells out of range");
+  if (!(cfg->L > 0.0) || !finite(cfg->L)) return fail(p, SIC_EINVAL, "L must be positive and finite");
+  if (!(cfg->dt > 0.0) || !finite(cfg->dt)) return fail(p, SIC_EINVAL, "dt must be positive and finite");
+  if (cfg->precision < 0 || cfg->precision > 2) return fail(p, SIC_EINVAL, "unknown precision");
+  if (cfg->deposit_order != 0) return fail(p, SIC_ENOTSUP, "only deposit_order 0 is implemented");
+  if (cfg->history_rows < 0) return fail(p, SIC_EINVAL, "history_rows < 0");
+  if (n_sheets < 1) return fail(p, SIC_EINVAL, "need at least one sheet");
+  for (int32_t s = 0; s < n_sheets; ++s) {
+    if (sheets[s].n_tracers < 2) return fail(p, SIC_EINVAL, "every sheet needs at least 2 tracers");
+    if (sheets[s].closed != 0 && sheets[s].closed != 1) return fail(p, SIC_EINVAL, "closed must be 0 or 1");
+    if (!finite(sheets[s].q_seg)) return fail(p, SIC_EINVAL, "non-finite segment charge");
+  }
+  return SIC_OK;
+}
+
+bool all_finite_host(const double *a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// Admits one simulation into a free slot and ingests it (see sic_init).
+sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
+                      const double *v0, int32_t mem_kind, int64_t n_steps, int32_t *slot_out) {
+  sic_status st = validate(p, cfg, sheets, n_sheets, x0, v0);
+  if (st != SIC_OK) return st;
+  if (cfg->precision != p->prec) return fail(p, SIC_EINVAL, "precision differs from the batch precision");
+  if (cfg->n_cells > p->max_cells) return fail(p, SIC_EINVAL, "n_cells above the batch max_cells");
+  if (mem_kind != SIC_MEM_HOST && mem_kind != SIC_MEM_DEVICE) return fail(p, SIC_EINVAL, "bad mem_kind");
+
+  int64_t n_tr = 0, n_ch = 0;
+  for (int32_t s = 0; s < n_sheets; ++s) {
+    n_tr += sheets[s].n_tracers;
+    n_ch += (sheets[s].n_tracers + kChunk - 1) / kChunk;
+  }
+  if (mem_kind == SIC_MEM_HOST && (!all_finite_host(x0, n_tr) || !all_finite_host(v0, n_tr)))
+    return fail(p, SIC_EINVAL, "non-finite initial position or velocity");
+  int32_t slot = -1;
+  for (int32_t i = 0; i < p->slot_cap; ++i)
+    if (!p->slots[i].live) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return fail(p, SIC_EBUSY, "no free slot");
+  if (p->budget > 0 && p->used_tracers + n_tr > p->budget) return fail(p, SIC_EBUSY, "over the tracer budget");
+  const int64_t cb = p->alloc.alloc(n_ch);
+  if (cb < 0) return fail(p, SIC_EBUSY, "tracer arena full");
+
+  // chunk descriptors
+  double total_abs = 0.0;
+  for (int32_t s = 0; s < n_sheets; ++s) {
+    const int64_t nseg = sheets[s].closed ? sheets[s].n_tracers : sheets[s].n_tracers - 1;
+    total_abs += std::fabs(sheets[s].q_seg) * (double)nseg;
+  }
+  double q_unit = 1.0, q_scale = 1.0;
+  if (p->prec != kFP64) {
+    // fixed point: total |charge| just under 2^62 units
+    int ex = 0;
+    std::frexp(total_abs > 0.0 ? total_abs : 1.0, &ex);  // total_abs < 2^ex
+    const int S = 62 - ex;
+    q_scale = std::ldexp(1.0, S);
+    q_unit = std::ldexp(1.0, -S);
+  }
+  std::vector<ChunkDesc> cd((size_t)n_ch);
+  SlotHost &sh = p->slots[slot];
+  sh.chunk_in_off.assign((size_t)n_ch, 0);
+  {
+    int64_t c = 0, in = 0;
+    for (int32_t s = 0; s < n_sheets; ++s) {
+      const int32_t nt = sheets[s].n_tracers;
+      const int32_t nch = (nt + kChunk - 1) / kChunk;
+      const int64_t first = cb + c;
+      for (int32_t k = 0; k < nch; ++k) {
+        ChunkDesc &d = cd[(size_t)(c + k)];
+        d.q = sheets[s].q_seg;
+        d.q_fix = p->prec != kFP64 ? (int64_t)std::llrint(sheets[s].q_seg * q_scale) : 0;
+        d.n_valid = std::min(kChunk, nt - k * kChunk);
+        d.inst = slot;
+        d.pad = 0;
+        if (k + 1 < nch) d.partner = (int32_t)(first + k + 1);
+        else d.partner = sheets[s].closed ? (int32_t)first : -1;
+        sh.chunk_in_off[(size_t)(c + k)] = in + (int64_t)k * kChunk;
+      }
+      c += nch;
+      in += nt;
+    }
+  }
+  sh.live = true;
+  sh.n_cells = cfg->n_cells;
+  sh.L = cfg->L;
+  sh.dt = cfg->dt;
+  sh.n_tracers = n_tr;
+  sh.chunk_begin = (int32_t)cb;
+  sh.n_chunks = (int32_t)n_ch;
+  sh.state = kStale;
+  sh.pending_push = sh.pending_dep = false;
+  sh.reported = false;
+
+  InstDesc I;
+  std::memset(&I, 0, sizeof(I));
+  I.L = cfg->L;
+  I.half_L = 0.5 * cfg->L;
+  I.dx = cfg->L / cfg->n_cells;
+  I.inv_dx = (double)cfg->n_cells / cfg->L;
+  I.dt = cfg->dt;
+  I.q_unit = q_unit;
+  I.mesh_off = (int64_t)slot * p->max_cells;
+  I.hist_off = (int64_t)slot * p->hist_rows;
+  I.hist_cap = p->hist_rows;
+  I.step = 0;
+  I.steps_left = p->batch ? n_steps : -1;
+  I.n_cells = cfg->n_cells;
+  I.active = (p->batch && n_steps == 0) ? 0 : 1;
+  I.flags = 0;
+  I.live = 1;
+
+  auto undo = [&]() {
+    p->alloc.release(cb, n_ch);
+    sh.live = false;
+    sh.chunk_in_off.clear();
+  };
+  hipError_t e = hipSuccess;
+  if (!sh.d_in_off) {
+    e = hipMalloc((void **)&sh.d_in_off, sizeof(int64_t) * (size_t)std::max<int64_t>(n_ch, 1));
+  } else {
+    hipFree(sh.d_in_off);
+    e = hipMalloc((void **)&sh.d_in_off, sizeof(int64_t) * (size_t)std::max<int64_t>(n_ch, 1));
+  }
+  if (e != hipSuccess) {
+    sh.d_in_off = nullptr;
+    undo();
+    return fail(p, SIC_ENOMEM, "hipMalloc chunk offsets");
+  }
+  double *stage = nullptr;
+  const double *dx0 = x0, *dv0 = v0;
+  if (mem_kind == SIC_MEM_HOST) {
+    e = hipMalloc((void **)&stage, sizeof(double) * 2 * (size_t)n_tr);
+    if (e != hipSuccess) {
+      undo();
+      return fail(p, SIC_ENOMEM, "hipMalloc staging");
+    }
+    e = hipMemcpyAsync(stage, x0, sizeof(double) * (size_t)n_tr, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(stage + n_tr, v0, sizeof(double) * (size_t)n_tr, hipMemcpyHostToDevice, p->stream);
+    dx0 = stage;
+    dv0 = stage + n_tr;
+  }
+  const int32_t zero = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->chunks + cb, cd.data(), sizeof(ChunkDesc) * (size_t)n_ch, hipMemcpyHostToDevice,
+                       p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sh.d_in_off, sh.chunk_in_off.data(), sizeof(int64_t) * (size_t)n_ch, hipMemcpyHostToDevice,
+                       p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->done + slot, &zero, sizeof(zero), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    if (stage) hipFree(stage);
+    undo();
+    return fail(p, SIC_EDEVICE, std::string("admission copies: ") + hipGetErrorString(e));
+  }
+  p->used_tracers += n_tr;
+  p->used_slots += 1;
+  st = rebuild_items(p);
+  if (st != SIC_OK) {
+    if (stage) hipFree(stage);
+    return st;
+  }
+  // ingest: place tracers, deposit, solve, half back-kick
+  IngestArgs ia;
+  ia.x_in = dx0;
+  ia.v_in = dv0;
+  ia.chunk_in_off = sh.d_in_off;
+  ia.chunk_begin = (int32_t)cb;
+  ia.n_chunks = (int32_t)n_ch;
+  ia.chunks = p->chunks;
+  ia.inst = p->inst;
+  ia.xs = p->xs;
+  ia.vs = p->vs;
+  ia.halo = p->halo[p->parity];
+  int le = launch_ingest(p->prec, ia, p->stream);
+  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->inst, p->slot_ids + slot, 1, p->stream);
+  if (le != 0) {
+    if (stage) hipFree(stage);
+    return fail(p, SIC_EDEVICE, std::string("ingest: ") + hipGetErrorString((hipError_t)le));
+  }
+  st = launch_tracer_mode(p, kDeposit, slot, p->stream);
+  if (st == SIC_OK) st = launch_solve_mode(p, kHaveDeposit, slot, p->stream);
+  if (st == SIC_OK) st = launch_tracer_mode(p, kKickHalf, slot, p->stream);
+  e = hipStreamSynchronize(p->stream);
+  if (stage) hipFree(stage);
+  if (st != SIC_OK) return st;
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("ingest: ") + hipGetErrorString(e));
+  sh.state = kField;
+  *slot_out = slot;
+  return SIC_OK;
+}
+
+sic_status pool_release(Pool *p, int32_t slot) {
+  if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return fail(p, SIC_EINVAL, "slot not live");
+  SlotHost &sh = p->slots[slot];
+  InstDesc I;
+  std::memset(&I, 0, sizeof(I));
+  HIPCHK(p, hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  p->alloc.release(sh.chunk_begin, sh.n_chunks);
+  p->used_tracers -= sh.n_tracers;
+  p->used_slots -= 1;
+  sh.live = false;
+  sh.chunk_in_off.clear();
+  if (sh.d_in_off) {
+    hipFree(sh.d_in_off);
+    sh.d_in_off = nullptr;
+  }
+  return rebuild_items(p);
+}
+
+sic_status read_inst(Pool *p, int32_t slot, InstDesc *I) {
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  HIPCHK(p, hipMemcpy(I, p->inst + slot, sizeof(InstDesc), hipMemcpyDeviceToHost));
+  return SIC_OK;
+}
+
+sic_status pool_diagnostics(Pool *p, int32_t slot, sic_diag *out, double *rho_out, double *E_out,
+                            sic_diag *history_out, int64_t *history_len) {
+  if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return fail(p, SIC_EINVAL, "slot not live");
+  InstDesc I;
+  sic_status st = read_inst(p, slot, &I);
+  if (st != SIC_OK) return st;
+  const int64_t step = I.step;
+  const int64_t cap = I.hist_cap;
+  const int64_t avail = std::min<int64_t>(step + 1, cap);
+  const DiagRow *H = p->hist + I.hist_off;
+  if (out) {
+    DiagRow r;
+    HIPCHK(p, hipMemcpy(&r, H + step % cap, sizeof(r), hipMemcpyDeviceToHost));
+    static_assert(sizeof(DiagRow) == sizeof(sic_diag), "row layout");
+    std::memcpy(out, &r, sizeof(r));
+  }
+  const int nc = p->slots[slot].n_cells;
+  if (rho_out) HIPCHK(p, hipMemcpy(rho_out, p->meshRho + I.mesh_off, sizeof(double) * nc, hipMemcpyDeviceToHost));
+  if (E_out) HIPCHK(p, hipMemcpy(E_out, p->meshE + I.mesh_off, sizeof(double) * nc, hipMemcpyDeviceToHost));
+  if (history_len) {
+    if (history_out) {
+      const int64_t want = std::min<int64_t>(*history_len, avail);
+      // the newest `want` rows, oldest first
+      std::vector<DiagRow> all((size_t)avail);
+      const int64_t first = step + 1 - avail;
+      const int64_t r0 = first % cap;
+      const int64_t n1 = std::min<int64_t>(avail, cap - r0);
+      HIPCHK(p, hipMemcpy(all.data(), H + r0, sizeof(DiagRow) * (size_t)n1, hipMemcpyDeviceToHost));
+      if (n1 < avail)
+        HIPCHK(p, hipMemcpy(all.data() + n1, H, sizeof(DiagRow) * (size_t)(avail - n1), hipMemcpyDeviceToHost));
+      std::memcpy(history_out, all.data() + (avail - want), sizeof(DiagRow) * (size_t)want);
+      *history_len = want;
+    } else {
+      *history_len = avail;
+    }
+  }
+  return SIC_OK;
+}
+
+sic_status pool_get_state(Pool *p, int32_t slot, double *x, double *v, int64_t *step, int32_t mem_kind) {
+  if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return fail(p, SIC_EINVAL, "slot not live");
+  SlotHost &sh = p->slots[slot];
+  double *dx = x, *dv = v, *stage = nullptr;
+  if (mem_kind == SIC_MEM_HOST) {
+    HIPCHK(p, hipMalloc((void **)&stage, sizeof(double) * 2 * (size_t)std::max<int64_t>(sh.n_tracers, 1)));
+    dx = stage;
+    dv = stage + sh.n_tracers;
+  }
+  ExtractArgs ea;
+  ea.chunk_in_off = sh.d_in_off;
+  ea.chunk_begin = sh.chunk_begin;
+  ea.n_chunks = sh.n_chunks;
+  ea.chunks = p->chunks;
+  ea.inst = p->inst;
+  ea.xs = p->xs;
+  ea.vs = p->vs;
+  ea.x_out = dx;
+  ea.v_out = dv;
+  int le = launch_extract(p->prec, ea, p->stream);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (le == 0 && e == hipSuccess && stage && x)
+    e = hipMemcpy(x, dx, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyDeviceToHost);
+  if (le == 0 && e == hipSuccess && stage && v)
+    e = hipMemcpy(v, dv, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyDeviceToHost);
+  if (stage) hipFree(stage);
+  if (le != 0) return fail(p, SIC_EDEVICE, std::string("extract: ") + hipGetErrorString((hipError_t)le));
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("get_state: ") + hipGetErrorString(e));
+  if (step) {
+    InstDesc I;
+    sic_status st = read_inst(p, slot, &I);
+    if (st != SIC_OK) return st;
+    *step = I.step;
+  }
+  return SIC_OK;
+}
+
+sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, const double *v,
+                          int32_t mem_kind) {
+  if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return fail(p, SIC_EINVAL, "slot not live");
+  if (!x || !v || step < 0) return fail(p, SIC_EINVAL, "bad state arguments");
+  SlotHost &sh = p->slots[slot];
+  if (mem_kind == SIC_MEM_HOST && (!all_finite_host(x, sh.n_tracers) || !all_finite_host(v, sh.n_tracers)))
+    return fail(p, SIC_EINVAL, "non-finite state");
+  InstDesc I;
+  sic_status st = read_inst(p, slot, &I);
+  if (st != SIC_OK) return st;
+  I.step = step;
+  double *stage = nullptr;
+  const double *dx = x, *dv = v;
+  if (mem_kind == SIC_MEM_HOST) {
+    HIPCHK(p, hipMalloc((void **)&stage, sizeof(double) * 2 * (size_t)std::max<int64_t>(sh.n_tracers, 1)));
+    hipMemcpyAsync(stage, x, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyHostToDevice, p->stream);
+    hipMemcpyAsync(stage + sh.n_tracers, v, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyHostToDevice, p->stream);
+    dx = stage;
+    dv = stage + sh.n_tracers;
+  }
+  hipError_t e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
+  IngestArgs ia;
+  ia.x_in = dx;
+  ia.v_in = dv;
+  ia.chunk_in_off = sh.d_in_off;
+  ia.chunk_begin = sh.chunk_begin;
+  ia.n_chunks = sh.n_chunks;
+  ia.chunks = p->chunks;
+  ia.inst = p->inst;
+  ia.xs = p->xs;
+  ia.vs = p->vs;
+  ia.halo = p->halo[p->parity];
+  int le = (e == hipSuccess) ? launch_ingest(p->prec, ia, p->stream) : 0;
+  if (le == 0 && e == hipSuccess)
+    le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->inst, p->slot_ids + slot, 1, p->stream);
+  hipError_t e2 = hipStreamSynchronize(p->stream);
+  if (stage) hipFree(stage);
+  if (e != hipSuccess || e2 != hipSuccess || le != 0) return fail(p, SIC_EDEVICE, "set_state failed");
+  sh.state = kStale;
+  sh.pending_push = sh.pending_dep = false;
+  return SIC_OK;
+}
+
+// ---- single-simulation state machine ----
+sic_status sim_deposit(Pool *p) {
+  SlotHost &sh = p->slots[0];
+  if (sh.state == kDeposited) {
+    LAUNCHCHK(p, launch_zero_mesh(p->prec, p->meshP, p->meshD, p->inst, p->slot_ids, 1, p->stream));
+  }
+  sic_status st = launch_tracer_mode(p, kDeposit, -1, p->stream);
+  if (st != SIC_OK) return st;
+  sh.state = kDeposited;
+  sh.pending_dep = true;
+  return SIC_OK;
+}
+
+sic_status sim_solve(Pool *p) {
+  SlotHost &sh = p->slots[0];
+  if (sh.state != kDeposited) return fail(p, SIC_ESTATE, "solve needs a deposit of the current positions");
+  const int flags = (sh.pending_push ? kHavePush : 0) | (sh.pending_dep ? kHaveDeposit : 0);
+  sic_status st = launch_solve_mode(p, flags, -1, p->stream);
+  if (st != SIC_OK) return st;
+  sh.state = kField;
+  sh.pending_push = sh.pending_dep = false;
+  return SIC_OK;
+}
+
+sic_status sim_push(Pool *p) {
+  SlotHost &sh = p->slots[0];
+  if (sh.state != kField) return fail(p, SIC_ESTATE, "push needs the field of the current step");
+  sic_status st = launch_tracer_mode(p, kPush, -1, p->stream);
+  if (st != SIC_OK) return st;
+  sh.state = kStale;
+  sh.pending_push = true;
+  return SIC_OK;
+}
+
+sic_status sim_step(Pool *p, int64_t n) {
+  if (n < 0) return fail(p, SIC_EINVAL, "n_steps < 0");
+  SlotHost &sh = p->slots[0];
+  sic_status st = SIC_OK;
+  if (sh.state == kStale) st = sim_deposit(p);
+  if (st == SIC_OK && sh.state == kDeposited) st = sim_solve(p);
+  if (st != SIC_OK) return st;
+  return run_fused(p, n);
+}
+
+const char *status_str(sic_status s) {
+  switch (s) {
+    case SIC_OK: return "ok";
+    case SIC_EINVAL: return "invalid argument";
+    case SIC_ENOMEM: return "out of memory";
+    case SIC_EDEVICE: return "HIP runtime error";
+    case SIC_ESTATE: return "call out of order";
+    case SIC_EBUSY: return "no free slot or budget";
+    case SIC_ENOTSUP: return "not supported";
+  }
+  return "unknown status";
+}
+
+sic_status apply_tuning(Pool *p, const sic_tuning *t) {
+  if (!t) return fail(p, SIC_EINVAL, "null tuning");
+  const int b = t->block_threads;
+  if (b != 0 && b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
+    return fail(p, SIC_EINVAL, "block_threads must be 64..1024, a power of two");
+  if (t->tile_chunks < 0 || t->grid_blocks < 0) return fail(p, SIC_EINVAL, "negative tuning value");
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  p->tune = *t;
+  destroy_graphs(p);
+  return rebuild_items(p);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int32_t sic_abi_version(void) { return SIC_ABI_VERSION; }
+
+const char *sic_status_str(sic_status s) { return status_str(s); }
+
+sic_status sic_init(const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
+                    const double *v0, int32_t mem_kind, void *hip_stream, sic_sim **out) {
+  if (!out) return SIC_EINVAL;
+  *out = nullptr;
+  sic_status st = validate(nullptr, cfg, sheets, n_sheets, x0, v0);
+  if (st != SIC_OK) return st;
+  int64_t n_ch = 0;
+  for (int32_t s = 0; s < n_sheets; ++s) n_ch += (sheets[s].n_tracers + kChunk - 1) / kChunk;
+  const int64_t rows = cfg->history_rows > 0 ? std::max<int64_t>(2, cfg->history_rows) : 65536;
+  Pool *p = nullptr;
+  std::string err;
+  st = pool_create(cfg->precision, false, 1, cfg->n_cells, n_ch, rows, 0, hip_stream, &p, &err);
+  if (st != SIC_OK) return st;
+  int32_t slot = -1;
+  st = pool_admit(p, cfg, sheets, n_sheets, x0, v0, mem_kind, -1, &slot);
+  if (st != SIC_OK) {
+    pool_free(p);
+    return st;
+  }
+  sic_sim *s = new sic_sim();
+  s->pool = p;
+  *out = s;
+  return SIC_OK;
+}
+
+sic_status sic_deposit(sic_sim *sim) {
+  if (!sim) return SIC_EINVAL;
+  return sim_deposit(sim->pool);
+}
+
+sic_status sic_solve_field(sic_sim *sim) {
+  if (!sim) return SIC_EINVAL;
+  return sim_solve(sim->pool);
+}
+
+sic_status sic_push(sic_sim *sim) {
+  if (!sim) return SIC_EINVAL;
+  return sim_push(sim->pool);
+}
+
+sic_status sic_step(sic_sim *sim, int64_t n_steps) {
+  if (!sim) return SIC_EINVAL;
+  return sim_step(sim->pool, n_steps);
+}
+
+sic_status sic_diagnostics(sic_sim *sim, sic_diag *out, double *rho_out, double *E_out, sic_diag *history_out,
+                           int64_t *history_len) {
+  if (!sim) return SIC_EINVAL;
+  return pool_diagnostics(sim->pool, 0, out, rho_out, E_out, history_out, history_len);
+}
+
+sic_status sic_get_state(sic_sim *sim, double *x, double *v_half, int64_t *step, int32_t mem_kind) {
+  if (!sim) return SIC_EINVAL;
+  return pool_get_state(sim->pool, 0, x, v_half, step, mem_kind);
+}
+
+sic_status sic_set_state(sic_sim *sim, int64_t step, const double *x, const double *v_half, int32_t mem_kind) {
+  if (!sim) return SIC_EINVAL;
+  return pool_set_state(sim->pool, 0, step, x, v_half, mem_kind);
+}
+
+void sic_destroy(sic_sim *sim) {
+  if (!sim) return;
+  pool_free(sim->pool);
+  delete sim;
+}
+
+const char *sic_last_error(const sic_sim *sim) { return sim ? sim->pool->err.c_str() : g_last_error.c_str(); }
+
+sic_status sic_set_tuning(sic_sim *sim, const sic_tuning *t) {
+  if (!sim) return SIC_EINVAL;
+  return apply_tuning(sim->pool, t);
+}
+
+sic_status sic_get_tuning(const sic_sim *sim, sic_tuning *t) {
+  if (!sim || !t) return SIC_EINVAL;
+  t->tile_chunks = sim->pool->tile;
+  t->block_threads = sim->pool->block;
+  t->grid_blocks = sim->pool->grid;
+  t->reserved = 0;
+  return SIC_OK;
+}
+
+sic_status sic_set_timing(sic_sim *sim, int32_t timing) {
+  if (!sim) return SIC_EINVAL;
+  sim->pool->timing = timing != 0;
+  return SIC_OK;
+}
+
+sic_status sic_last_timing(const sic_sim *sim, double *tracer_ms, double *solve_ms) {
+  if (!sim) return SIC_EINVAL;
+  if (tracer_ms) *tracer_ms = sim->pool->t_tracer;
+  if (solve_ms) *solve_ms = sim->pool->t_solve;
+  return SIC_OK;
+}
+
+// ---- batch ----
+sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t max_cells, int32_t precision,
+                            int64_t history_rows, void *hip_stream, sic_batch **out) {
+  if (!out) return SIC_EINVAL;
+  *out = nullptr;
+  if (budget_tracers < 2 || max_slots < 1 || max_cells < 1 || max_cells > SIC_MAX_CELLS) return SIC_EINVAL;
+  if (precision < 0 || precision > 2 || history_rows < 0) return SIC_EINVAL;
+  const int64_t rows = history_rows > 0 ? std::max<int64_t>(2, history_rows) : 4096;
+  // arena: the budget plus the padding of partly filled last chunks
+  const int64_t chunks = (budget_tracers + kChunk - 1) / kChunk + budget_tracers / 512 + 8 * (int64_t)max_slots;
+  Pool *p = nullptr;
+  std::string err;
+  sic_status st = pool_create(precision, true, max_slots, max_cells, chunks, rows, budget_tracers, hip_stream, &p,
+                              &err);
+  if (st != SIC_OK) return st;
+  st = rebuild_items(p);
+  if (st != SIC_OK) {
+    pool_free(p);
+    return st;
+  }
+  sic_batch *b = new sic_batch();
+  b->pool = p;
+  *out = b;
+  return SIC_OK;
+}
+
+sic_status sic_batch_admit(sic_batch *b, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets,
+                           const double *x0, const double *v0, int32_t mem_kind, int64_t n_steps,
+                           int32_t *slot) {
+  if (!b || !slot) return SIC_EINVAL;
+  return pool_admit(b->pool, cfg, sheets, n_sheets, x0, v0, mem_kind, n_steps, slot);
+}
+
+sic_status sic_batch_step(sic_batch *b, int64_t n_steps) {
+  if (!b) return SIC_EINVAL;
+  if (n_steps < 0) return fail(b->pool, SIC_EINVAL, "n_steps < 0");
+  return run_fused(b->pool, n_steps);
+}
+
+sic_status sic_batch_poll(sic_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done) {
+  if (!b || !n_done) return SIC_EINVAL;
+  Pool *p = b->pool;
+  std::vector<int32_t> d((size_t)p->slot_cap);
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  HIPCHK(p, hipMemcpy(d.data(), p->done, sizeof(int32_t) * d.size(), hipMemcpyDeviceToHost));
+  int32_t n = 0;
+  for (int32_t i = 0; i < p->slot_cap; ++i) {
+    if (p->slots[i].live && d[i] && !p->slots[i].reported) {
+      if (n >= cap) break;
+      if (done_slots) done_slots[n] = i;
+      p->slots[i].reported = true;
+      ++n;
+    }
+  }
+  *n_done = n;
+  return SIC_OK;
+}
+
+sic_status sic_batch_result(sic_batch *b, int32_t slot, sic_diag *out, double *rho_out, double *E_out,
+                            sic_diag *history_out, int64_t *history_len) {
+  if (!b) return SIC_EINVAL;
+  return pool_diagnostics(b->pool, slot, out, rho_out, E_out, history_out, history_len);
+}
+
+sic_status sic_batch_get_state(sic_batch *b, int32_t slot, double *x, double *v_half, int64_t *step,
+                               int32_t mem_kind) {
+  if (!b) return SIC_EINVAL;
+  return pool_get_state(b->pool, slot, x, v_half, step, mem_kind);
+}
+
+sic_status sic_batch_release(sic_batch *b, int32_t slot) {
+  if (!b) return SIC_EINVAL;
+  return pool_release(b->pool, slot);
+}
+
+sic_status sic_batch_usage(const sic_batch *b, int64_t *tracers, int32_t *slots) {
+  if (!b) return SIC_EINVAL;
+  if (tracers) *tracers = b->pool->used_tracers;
+  if (slots) *slots = b->pool->used_slots;
+  return SIC_OK;
+}
+
+sic_status sic_batch_set_tuning(sic_batch *b, const sic_tuning *t) {
+  if (!b) return SIC_EINVAL;
+  return apply_tuning(b->pool, t);
+}
+
+sic_status sic_batch_get_tuning(const sic_batch *b, sic_tuning *t) {
+  if (!b || !t) return SIC_EINVAL;
+  t->tile_chunks = b->pool->tile;
+  t->block_threads = b->pool->block;
+  t->grid_blocks = b->pool->grid;
+  t->reserved = 0;
+  return SIC_OK;
+}
+
+void sic_batch_destroy(sic_batch *b) {
+  if (!b) return;
+  pool_free(b->pool);
+  delete b;
+}
+
+const char *sic_batch_last_error(const sic_batch *b) { return b ? b->pool->err.c_str() : g_last_error.c_str(); }
+
+sic_status sic_batch_set_timing(sic_batch *b, int32_t timing) {
+  if (!b) return SIC_EINVAL;
+  b->pool->timing = timing != 0;
+  return SIC_OK;
+}
+
+sic_status sic_batch_last_timing(const sic_batch *b, double *tracer_ms, double *solve_ms) {
+  if (!b) return SIC_EINVAL;
+  if (tracer_ms) *tracer_ms = b->pool->t_tracer;
+  if (solve_ms) *solve_ms = b->pool->t_solve;
+  return SIC_OK;
+}
+
+sic_status sic_copy_bandwidth(int64_t n_bytes, int32_t iters, void *hip_stream, double *gbps) {
+  if (n_bytes < 1024 || iters < 1 || !gbps) return SIC_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t n = n_bytes / 16 * 2;  // doubles, even
+  double *a = nullptr, *b = nullptr;
+  if (hipMalloc((void **)&a, sizeof(double) * (size_t)n) != hipSuccess) return SIC_ENOMEM;
+  if (hipMalloc((void **)&b, sizeof(double) * (size_t)n) != hipSuccess) {
+    hipFree(a);
+    return SIC_ENOMEM;
+  }
+  hipMemsetAsync(a, 0, sizeof(double) * (size_t)n, st);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  double best = 0.0;
+  sic_status rc = SIC_OK;
+  launch_copy_bench(a, b, n, st);  // warm-up
+  for (int i = 0; i < iters; ++i) {
+    hipEventRecord(e0, st);
+    if (launch_copy_bench(a, b, n, st) != 0) {
+      rc = SIC_EDEVICE;
+      break;
+    }
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = SIC_EDEVICE;
+      break;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double g = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
+    best = std::max(best, g);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(a);
+  hipFree(b);
+  *gbps = best;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// sic_internal.h - device-side layout shared by the kernels and the host
+// side of libsic (not part of the public ABI).
+//
+// Tracer storage.  Tracers live in 64-slot chunks, one wavefront per chunk;
+// every sheet starts on a chunk boundary (its last chunk may be partly
+// empty), so a wavefront never straddles two sheets.  State is two arrays of
+// 8-byte words per tracer slot:
+//   word 0: x (float64)                      - SIC_FP64
+//           cell (int32, low) | offset (high) - split forms (offset is a
+//           float32 in [0,1) or a uint32 fraction of a cell)
+//   word 1: v (float64)
+// Every chunk also keeps a copy of its first tracer's state in a "halo"
+// array.  A step that moves tracers and deposits their new positions in the
+// same kernel needs, for the last tracer of each chunk, the new position of
+// the first tracer of the next chunk, which another workgroup may already
+// have overwritten; it recomputes that move from the halo copy written by the
+// previous step.  The halo is double-buffered (read one, write the other).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sic {
+
+constexpr int kChunk = 64;          // tracer slots per chunk = wavefront width
+constexpr int kMaxCells = 4096;     // mirrors SIC_MAX_CELLS
+constexpr int kSolveThreads = 256;  // field-solve workgroup
+constexpr int kMaxCellsPerThread = kMaxCells / kSolveThreads;
+
+enum Prec : int { kFP64 = 0, kSplitF32 = 1, kSplitU32 = 2 };
+
+// Tracer-kernel modes (bit set).
+enum Mode : int {
+  kDeposit = 1,      // deposit the (possibly new) positions into the mesh
+  kPush = 2,         // kick with E and drift
+  kKickHalf = 4,     // start-up: v <- v - dt/2 E(x), positions unchanged
+};
+
+// Solve-kernel flags.
+enum SolveFlags : int {
+  kHavePush = 1,     // a push ran since the last solve: step += 1, KE/momentum rows
+  kHaveDeposit = 2,  // partials hold the max segment of the deposited positions
+  kBatchStep = 4,    // count the step against steps_left; finish at zero
+};
+
+struct alignas(16) InstDesc {
+  double L, half_L, dx, inv_dx;
+  double dt, q_unit;      // q_unit: charge of one fixed-point unit (split forms)
+  int64_t mesh_off;       // first cell of this slot in the mesh arrays
+  int64_t hist_off;       // first row of this slot in the history array
+  int64_t hist_cap;       // rows in the ring
+  int64_t step;           // positions are x^step
+  int64_t steps_left;     // batch: steps still to run (< 0: unlimited)
+  int32_t n_cells;
+  int32_t active;         // 1: advanced by batch steps
+  int32_t flags;          // sticky sic_diag flags
+  int32_t live;           // slot holds a simulation
+};
+
+struct alignas(16) ChunkDesc {
+  double q;               // segment charge
+  int64_t q_fix;          // segment charge in fixed-point units
+  int32_t partner;        // chunk whose first tracer follows this chunk's last
+                          // valid tracer in the sheet; -1: open sheet end
+  int32_t n_valid;        // valid tracer slots (1..64)
+  int32_t inst;           // slot
+  int32_t pad;
+};
+
+struct alignas(16) Item {
+  int32_t inst;
+  int32_t chunk_begin;
+  int32_t chunk_end;
+  int32_t pad;
+};
+
+struct alignas(32) Partial {
+  double ke, mom, maxseg, pad;
+};
+
+// Row layout of the history ring (matches sic_diag).
+struct alignas(64) DiagRow {
+  int64_t step;
+  double t, W_E, KE, momentum, total_charge, max_segment;
+  int64_t flags;
+};
+
+struct TracerArgs {
+  const Item *items;
+  const int32_t *n_items;  // device-side item count
+  const InstDesc *inst;
+  const ChunkDesc *chunks;
+  uint64_t *xs;            // word 0 per slot
+  double *vs;              // word 1 per slot
+  const double2 *halo_in;  // (x word as bits, v) per chunk
+  double2 *halo_out;
+  void *meshP;             // direct cell charge (double or int64)
+  void *meshD;             // difference array for covered cell runs
+  const double *meshE;
+  Partial *partials;       // per item
+  int32_t mesh_cells;      // LDS capacity in cells (max n_cells of the pool)
+  int32_t respect_active;  // skip slots with active == 0
+};
+
+struct SolveArgs {
+  InstDesc *inst;
+  const int2 *slot_items;    // per slot: (first item, item count) in the item list
+  const int32_t *slot_list;  // NULL: slot = blockIdx.x
+  const Partial *partials;
+  void *meshP;
+  void *meshD;
+  double *meshE;
+  double *meshRho;           // n_j - nbar of the newest solve
+  DiagRow *hist;
+  int32_t *done;             // per slot: set to 1 when a batch run finishes
+  int32_t flags;
+  int32_t respect_active;
+};
+
+struct IngestArgs {
+  const double *x_in;
+  const double *v_in;
+  const int64_t *chunk_in_off;  // per chunk of the range: first input index
+  int32_t chunk_begin;
+  int32_t n_chunks;
+  const ChunkDesc *chunks;
+  const InstDesc *inst;
+  uint64_t *xs;
+  double *vs;
+  double2 *halo;
+};
+
+struct ExtractArgs {
+  const int64_t *chunk_in_off;
+  int32_t chunk_begin;
+  int32_t n_chunks;
+  const ChunkDesc *chunks;
+  const InstDesc *inst;
+  const uint64_t *xs;
+  const double *vs;
+  double *x_out;
+  double *v_out;
+};
+
+// Launchers (sic_kernels.hip).  All return hipError_t as int.
+int launch_tracers(int prec, int mode, const TracerArgs &a, int grid, int block, size_t lds_bytes,
+                   void *stream);
+int set_tracer_lds_limit(int prec, size_t lds_bytes);
+int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream);
+int launch_ingest(int prec, const IngestArgs &a, void *stream);
+int launch_extract(int prec, const ExtractArgs &a, void *stream);
+int launch_zero_mesh(int prec, void *meshP, void *meshD, const InstDesc *inst, const int32_t *slot_list,
+                     int n_blocks, void *stream);
+int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream);
+
+}  // namespace sic

@@ -1,0 +1,816 @@
+// sic_kernels.hip - gfx950 kernels of the simplex-in-cell (SIC) 1D1V step.
+//
+//   k_tracers  one pass over the tracers: gather + leapfrog move (section 2.3,
+//              "gather" with first-order weighting of section 2.4, "move"),
+//              and/or the exact segment deposit (section 2.3, eqs. "overlap"
+//              and "rho_sum") of the resulting positions.  Persistent
+//              workgroups walk a list of work items; one item is a run of
+//              64-tracer chunks of one simulation.  Each workgroup
+//              accumulates the item's charge in a private LDS copy of that
+//              simulation's mesh and merges it into the global mesh with one
+//              atomic per touched cell.
+//   k_solve    one workgroup per simulation: finishes the deposit (prefix sum
+//              of the covered-run difference array), removes the mean density,
+//              integrates Gauss's law for the face fields, averages them to
+//              cell centres (identical to the 3-point Poisson equation with a
+//              centred-difference field), and writes the field energy and
+//              the diagnostics row.
+//
+// Deposit of one segment.  In mesh units (u = x / dx) a segment [u0, u1]
+// covers cells c0 = floor(u0) .. c1 = ceil(u1) - 1.  Its charge q is spread
+// with density q / (u1 - u0): the two end cells get their partial overlaps,
+// and each fully covered cell in between gets the same amount q / (u1 - u0).
+// The covered run is added through a difference array D (+w at its first
+// cell, -w after its last) that the solve kernel prefix-sums, so a segment
+// costs O(1) however many cells it spans.
+//
+// Split forms keep positions as (cell, fraction) and deposit int64
+// fixed-point charge: the first end cell gets round(q * f0), every covered
+// cell round(q / len) and the last end cell the remainder, so each segment
+// deposits exactly its fixed-point charge and the mesh is independent of the
+// order of the atomics.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "sic_internal.h"
+
+namespace sic {
+
+namespace {
+
+// Cell index modulo nc for c in [-nc, 2nc); anything else (only reachable
+// from non-finite data) is clamped to cell 0 so that no access leaves the mesh.
+__device__ __forceinline__ int wrap_cell(int c, int nc) {
+  c = c < 0 ? c + nc : (c >= nc ? c - nc : c);
+  return ((unsigned)c < (unsigned)nc) ? c : 0;
+}
+
+// Periodic reduction of a position into [0, L).  The common case moves at
+// most one period, where x - L is exact; a sum that rounds up to L is 0.
+__device__ __forceinline__ double wrap_into_box(double x, double L) {
+  if (x >= L) {
+    x = x - L;
+    if (x >= L) x = x - L * floor(x / L);
+  } else if (x < 0.0) {
+    x = (x >= -L) ? x + L : x - L * floor(x / L);
+    if (x < 0.0) x += L;
+  }
+  return (x >= L) ? 0.0 : x;
+}
+
+// ---- split position words: cell in the low 32 bits, fraction bits high ----
+template <int PREC>
+__device__ __forceinline__ double split_frac(uint32_t bits) {
+  if constexpr (PREC == kSplitF32) {
+    return (double)__uint_as_float(bits);
+  } else {
+    return (double)bits * 2.3283064365386963e-10;  // 2^-32
+  }
+}
+
+// Quantises a fraction r in [0, 1] to the offset type; carry = 1 when it
+// rounds up to a whole cell.
+template <int PREC>
+__device__ __forceinline__ uint32_t split_quantise(double r, int &carry) {
+  carry = 0;
+  if constexpr (PREC == kSplitF32) {
+    float o = (float)r;
+    if (o >= 1.0f) {
+      o = 0.0f;
+      carry = 1;
+    }
+    return __float_as_uint(o);
+  } else {
+    double s = rint(r * 4294967296.0);
+    if (s >= 4294967296.0) {
+      s = 0.0;
+      carry = 1;
+    }
+    return (uint32_t)s;
+  }
+}
+
+__device__ __forceinline__ uint64_t pack_split(int cell, uint32_t bits) {
+  return (uint64_t)(uint32_t)cell | ((uint64_t)bits << 32);
+}
+__device__ __forceinline__ int split_cell(uint64_t w) { return (int)(uint32_t)(w & 0xffffffffull); }
+__device__ __forceinline__ uint32_t split_bits(uint64_t w) { return (uint32_t)(w >> 32); }
+
+// Position in mesh units of a state word.
+template <int PREC>
+__device__ __forceinline__ double mesh_pos(uint64_t w, double inv_dx) {
+  if constexpr (PREC == kFP64) {
+    return __longlong_as_double((long long)w) * inv_dx;
+  } else {
+    return (double)split_cell(w) + split_frac<PREC>(split_bits(w));
+  }
+}
+
+// Field at a tracer: linear interpolation between the two cell centres
+// around it (first-order weighting).  u is the position in mesh units.
+__device__ __forceinline__ double gather_field(const double *__restrict__ E, double u, int nc) {
+  const double g = u - 0.5;
+  const double f = floor(g);
+  const double s = g - f;
+  const int j0 = wrap_cell((int)f, nc);
+  const int j1 = (j0 + 1 == nc) ? 0 : j0 + 1;
+  return (1.0 - s) * E[j0] + s * E[j1];
+}
+
+// Drift of a state word by dt * v.
+template <int PREC>
+__device__ __forceinline__ uint64_t drift(uint64_t w, double v, double dt, double L, double inv_dx, int nc) {
+  if constexpr (PREC == kFP64) {
+    const double x = __longlong_as_double((long long)w);
+    return (uint64_t)__double_as_longlong(wrap_into_box(x + dt * v, L));
+  } else {
+    const double t = split_frac<PREC>(split_bits(w)) + (dt * v) * inv_dx;
+    const double k = floor(t);
+    const double r = t - k;
+    int carry;
+    const uint32_t bits = split_quantise<PREC>(r, carry);
+    long long cell = (long long)split_cell(w) + (long long)k + carry;
+    cell %= nc;
+    if (cell < 0) cell += nc;
+    return pack_split((int)cell, bits);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void lds_add(T *p, T v) {
+  if constexpr (std::is_same<T, double>::value) {
+    unsafeAtomicAdd(p, v);
+  } else {
+    atomicAdd(p, v);
+  }
+}
+
+// Adds w to cells lo..hi (unwrapped indices, 0 <= hi - lo < nc) of the
+// difference array: +w at the first cell, -w after the last.
+template <class T>
+__device__ __forceinline__ void add_run(T *sD, int lo, int hi, T w, int nc) {
+  const int l = wrap_cell(lo, nc);
+  const int h = l + min(hi - lo, nc - 1);
+  lds_add(sD + l, w);
+  if (h + 1 < nc) {
+    lds_add(sD + h + 1, (T)(0 - w));
+  } else if (h >= nc) {
+    lds_add(sD, w);
+    lds_add(sD + (h - nc + 1), (T)(0 - w));
+  }
+}
+
+struct Geo {
+  double L, half_L, dx, inv_dx, dt;
+  int nc;
+};
+
+// FP64 segment from position a to position b (both in [0, L)).
+__device__ __forceinline__ double deposit_fp64(double a, double b, double q, const Geo &g, double *sP,
+                                               double *sD) {
+  double d = b - a;
+  if (d >= g.half_L) d -= g.L;
+  else if (d < -g.half_L) d += g.L;
+  const double ad = fabs(d);
+  if (!(ad <= g.half_L)) return ad;  // non-finite positions: nothing deposited
+  if (d == 0.0) {
+    // zero-length segment: all of q into the cell owning the point, a point
+    // on a face belonging to the lower cell
+    const int c = wrap_cell((int)ceil(a / g.dx) - 1, g.nc);
+    lds_add(sP + c, q);
+    return 0.0;
+  }
+  const double ua = a * g.inv_dx;
+  const double ue = ua + d * g.inv_dx;
+  const double u0 = d > 0.0 ? ua : ue;
+  const double u1 = d > 0.0 ? ue : ua;
+  const double len = u1 - u0;
+  const double f0 = floor(u0);
+  const int c0 = (int)f0;
+  const int c1 = (int)ceil(u1) - 1;
+  if (!(len > 0.0) || c1 <= c0) {
+    lds_add(sP + wrap_cell(c0, g.nc), q);
+    return ad;
+  }
+  const double w = q / len;
+  lds_add(sP + wrap_cell(c0, g.nc), w * ((f0 + 1.0) - u0));
+  lds_add(sP + wrap_cell(c1, g.nc), w * (u1 - (double)c1));
+  if (c1 - c0 >= 2) add_run(sD, c0 + 1, c1 - 1, w, g.nc);
+  return ad;
+}
+
+// Split-form segment; positions in mesh units ua = cell + fraction.
+template <int PREC>
+__device__ __forceinline__ double deposit_split(uint64_t wa, uint64_t wb, long long qf, const Geo &g,
+                                                unsigned long long *sP, unsigned long long *sD) {
+  const int ca = split_cell(wa);
+  const double fa = split_frac<PREC>(split_bits(wa));
+  const double ua = (double)ca + fa;
+  const double ub = (double)split_cell(wb) + split_frac<PREC>(split_bits(wb));
+  const double half_nc = 0.5 * (double)g.nc;
+  double du = ub - ua;
+  if (du >= half_nc) du -= (double)g.nc;
+  else if (du < -half_nc) du += (double)g.nc;
+  const double ad = fabs(du) * g.dx;
+  if (!(fabs(du) <= half_nc)) return ad;
+  if (du == 0.0) {
+    const int c = wrap_cell(fa == 0.0 ? ca - 1 : ca, g.nc);
+    lds_add(sP + c, (unsigned long long)qf);
+    return 0.0;
+  }
+  const double ue = ua + du;
+  const double u0 = du > 0.0 ? ua : ue;
+  const double u1 = du > 0.0 ? ue : ua;
+  const double len = u1 - u0;
+  const double f0 = floor(u0);
+  const int c0 = (int)f0;
+  const int c1 = (int)ceil(u1) - 1;
+  if (!(len > 0.0) || c1 <= c0) {
+    lds_add(sP + wrap_cell(c0, g.nc), (unsigned long long)qf);
+    return ad;
+  }
+  const double inv = 1.0 / len;
+  const double qd = (double)qf;
+  const long long p0 = llrint(qd * (((f0 + 1.0) - u0) * inv));
+  long long p1 = qf - p0;
+  if (c1 - c0 >= 2) {
+    const long long wfix = llrint(qd * inv);
+    add_run(sD, c0 + 1, c1 - 1, (unsigned long long)wfix, g.nc);
+    p1 -= (long long)(c1 - c0 - 1) * wfix;
+  }
+  lds_add(sP + wrap_cell(c0, g.nc), (unsigned long long)p0);
+  lds_add(sP + wrap_cell(c1, g.nc), (unsigned long long)p1);
+  return ad;
+}
+
+__device__ __forceinline__ double nan_max(double a, double b) {
+  // max that propagates NaN (a non-finite segment must reach the flags)
+  return (b > a || b != b) ? b : a;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Tracer kernel
+// ---------------------------------------------------------------------------
+template <int PREC, int MODE>
+__global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  acc_t *sP = reinterpret_cast<acc_t *>(smem);
+  acc_t *sD = sP + a.mesh_cells;
+  double *sRed = reinterpret_cast<double *>(sD + a.mesh_cells);  // 3 x 16 waves
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int n_items = *a.n_items;
+  constexpr bool kDep = (MODE & kDeposit) != 0;
+  constexpr bool kMove = (MODE & kPush) != 0;
+  constexpr bool kKick = (MODE & kKickHalf) != 0;
+
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const Item item = a.items[it];
+    const InstDesc &I = a.inst[item.inst];
+    if (a.respect_active && !I.active) continue;
+    Geo g;
+    g.L = I.L;
+    g.half_L = I.half_L;
+    g.dx = I.dx;
+    g.inv_dx = I.inv_dx;
+    g.dt = I.dt;
+    g.nc = I.n_cells;
+    const double *__restrict__ E = a.meshE + I.mesh_off;
+
+    if constexpr (kDep) {
+      for (int i = tid; i < g.nc; i += blockDim.x) {
+        sP[i] = (acc_t)0;
+        sD[i] = (acc_t)0;
+      }
+      __syncthreads();
+    }
+
+    double ke = 0.0, mom = 0.0, ms = 0.0;
+    for (int c = item.chunk_begin + wave; c < item.chunk_end; c += nwaves) {
+      const ChunkDesc ch = a.chunks[c];
+      const bool valid = lane < ch.n_valid;
+      const size_t s = (size_t)c * kChunk + lane;
+      uint64_t xw = 0;
+      double v = 0.0;
+      if (valid) {
+        xw = a.xs[s];
+        v = a.vs[s];
+      }
+      if constexpr (kMove || kKick) {
+        if (valid) {
+          const double e = gather_field(E, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
+          if constexpr (kKick) {
+            v = v - (0.5 * g.dt) * e;
+            a.vs[s] = v;
+          } else {
+            const double vn = v + g.dt * e;
+            ke += 0.5 * ch.q * v * vn;
+            mom += ch.q * (0.5 * (v + vn));
+            v = vn;
+            xw = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
+            a.xs[s] = xw;
+            a.vs[s] = vn;
+          }
+        }
+        if (lane == 0) a.halo_out[c] = make_double2(__longlong_as_double((long long)xw), v);
+      }
+      if constexpr (kDep) {
+        uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
+        const bool tail = (lane == ch.n_valid - 1);
+        bool has_seg = valid;
+        if (tail) {
+          if (ch.partner < 0) {
+            has_seg = false;  // open sheet: the last tracer ends the chain
+          } else {
+            const double2 h = a.halo_in[ch.partner];
+            pw = (uint64_t)__double_as_longlong(h.x);
+            if constexpr (kMove) {
+              // the partner's move, recomputed from its state before this step
+              const double e = gather_field(E, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
+              const double hv = h.y + g.dt * e;
+              pw = drift<PREC>(pw, hv, g.dt, g.L, g.inv_dx, g.nc);
+            }
+          }
+        }
+        if (has_seg) {
+          double len;
+          if constexpr (PREC == kFP64) {
+            len = deposit_fp64(__longlong_as_double((long long)xw), __longlong_as_double((long long)pw), ch.q, g,
+                               sP, sD);
+          } else {
+            len = deposit_split<PREC>(xw, pw, ch.q_fix, g, sP, sD);
+          }
+          ms = nan_max(ms, len);
+        }
+      }
+    }
+
+    // Work-item partial sums in a fixed order (deterministic for a fixed
+    // item decomposition).
+    if constexpr (kMove) {
+      ke = wave_sum(ke);
+      mom = wave_sum(mom);
+    }
+    if constexpr (kDep) ms = wave_max(ms);
+    if (lane == 0) {
+      sRed[wave] = ke;
+      sRed[16 + wave] = mom;
+      sRed[32 + wave] = ms;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double k = 0.0, m = 0.0, x = 0.0;
+      for (int w = 0; w < nwaves; ++w) {
+        k += sRed[w];
+        m += sRed[16 + w];
+        x = nan_max(x, sRed[32 + w]);
+      }
+      if constexpr (kMove) {
+        a.partials[it].ke = k;
+        a.partials[it].mom = m;
+      }
+      if constexpr (kDep) a.partials[it].maxseg = x;
+    }
+    if constexpr (kDep) {
+      acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + I.mesh_off;
+      acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + I.mesh_off;
+      for (int i = tid; i < g.nc; i += blockDim.x) {
+        const acc_t p = sP[i];
+        const acc_t d = sD[i];
+        if (p != (acc_t)0) {
+          if constexpr (PREC == kFP64) unsafeAtomicAdd(gP + i, p);
+          else atomicAdd(gP + i, p);
+        }
+        if (d != (acc_t)0) {
+          if constexpr (PREC == kFP64) unsafeAtomicAdd(gD + i, d);
+          else atomicAdd(gD + i, d);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Field solve
+// ---------------------------------------------------------------------------
+namespace {
+
+// Inclusive scan over the 256-thread block of one value per thread, in a
+// fixed order.  sWave holds 4 entries.
+template <class T>
+__device__ __forceinline__ T block_incl_scan(T v, T *sWave) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T n = __shfl_up(v, off, 64);
+    if (lane >= off) v += n;
+  }
+  if (lane == 63) sWave[wave] = v;
+  __syncthreads();
+  T base = (T)0;
+  for (int w = 0; w < wave; ++w) base += sWave[w];
+  __syncthreads();
+  return v + base;
+}
+
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T *sWave) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sWave[wave] = v;
+  __syncthreads();
+  const T r = sWave[0] + sWave[1] + sWave[2] + sWave[3];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double *sWave) {
+  v = wave_max(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sWave[wave] = v;
+  __syncthreads();
+  const double r = nan_max(nan_max(sWave[0], sWave[1]), nan_max(sWave[2], sWave[3]));
+  __syncthreads();
+  return r;
+}
+
+}  // namespace
+
+template <int PREC>
+__global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+  __shared__ double sWd[4];
+  __shared__ long long sWi[4];
+  __shared__ double sLastF[kSolveThreads];
+
+  const int slot = a.slot_list ? a.slot_list[blockIdx.x] : (int)blockIdx.x;
+  InstDesc *Ip = a.inst + slot;
+  if (!Ip->live) return;
+  if (a.respect_active && !Ip->active) return;
+  const int tid = threadIdx.x;
+  const int nc = Ip->n_cells;
+  const double L = Ip->L, dx = Ip->dx, dt = Ip->dt;
+  const double q_unit = Ip->q_unit;
+  const int64_t step0 = Ip->step;
+  const int2 si = a.slot_items[slot];
+  const int item_begin = si.x, item_count = si.y;
+
+  // 1. work-item partials, in item order
+  double ke = 0.0, mom = 0.0, ms = 0.0;
+  for (int i = tid; i < item_count; i += kSolveThreads) {
+    const Partial p = a.partials[item_begin + i];
+    ke += p.ke;
+    mom += p.mom;
+    ms = nan_max(ms, p.maxseg);
+  }
+  if (a.flags & kHavePush) {
+    ke = block_sum(ke, sWd);
+    mom = block_sum(mom, sWd);
+  }
+  if (a.flags & kHaveDeposit) ms = block_max(ms, sWd);
+
+  // 2. charge per cell: Q_j = P_j + sum_{m <= j} D_m; clear the accumulators
+  const int per = (nc + kSolveThreads - 1) / kSolveThreads;
+  const int j0 = tid * per;
+  acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + Ip->mesh_off;
+  acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + Ip->mesh_off;
+  double *gE = a.meshE + Ip->mesh_off;
+  double *gR = a.meshRho + Ip->mesh_off;
+  acc_t pv[kMaxCellsPerThread], dv[kMaxCellsPerThread];
+  acc_t dsum = (acc_t)0;
+#pragma unroll
+  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    pv[k] = (acc_t)0;
+    dv[k] = (acc_t)0;
+    const int j = j0 + k;
+    if (k < per && j < nc) {
+      pv[k] = gP[j];
+      dv[k] = gD[j];
+      gP[j] = (acc_t)0;
+      gD[j] = (acc_t)0;
+    }
+    dsum += dv[k];
+  }
+  acc_t dbase;
+  if constexpr (PREC == kFP64) dbase = block_incl_scan(dsum, sWd) - dsum;
+  else dbase = block_incl_scan(dsum, sWi) - dsum;
+  double Q[kMaxCellsPerThread];
+  acc_t qsum_acc = (acc_t)0;
+  {
+    acc_t run = dbase;
+#pragma unroll
+    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+      run += dv[k];
+      const acc_t qa = pv[k] + run;
+      const bool in = (k < per) && (j0 + k < nc);
+      if constexpr (PREC == kFP64) Q[k] = in ? qa : 0.0;
+      else Q[k] = in ? (double)qa * q_unit : 0.0;
+      if (in) qsum_acc += qa;
+    }
+  }
+  double Qtot;
+  if constexpr (PREC == kFP64) Qtot = block_sum(qsum_acc, sWd);
+  else Qtot = (double)block_sum(qsum_acc, sWi) * q_unit;
+
+  // 3. Gauss's law on faces: F_{j+1/2} = F_{j-1/2} + (Q_j - Qtot/nc),
+  //    F shifted to zero mean; E_j = (F_{j-1/2} + F_{j+1/2}) / 2.
+  const double qmean = Qtot / (double)nc;
+  double F[kMaxCellsPerThread];
+  double rsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    const bool in = (k < per) && (j0 + k < nc);
+    const double r = in ? (Q[k] - qmean) : 0.0;
+    rsum += r;
+    F[k] = r;
+  }
+  const double fbase = block_incl_scan(rsum, sWd) - rsum;
+  double fsum = 0.0;
+  {
+    double run = fbase;
+#pragma unroll
+    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+      const bool in = (k < per) && (j0 + k < nc);
+      run += F[k];
+      F[k] = in ? run : 0.0;
+      if (in) fsum += F[k];
+    }
+  }
+  const double fmean = block_sum(fsum, sWd) / (double)nc;
+  double lastF = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    if ((k < per) && (j0 + k < nc)) {
+      F[k] -= fmean;
+      lastF = F[k];
+    }
+  }
+  sLastF[tid] = lastF;
+  __syncthreads();
+  double prevF = (tid == 0) ? sLastF[(nc - 1) / per] : sLastF[tid - 1];
+  double w2 = 0.0;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    const int j = j0 + k;
+    if ((k < per) && (j < nc)) {
+      const double e = 0.5 * (prevF + F[k]);
+      prevF = F[k];
+      gE[j] = e;
+      gR[j] = (Q[k] - qmean) / dx;
+      w2 += e * e;
+      finite = finite && (e - e == 0.0);
+    }
+  }
+  const double W = 0.5 * dx * block_sum(w2, sWd);
+  const int bad = block_sum(finite ? 0 : 1, reinterpret_cast<int *>(sWi));
+
+  // 4. diagnostics and step bookkeeping
+  if (tid == 0) {
+    const bool pushed = (a.flags & kHavePush) != 0;
+    const int64_t step = pushed ? step0 + 1 : step0;
+    int f = 0;
+    if (bad || !(W - W == 0.0)) f |= 1;
+    if (a.flags & kHaveDeposit) {
+      if (ms != ms) f |= 1;
+      else if (ms > 0.45 * L) f |= 2;
+    }
+    const int flags = Ip->flags | f;
+    Ip->flags = flags;
+    const int64_t cap = Ip->hist_cap;
+    DiagRow *H = a.hist + Ip->hist_off;
+    DiagRow r;
+    r.step = step;
+    r.t = (double)step * dt;
+    r.W_E = W;
+    r.KE = __longlong_as_double(0x7ff8000000000000ll);
+    r.momentum = r.KE;
+    r.total_charge = Qtot;
+    r.max_segment = (a.flags & kHaveDeposit) ? ms : r.KE;
+    r.flags = flags;
+    H[step % cap] = r;
+    if (pushed && step >= 1) {
+      DiagRow *prev = H + (step - 1) % cap;
+      prev->KE = ke;
+      prev->momentum = mom;
+    }
+    Ip->step = step;
+    if ((a.flags & kBatchStep) && pushed && Ip->steps_left > 0) {
+      const int64_t left = Ip->steps_left - 1;
+      Ip->steps_left = left;
+      if (left == 0) {
+        Ip->active = 0;
+        a.done[slot] = 1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ingest / extract / utilities
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ void __launch_bounds__(256) k_ingest(IngestArgs a) {
+  const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (cl >= a.n_chunks) return;
+  const int lane = threadIdx.x & 63;
+  const int c = a.chunk_begin + cl;
+  const ChunkDesc ch = a.chunks[c];
+  const InstDesc &I = a.inst[ch.inst];
+  const size_t s = (size_t)c * kChunk + lane;
+  uint64_t w = 0;
+  double v = 0.0;
+  if (lane < ch.n_valid) {
+    const int64_t src = a.chunk_in_off[cl] + lane;
+    const double x = wrap_into_box(a.x_in[src], I.L);
+    v = a.v_in[src];
+    if constexpr (PREC == kFP64) {
+      w = (uint64_t)__double_as_longlong(x);
+    } else {
+      const double u = x * I.inv_dx;
+      const double f = floor(u);
+      int carry;
+      const uint32_t bits = split_quantise<PREC>(u - f, carry);
+      const int cell = wrap_cell((int)f + carry, I.n_cells);
+      w = pack_split(cell, bits);
+    }
+  }
+  a.xs[s] = w;
+  a.vs[s] = v;
+  if (lane == 0) a.halo[c] = make_double2(__longlong_as_double((long long)w), v);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_extract(ExtractArgs a) {
+  const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (cl >= a.n_chunks) return;
+  const int lane = threadIdx.x & 63;
+  const int c = a.chunk_begin + cl;
+  const ChunkDesc ch = a.chunks[c];
+  if (lane >= ch.n_valid) return;
+  const InstDesc &I = a.inst[ch.inst];
+  const size_t s = (size_t)c * kChunk + lane;
+  const int64_t dst = a.chunk_in_off[cl] + lane;
+  const uint64_t w = a.xs[s];
+  double x;
+  if constexpr (PREC == kFP64) {
+    x = __longlong_as_double((long long)w);
+  } else {
+    x = ((double)split_cell(w) + split_frac<PREC>(split_bits(w))) * I.dx;
+  }
+  a.x_out[dst] = x;
+  a.v_out[dst] = a.vs[s];
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_zero_mesh(void *meshP, void *meshD, const InstDesc *inst,
+                                                   const int32_t *slot_list) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+  const int slot = slot_list ? slot_list[blockIdx.x] : (int)blockIdx.x;
+  const InstDesc &I = inst[slot];
+  acc_t *P = reinterpret_cast<acc_t *>(meshP) + I.mesh_off;
+  acc_t *D = reinterpret_cast<acc_t *>(meshD) + I.mesh_off;
+  for (int j = threadIdx.x; j < I.n_cells; j += blockDim.x) {
+    P[j] = (acc_t)0;
+    D[j] = (acc_t)0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int PREC>
+static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
+  switch (mode) {
+    case kDeposit:
+      hipLaunchKernelGGL((k_tracers<PREC, kDeposit>), dim3(grid), dim3(block), lds, st, a);
+      break;
+    case kPush:
+      hipLaunchKernelGGL((k_tracers<PREC, kPush>), dim3(grid), dim3(block), lds, st, a);
+      break;
+    case kPush | kDeposit:
+      hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit>), dim3(grid), dim3(block), lds, st, a);
+      break;
+    case kKickHalf:
+      hipLaunchKernelGGL((k_tracers<PREC, kKickHalf>), dim3(grid), dim3(block), lds, st, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t set_lds_limit(size_t bytes) {
+  hipError_t e = hipSuccess;
+  const int b = (int)bytes;
+  e = hipFuncSetAttribute((const void *)k_tracers<PREC, kDeposit>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_tracers<PREC, kPush>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_tracers<PREC, kPush | kDeposit>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_tracers<PREC, kKickHalf>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             b);
+}
+
+int set_tracer_lds_limit(int prec, size_t lds) {
+  hipError_t e = prec == kFP64 ? set_lds_limit<kFP64>(lds)
+                               : (prec == kSplitF32 ? set_lds_limit<kSplitF32>(lds) : set_lds_limit<kSplitU32>(lds));
+  return (int)e;
+}
+
+int launch_tracers(int prec, int mode, const TracerArgs &a, int grid, int block, size_t lds, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (grid <= 0) return 0;
+  switch (prec) {
+    case kFP64: return (int)tracers_prec<kFP64>(mode, a, grid, block, lds, st);
+    case kSplitF32: return (int)tracers_prec<kSplitF32>(mode, a, grid, block, lds, st);
+    case kSplitU32: return (int)tracers_prec<kSplitU32>(mode, a, grid, block, lds, st);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n_blocks <= 0) return 0;
+  switch (prec) {
+    case kFP64: hipLaunchKernelGGL(k_solve<kFP64>, dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
+    case kSplitF32: hipLaunchKernelGGL(k_solve<kSplitF32>, dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
+    case kSplitU32: hipLaunchKernelGGL(k_solve<kSplitU32>, dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_ingest(int prec, const IngestArgs &a, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int grid = (a.n_chunks + 3) / 4;
+  if (grid <= 0) return 0;
+  switch (prec) {
+    case kFP64: hipLaunchKernelGGL(k_ingest<kFP64>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitF32: hipLaunchKernelGGL(k_ingest<kSplitF32>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitU32: hipLaunchKernelGGL(k_ingest<kSplitU32>, dim3(grid), dim3(256), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_extract(int prec, const ExtractArgs &a, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int grid = (a.n_chunks + 3) / 4;
+  if (grid <= 0) return 0;
+  switch (prec) {
+    case kFP64: hipLaunchKernelGGL(k_extract<kFP64>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitF32: hipLaunchKernelGGL(k_extract<kSplitF32>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitU32: hipLaunchKernelGGL(k_extract<kSplitU32>, dim3(grid), dim3(256), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_zero_mesh(int prec, void *meshP, void *meshD, const InstDesc *inst, const int32_t *slot_list,
+                     int n_blocks, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n_blocks <= 0) return 0;
+  if (prec == kFP64)
+    hipLaunchKernelGGL(k_zero_mesh<kFP64>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, inst, slot_list);
+  else
+    hipLaunchKernelGGL(k_zero_mesh<kSplitF32>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, inst, slot_list);
+  return (int)hipGetLastError();
+}
+
+int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream) {
+  const int64_t n2 = n / 2;
+  hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, (hipStream_t)stream, (const double2 *)src, (double2 *)dst, n2);
+  return (int)hipGetLastError();
+}
+
+}  // namespace sic
