@@ -1,0 +1,227 @@
+"""Benchmark: batched simplex-in-cell steps on one MI355X.
+
+Default workload: the mixed batch of 4096 independent 1D1V instances (seeded
+draw: Landau or two-stream, k in [0.2, 0.6], alpha log-uniform in
+[1e-3, 0.5], 32-512 sheets x 64-2048 tracers, 64-1024 cells), all resident in
+HBM, advanced together.  One step = one pass of the whole hot path (move,
+deposit, field solve) over every instance.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+
+Besides the batched throughput (``value``) the line carries the same
+instances run one simulation per launch sequence (``plain``), the roofline of
+the tracer kernel (HIP-event timing of the kernel itself) and the FP64 CPU
+oracle timed on a bounded sample (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "tracer-updates/s batched vs plain at <=1e-6 rel field-energy err; p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+BYTES_PER_TRACER = 32  # read + write of x and v (8 B each) per fused step
+BYTES_PER_CELL = 32    # per instance per step: E read, charge accumulators read and cleared, E written
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--instances", type=int, default=4096)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split_f32", "split_u32"])
+    ap.add_argument("--plain-instances", type=int, default=256)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    return ap.parse_args()
+
+
+def device_inputs(problem, torch):
+    line = torch.from_numpy(problem.line).cuda()
+    x0 = line.repeat(problem.n_sheets)
+    v0 = torch.from_numpy(problem.sheet_v).cuda().repeat_interleave(int(problem.n_tracers[0]))
+    return x0, v0
+
+
+def build_batch(B, specs, precision, torch, history_rows=256):
+    total = sum(s.tracers for s in specs)
+    max_cells = max(s.n_cells for s in specs)
+    b = B.sic_batch_create(total, len(specs), max_cells, precision=precision, history_rows=history_rows)
+    t0 = time.time()
+    cells = 0
+    for i, s in enumerate(specs):
+        p = s.build()
+        x0, v0 = device_inputs(p, torch)
+        B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x0, v0, p.n_steps,
+                          precision=precision)
+        cells += p.n_cells
+        if (i + 1) % 512 == 0:
+            log(f"admitted {i + 1}/{len(specs)} instances ({time.time() - t0:.1f}s)")
+    return b, total, cells
+
+
+def time_batched(B, b, steps, warmup, torch):
+    B.sic_batch_step(b, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.sic_batch_step(b, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_timing(B, b, steps=5):
+    B.sic_batch_set_timing(b, True)
+    B.sic_batch_step(b, steps)
+    tr, so = B.sic_batch_last_timing(b)
+    B.sic_batch_set_timing(b, False)
+    return tr, so
+
+
+def time_plain(B, specs, precision, steps, torch):
+    """The same instances, one simulation per launch sequence (no batching)."""
+    sims = []
+    n_tr = 0
+    for s in specs:
+        p = s.build()
+        x0, v0 = device_inputs(p, torch)
+        sims.append(B.Simulation(p, precision=precision, history_rows=64, x0=x0, v0=v0))
+        n_tr += p.total_tracers
+    for sim in sims:
+        sim.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for sim in sims:
+        sim.close()
+    return n_tr * steps / dt, n_tr, dt
+
+
+def cpu_baseline(specs, seconds):
+    """The FP64 oracle (single thread) on whole instances of the same mix, a
+    few steps each, until about ``seconds`` of CPU work."""
+    from oracle import oracle as O
+
+    done_updates = 0
+    t_total = 0.0
+    used = []
+    for s in specs:
+        p = s.build()
+        t0 = time.perf_counter()
+        O.run_problem(p, 2)
+        dt = time.perf_counter() - t0
+        done_updates += 2 * p.total_tracers
+        t_total += dt
+        used.append(s.tracers)
+        if t_total >= seconds:
+            break
+    return done_updates / t_total, len(used), t_total
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched path shards by "
+              "instance across GPUs with no exchange, so multi-GPU figures are not produced here.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1506_07207_amd import binding as B
+    from paper_1506_07207_amd import inputs as I
+
+    if not os.path.exists(B.LIB_PATH):
+        from paper_1506_07207_amd import build as hb
+        hb.build()
+    torch.cuda.set_device(0)
+    precision = B.PRECISIONS[args.precision]
+    specs = I.batch_mix(args.instances)
+    log(f"building batch of {len(specs)} instances ({args.precision})")
+    t_setup = time.time()
+    b, total, cells = build_batch(B, specs, precision, torch)
+    if args.tile or args.block or args.grid:
+        B.sic_batch_set_tuning(b, args.tile, args.block, args.grid)
+    tuning = B.sic_batch_get_tuning(b)
+    log(f"resident tracers {total:.3e}, setup {time.time() - t_setup:.1f}s, tuning {tuning}")
+
+    elapsed = time_batched(B, b, args.steps, args.warmup, torch)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = total * args.steps / elapsed
+    log(f"batched: {ms_per_step:.3f} ms/step, {value:.4e} tracer-updates/s")
+
+    tr_ms, so_ms = kernel_timing(B, b)
+    bytes_launch = BYTES_PER_TRACER * total + BYTES_PER_CELL * cells
+    achieved = bytes_launch / (tr_ms * 1e-3) / 1e9
+    copy_gbps = B.sic_copy_bandwidth(4 << 30, 5)
+    log(f"tracer kernel {tr_ms:.3f} ms ({achieved:.0f} GB/s), solve kernel {so_ms:.3f} ms, copy {copy_gbps:.0f} GB/s")
+    B.sic_batch_destroy(b)
+    torch.cuda.empty_cache()
+
+    plain = None
+    if not args.no_plain:
+        rng = np.random.default_rng(7)
+        idx = rng.choice(len(specs), size=min(args.plain_instances, len(specs)), replace=False)
+        sub = [specs[i] for i in sorted(idx)]
+        rate, n_tr, dt = time_plain(B, sub, precision, 5, torch)
+        plain = {"value": rate, "unit": "tracer-updates/s", "instances": len(sub), "tracers": n_tr,
+                 "steps": 5, "batched_over_plain": value / rate}
+        log(f"plain: {rate:.4e} tracer-updates/s over {len(sub)} instances")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rate, n_inst, secs = cpu_baseline(specs, args.cpu_seconds)
+        cpu = {"value": rate, "unit": "tracer-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n_inst} instances of the same mix, 2 steps each, FP64 oracle, one thread "
+                         f"({secs:.1f}s)"}
+        log(f"cpu oracle: {rate:.4e} tracer-updates/s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tracer-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "split_f32": "i32+f32/i64/f64", "split_u32": "i32+u32/i64/f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"batched mix of {len(specs)} SIC 1D1V instances (Landau/two-stream, "
+                               "32-512 sheets x 64-2048 tracers, 64-1024 cells), one shared step",
+                   "instances": len(specs), "tracers": total, "cells": cells, "precision": args.precision,
+                   "tuning": tuning},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
+                     "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

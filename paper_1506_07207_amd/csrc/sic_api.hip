@@ -60,6 +60,11 @@ class ChunkAllocator {
     }
     return -1;
   }
+  // One past the last allocated element (0 when nothing is allocated).
+  int64_t used_end(int64_t cap) const {
+    if (!free_.empty() && free_.back().end == cap) return free_.back().begin;
+    return cap;
+  }
   void release(int64_t b, int64_t n) {
     if (n <= 0) return;
     Range r{b, b + n};
@@ -87,6 +92,7 @@ struct SlotHost {
   double L = 0.0, dt = 0.0;
   int64_t n_tracers = 0;
   int32_t chunk_begin = 0, n_chunks = 0;
+  int32_t item_begin = 0, n_items = 0;
   std::vector<int64_t> chunk_in_off;
   int64_t *d_in_off = nullptr;
   int state = kStale;
@@ -125,10 +131,10 @@ struct Pool {
   int32_t *slot_ids = nullptr;
 
   std::vector<SlotHost> slots;
-  ChunkAllocator alloc;
-  std::vector<Item> items_h;
+  ChunkAllocator alloc;       // tracer chunks
+  ChunkAllocator item_alloc;  // work items
   std::vector<int2> slot_items_h;
-  int32_t n_items_h = 0;
+  int32_t n_items_h = 0;      // item high-water mark (items the kernel walks)
   int parity = 0;
   sic_tuning tune{};  // requested (0 = automatic)
   int block = kDefaultBlock, grid = kDefaultGrid, tile = kMinTile;
@@ -221,6 +227,7 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   p->slots.resize(slot_cap);
   p->slot_items_h.assign(slot_cap, make_int2(0, 0));
   p->alloc.init(chunk_cap);
+  p->item_alloc.init(p->item_cap);
 
   auto bail = [&](const std::string &m, sic_status s) {
     if (err) *err = m;
@@ -285,15 +292,17 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   return SIC_OK;
 }
 
-// Work-item size in chunks for the pool's current contents.
-int auto_tile(const Pool *p, int64_t total_chunks) {
+// Work-item size in chunks for a slot of n_chunks chunks.  A batch uses one
+// size for every slot; a single simulation sizes its items to give the
+// machine about 2048 of them.
+int slot_tile(const Pool *p, int64_t n_chunks) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
-  // aim for about four work items per workgroup slot of the machine, with
-  // at least one chunk per wavefront of the workgroup
-  const int64_t per = (total_chunks + 2047) / 2048;
+  const int wave_min = p->block / kChunk;
+  if (p->batch) return std::max(128, wave_min);
+  const int64_t per = (n_chunks + 2047) / 2048;
   int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(64, per));
   t = (t + 3) / 4 * 4;
-  return std::max(t, p->block / 64);
+  return std::max(t, wave_min);
 }
 
 void apply_launch_shape(Pool *p) {
@@ -303,40 +312,74 @@ void apply_launch_shape(Pool *p) {
   else p->grid = std::max(1, std::min<int>(kDefaultGrid, p->n_items_h));
 }
 
-// Rebuilds the work-item list from the live slots and uploads it (stream
-// ordered; synchronises so host staging can be reused).
-sic_status rebuild_items(Pool *p) {
-  int64_t total = 0;
-  for (auto &s : p->slots)
-    if (s.live) total += s.n_chunks;
-  p->tile = auto_tile(p, total);
-  p->items_h.clear();
-  for (int32_t i = 0; i < p->slot_cap; ++i) {
-    SlotHost &s = p->slots[i];
-    const int32_t first = (int32_t)p->items_h.size();
-    if (s.live) {
-      for (int32_t c = 0; c < s.n_chunks; c += p->tile) {
-        Item it;
-        it.inst = i;
-        it.chunk_begin = s.chunk_begin + c;
-        it.chunk_end = s.chunk_begin + std::min(s.n_chunks, c + p->tile);
-        it.pad = 0;
-        p->items_h.push_back(it);
-      }
-    }
-    p->slot_items_h[i] = make_int2(first, (int32_t)p->items_h.size() - first);
-  }
-  if ((int64_t)p->items_h.size() > p->item_cap) return fail(p, SIC_ENOMEM, "work-item list over capacity");
-  p->n_items_h = (int32_t)p->items_h.size();
-  apply_launch_shape(p);
-  if (!p->items_h.empty())
-    HIPCHK(p, hipMemcpyAsync(p->items, p->items_h.data(), sizeof(Item) * p->items_h.size(), hipMemcpyHostToDevice,
-                             p->stream));
+// Uploads the device-side item count (the high-water mark of the item arena).
+sic_status upload_item_count(Pool *p) {
+  p->n_items_h = (int32_t)p->item_alloc.used_end(p->item_cap);
   HIPCHK(p, hipMemcpyAsync(p->n_items, &p->n_items_h, sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
-  HIPCHK(p, hipMemcpyAsync(p->slot_items, p->slot_items_h.data(), sizeof(int2) * p->slot_items_h.size(),
-                           hipMemcpyHostToDevice, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
+  apply_launch_shape(p);
   return SIC_OK;
+}
+
+// Lays out the work items of one slot in the item arena and uploads them.
+sic_status place_slot_items(Pool *p, int32_t slot) {
+  SlotHost &s = p->slots[slot];
+  const int tile = slot_tile(p, s.n_chunks);
+  p->tile = tile;
+  const int32_t n = (s.n_chunks + tile - 1) / tile;
+  const int64_t ib = p->item_alloc.alloc(n);
+  if (ib < 0) return fail(p, SIC_EBUSY, "work-item arena full");
+  std::vector<Item> its((size_t)n);
+  for (int32_t k = 0; k < n; ++k) {
+    its[k].inst = slot;
+    its[k].chunk_begin = s.chunk_begin + k * tile;
+    its[k].chunk_end = s.chunk_begin + std::min(s.n_chunks, (k + 1) * tile);
+    its[k].pad = 0;
+  }
+  s.item_begin = (int32_t)ib;
+  s.n_items = n;
+  p->slot_items_h[slot] = make_int2((int32_t)ib, n);
+  HIPCHK(p, hipMemcpyAsync(p->items + ib, its.data(), sizeof(Item) * (size_t)n, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->slot_items + slot, &p->slot_items_h[slot], sizeof(int2), hipMemcpyHostToDevice,
+                           p->stream));
+  return upload_item_count(p);
+}
+
+// Marks a slot's items dead (the kernels skip them) and frees their range.
+sic_status clear_slot_items(Pool *p, int32_t slot) {
+  SlotHost &s = p->slots[slot];
+  if (s.n_items > 0) {
+    std::vector<Item> dead((size_t)s.n_items);
+    for (auto &it : dead) {
+      it.inst = -1;
+      it.chunk_begin = it.chunk_end = it.pad = 0;
+    }
+    HIPCHK(p, hipMemcpyAsync(p->items + s.item_begin, dead.data(), sizeof(Item) * dead.size(), hipMemcpyHostToDevice,
+                             p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    p->item_alloc.release(s.item_begin, s.n_items);
+  }
+  s.item_begin = 0;
+  s.n_items = 0;
+  p->slot_items_h[slot] = make_int2(0, 0);
+  HIPCHK(p, hipMemcpyAsync(p->slot_items + slot, &p->slot_items_h[slot], sizeof(int2), hipMemcpyHostToDevice,
+                           p->stream));
+  return upload_item_count(p);
+}
+
+// Re-lays out every live slot's items (after a tuning change).
+sic_status relayout_items(Pool *p) {
+  for (int32_t i = 0; i < p->slot_cap; ++i) {
+    if (!p->slots[i].live) continue;
+    sic_status st = clear_slot_items(p, i);
+    if (st != SIC_OK) return st;
+  }
+  for (int32_t i = 0; i < p->slot_cap; ++i) {
+    if (!p->slots[i].live) continue;
+    sic_status st = place_slot_items(p, i);
+    if (st != SIC_OK) return st;
+  }
+  return upload_item_count(p);
 }
 
 TracerArgs tracer_args(Pool *p, int mode, int slot) {
@@ -608,10 +651,16 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   I.live = 1;
 
   auto undo = [&]() {
+    if (sh.n_items > 0) clear_slot_items(p, slot);
     p->alloc.release(cb, n_ch);
     sh.live = false;
     sh.chunk_in_off.clear();
   };
+  st = place_slot_items(p, slot);
+  if (st != SIC_OK) {
+    undo();
+    return st;
+  }
   hipError_t e = hipSuccess;
   if (!sh.d_in_off) {
     e = hipMalloc((void **)&sh.d_in_off, sizeof(int64_t) * (size_t)std::max<int64_t>(n_ch, 1));
@@ -655,11 +704,6 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   }
   p->used_tracers += n_tr;
   p->used_slots += 1;
-  st = rebuild_items(p);
-  if (st != SIC_OK) {
-    if (stage) hipFree(stage);
-    return st;
-  }
   // ingest: place tracers, deposit, solve, half back-kick
   IngestArgs ia;
   ia.x_in = dx0;
@@ -697,6 +741,8 @@ sic_status pool_release(Pool *p, int32_t slot) {
   std::memset(&I, 0, sizeof(I));
   HIPCHK(p, hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
+  sic_status st = clear_slot_items(p, slot);
+  if (st != SIC_OK) return st;
   p->alloc.release(sh.chunk_begin, sh.n_chunks);
   p->used_tracers -= sh.n_tracers;
   p->used_slots -= 1;
@@ -706,7 +752,7 @@ sic_status pool_release(Pool *p, int32_t slot) {
     hipFree(sh.d_in_off);
     sh.d_in_off = nullptr;
   }
-  return rebuild_items(p);
+  return SIC_OK;
 }
 
 sic_status read_inst(Pool *p, int32_t slot, InstDesc *I) {
@@ -900,7 +946,8 @@ sic_status apply_tuning(Pool *p, const sic_tuning *t) {
   HIPCHK(p, hipStreamSynchronize(p->stream));
   p->tune = *t;
   destroy_graphs(p);
-  return rebuild_items(p);
+  apply_launch_shape(p);
+  return relayout_items(p);
 }
 
 }  // namespace
@@ -1025,7 +1072,7 @@ sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t m
   sic_status st = pool_create(precision, true, max_slots, max_cells, chunks, rows, budget_tracers, hip_stream, &p,
                               &err);
   if (st != SIC_OK) return st;
-  st = rebuild_items(p);
+  st = upload_item_count(p);
   if (st != SIC_OK) {
     pool_free(p);
     return st;

@@ -285,6 +285,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item item = a.items[it];
+    if (item.inst < 0) continue;  // freed slot
     const InstDesc &I = a.inst[item.inst];
     if (a.respect_active && !I.active) continue;
     Geo g;
