@@ -32,7 +32,8 @@ namespace {
 
 constexpr int kGraphSteps = 32;         // steps per captured graph
 constexpr int kDefaultGrid = 2048;      // persistent tracer workgroups (8 per CU)
-constexpr int kDefaultBlock = 256;
+constexpr int kDefaultBlock = 256;       // single simulations
+constexpr int kDefaultBatchBlock = 512;  // batches (measured best of 256/512/1024)
 constexpr int kMinTile = 4;             // chunks per work item, lower bound
 constexpr int kMaxTile = 256;
 
@@ -223,7 +224,7 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   p->item_cap = chunk_cap / kMinTile + slot_cap + 1;
   p->hist_rows = hist_rows;
   p->budget = budget;
-  p->lds_bytes = 2 * (size_t)max_cells * acc_size(prec) + 48 * sizeof(double);
+  p->lds_bytes = tracer_lds_size(prec, max_cells, kMaxTile);
   p->slots.resize(slot_cap);
   p->slot_items_h.assign(slot_cap, make_int2(0, 0));
   p->alloc.init(chunk_cap);
@@ -298,7 +299,7 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
 int slot_tile(const Pool *p, int64_t n_chunks) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
   const int wave_min = p->block / kChunk;
-  if (p->batch) return std::max(128, wave_min);
+  if (p->batch) return std::max(128, wave_min);  // ~8k tracers: one mesh merge per 8k tracers
   const int64_t per = (n_chunks + 2047) / 2048;
   int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(64, per));
   t = (t + 3) / 4 * 4;
@@ -306,7 +307,7 @@ int slot_tile(const Pool *p, int64_t n_chunks) {
 }
 
 void apply_launch_shape(Pool *p) {
-  p->block = p->tune.block_threads > 0 ? p->tune.block_threads : kDefaultBlock;
+  p->block = p->tune.block_threads > 0 ? p->tune.block_threads : (p->batch ? kDefaultBatchBlock : kDefaultBlock);
   if (p->tune.grid_blocks > 0) p->grid = p->tune.grid_blocks;
   else if (p->batch) p->grid = kDefaultGrid;
   else p->grid = std::max(1, std::min<int>(kDefaultGrid, p->n_items_h));
@@ -404,6 +405,7 @@ TracerArgs tracer_args(Pool *p, int mode, int slot) {
   a.meshE = p->meshE;
   a.partials = p->partials + first;
   a.mesh_cells = p->max_cells;
+  a.tile_cap = p->tile;
   a.respect_active = (p->batch && !one) ? 1 : 0;
   return a;
 }
@@ -432,7 +434,8 @@ int grid_for(Pool *p, int slot) {
 
 sic_status launch_tracer_mode(Pool *p, int mode, int slot, hipStream_t st) {
   TracerArgs a = tracer_args(p, mode, slot);
-  LAUNCHCHK(p, launch_tracers(p->prec, mode, a, grid_for(p, slot), p->block, p->lds_bytes, st));
+  const size_t lds = tracer_lds_size(p->prec, p->max_cells, p->tile);
+  LAUNCHCHK(p, launch_tracers(p->prec, mode, a, grid_for(p, slot), p->block, lds, st));
   return SIC_OK;
 }
 

@@ -98,6 +98,7 @@ struct TracerArgs {
   const double *meshE;
   Partial *partials;       // per item
   int32_t mesh_cells;      // LDS capacity in cells (max n_cells of the pool)
+  int32_t tile_cap;        // LDS capacity in chunks per work item
   int32_t respect_active;  // skip slots with active == 0
 };
 
@@ -145,6 +146,7 @@ struct ExtractArgs {
 int launch_tracers(int prec, int mode, const TracerArgs &a, int grid, int block, size_t lds_bytes,
                    void *stream);
 int set_tracer_lds_limit(int prec, size_t lds_bytes);
+size_t tracer_lds_size(int prec, int mesh_cells, int tile_cap);
 int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream);
 int launch_ingest(int prec, const IngestArgs &a, void *stream);
 int launch_extract(int prec, const ExtractArgs &a, void *stream);

@@ -109,7 +109,7 @@ __device__ __forceinline__ double mesh_pos(uint64_t w, double inv_dx) {
 
 // Field at a tracer: linear interpolation between the two cell centres
 // around it (first-order weighting).  u is the position in mesh units.
-__device__ __forceinline__ double gather_field(const double *__restrict__ E, double u, int nc) {
+__device__ __forceinline__ double gather_field(const double *E, double u, int nc) {
   const double g = u - 0.5;
   const double f = floor(g);
   const double s = g - f;
@@ -266,22 +266,35 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------
 // Tracer kernel
 // ---------------------------------------------------------------------------
+// Per-item LDS layout (bytes): P, D accumulators and the field E for
+// mesh_cells cells; the item's chunk descriptors and the halo copies of their
+// partner chunks for tile_cap chunks; 48 doubles for the block reduction.
+template <class Acc>
+__host__ __device__ constexpr size_t tracer_lds_bytes(int mesh_cells, int tile_cap) {
+  return 2 * (size_t)mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
+         (size_t)tile_cap * (sizeof(ChunkDesc) + sizeof(double2)) + 48 * sizeof(double);
+}
+
 template <int PREC, int MODE>
 __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   acc_t *sP = reinterpret_cast<acc_t *>(smem);
   acc_t *sD = sP + a.mesh_cells;
-  double *sRed = reinterpret_cast<double *>(sD + a.mesh_cells);  // 3 x 16 waves
+  double *sE = reinterpret_cast<double *>(sD + a.mesh_cells);
+  ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sE + a.mesh_cells);
+  double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);
+  double *sRed = reinterpret_cast<double *>(sHalo + a.tile_cap);  // 3 x 16 waves
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nwaves = blockDim.x >> 6;
   const int n_items = *a.n_items;
   constexpr bool kDep = (MODE & kDeposit) != 0;
   constexpr bool kMove = (MODE & kPush) != 0;
   constexpr bool kKick = (MODE & kKickHalf) != 0;
+  constexpr bool kField = kMove || kKick;
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item item = a.items[it];
@@ -295,58 +308,79 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     g.inv_dx = I.inv_dx;
     g.dt = I.dt;
     g.nc = I.n_cells;
-    const double *__restrict__ E = a.meshE + I.mesh_off;
+    const int cb = item.chunk_begin;
+    const int nch = item.chunk_end - item.chunk_begin;
 
-    if constexpr (kDep) {
-      for (int i = tid; i < g.nc; i += blockDim.x) {
+    // Stage the item's tables in LDS: one pass of global reads per item
+    // instead of dependent reads per chunk.
+    for (int i = tid; i < g.nc; i += blockDim.x) {
+      if constexpr (kDep) {
         sP[i] = (acc_t)0;
         sD[i] = (acc_t)0;
+      }
+      if constexpr (kField) sE[i] = a.meshE[I.mesh_off + i];
+    }
+    for (int i = tid; i < nch; i += blockDim.x) sDesc[i] = a.chunks[cb + i];
+    __syncthreads();
+    if constexpr (kDep) {
+      for (int i = tid; i < nch; i += blockDim.x) {
+        const int pc = sDesc[i].partner;
+        if (pc >= 0) sHalo[i] = a.halo_in[pc];
       }
       __syncthreads();
     }
 
+    // Chunk loop: wave w takes local chunks w, w + nwaves, ...  The loop is
+    // unrolled three times with fixed registers per stage, so the state of
+    // the next two chunks is in flight while the current one is processed
+    // (moving a register whose load is pending would force a wait).
     double ke = 0.0, mom = 0.0, ms = 0.0;
-    for (int c = item.chunk_begin + wave; c < item.chunk_end; c += nwaves) {
-      const ChunkDesc ch = a.chunks[c];
-      const bool valid = lane < ch.n_valid;
-      const size_t s = (size_t)c * kChunk + lane;
-      uint64_t xw = 0;
-      double v = 0.0;
-      if (valid) {
-        xw = a.xs[s];
-        v = a.vs[s];
-      }
-      if constexpr (kMove || kKick) {
-        if (valid) {
-          const double e = gather_field(E, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
-          if constexpr (kKick) {
-            v = v - (0.5 * g.dt) * e;
-            a.vs[s] = v;
-          } else {
-            const double vn = v + g.dt * e;
-            ke += 0.5 * ch.q * v * vn;
-            mom += ch.q * (0.5 * (v + vn));
-            v = vn;
-            xw = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
-            a.xs[s] = xw;
-            a.vs[s] = vn;
-          }
+    // Loads and stores are unconditional (a chunk always has 64 slots; the
+    // padding slots of a sheet's last chunk are read and written back
+    // unchanged), so the only branches around memory operations are uniform.
+    auto load_state = [&](int kk, uint64_t &xw, double &v) {
+      const int kc = kk < nch ? kk : nch - 1;
+      const size_t s = (size_t)(cb + kc) * kChunk + lane;
+      xw = a.xs[s];
+      v = a.vs[s];
+    };
+    auto process = [&](int kk, uint64_t xw, double v) {
+      const ChunkDesc ch = sDesc[kk];
+      const int n_valid = __builtin_amdgcn_readfirstlane(ch.n_valid);
+      const bool valid = lane < n_valid;
+      const size_t s = (size_t)(cb + kk) * kChunk + lane;
+      if constexpr (kField) {
+        const double e = gather_field(sE, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
+        if constexpr (kKick) {
+          const double vk = v - (0.5 * g.dt) * e;
+          v = valid ? vk : v;
+          a.vs[s] = v;
+        } else {
+          const double vn = v + g.dt * e;
+          const double qv = valid ? ch.q : 0.0;
+          ke += 0.5 * qv * v * vn;
+          mom += qv * (0.5 * (v + vn));
+          const uint64_t xn = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
+          xw = valid ? xn : xw;
+          v = valid ? vn : v;
+          a.xs[s] = xw;
+          a.vs[s] = v;
         }
-        if (lane == 0) a.halo_out[c] = make_double2(__longlong_as_double((long long)xw), v);
+        if (lane == 0) a.halo_out[cb + kk] = make_double2(__longlong_as_double((long long)xw), v);
       }
       if constexpr (kDep) {
         uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
-        const bool tail = (lane == ch.n_valid - 1);
+        const bool tail = (lane == n_valid - 1);
         bool has_seg = valid;
         if (tail) {
           if (ch.partner < 0) {
             has_seg = false;  // open sheet: the last tracer ends the chain
           } else {
-            const double2 h = a.halo_in[ch.partner];
+            const double2 h = sHalo[kk];
             pw = (uint64_t)__double_as_longlong(h.x);
             if constexpr (kMove) {
               // the partner's move, recomputed from its state before this step
-              const double e = gather_field(E, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
+              const double e = gather_field(sE, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
               const double hv = h.y + g.dt * e;
               pw = drift<PREC>(pw, hv, g.dt, g.L, g.inv_dx, g.nc);
             }
@@ -363,6 +397,21 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           ms = nan_max(ms, len);
         }
       }
+    };
+    uint64_t xa = 0, xb = 0, xc = 0;
+    double va = 0.0, vb = 0.0, vc = 0.0;
+    load_state(wave, xa, va);
+    load_state(wave + nwaves, xb, vb);
+    load_state(wave + 2 * nwaves, xc, vc);
+    for (int k = wave; k < nch; k += 3 * nwaves) {
+      process(k, xa, va);
+      load_state(k + 3 * nwaves, xa, va);
+      if (k + nwaves >= nch) break;
+      process(k + nwaves, xb, vb);
+      load_state(k + 4 * nwaves, xb, vb);
+      if (k + 2 * nwaves >= nch) break;
+      process(k + 2 * nwaves, xc, vc);
+      load_state(k + 5 * nwaves, xc, vc);
     }
 
     // Work-item partial sums in a fixed order (deterministic for a fixed
@@ -379,14 +428,14 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      double k = 0.0, m = 0.0, x = 0.0;
+      double kk = 0.0, m = 0.0, x = 0.0;
       for (int w = 0; w < nwaves; ++w) {
-        k += sRed[w];
+        kk += sRed[w];
         m += sRed[16 + w];
         x = nan_max(x, sRed[32 + w]);
       }
       if constexpr (kMove) {
-        a.partials[it].ke = k;
+        a.partials[it].ke = kk;
         a.partials[it].mom = m;
       }
       if constexpr (kDep) a.partials[it].maxseg = x;
@@ -409,6 +458,11 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     }
     __syncthreads();
   }
+}
+
+size_t tracer_lds_size(int prec, int mesh_cells, int tile_cap) {
+  return prec == kFP64 ? tracer_lds_bytes<double>(mesh_cells, tile_cap)
+                       : tracer_lds_bytes<unsigned long long>(mesh_cells, tile_cap);
 }
 
 // ---------------------------------------------------------------------------
