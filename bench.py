@@ -49,6 +49,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape with the autotuner first")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="seconds of Poisson arrivals for the serving run (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--plain-serve-requests", type=int, default=100)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
@@ -139,6 +144,45 @@ def cpu_baseline(specs, seconds):
     return done_updates / t_total, len(used), t_total
 
 
+def serving(B, S, I, value, args, torch):
+    """Continuous-batching run: Poisson arrivals drawn like the mixed batch
+    plus rare large jobs (2048 x 16384 tracers on 4096 cells), at a fraction
+    of the measured saturation rate; then the plain one-request-at-a-time
+    server on a prefix of the same stream."""
+    sample = list(I.request_stream(4000, 1.0, seed=20251204))
+    mean_work = float(np.mean([r.spec.tracers * r.spec.n_steps for r in sample]))
+    rate = args.serve_load * value / mean_work
+    n = max(20, int(rate * args.serve_seconds))
+    reqs = S.poisson_stream(n, rate)
+    log(f"serving {n} requests at {rate:.1f}/s (mean {mean_work:.3e} tracer-updates per request)")
+    ex = S.GpuExecutor()
+    try:
+        rep = S.Server(ex, chunk_steps=32).run(reqs, warmup_fraction=0.2, prepare=S.serve_prepare(ex))
+    finally:
+        ex.close()
+    torch.cuda.empty_cache()
+    summ = rep.summary()
+    log(f"served: p50 {summ['p50_s']:.3f}s p99 {summ['p99_s']:.3f}s, {summ['tracer_updates_per_s']:.3e} tracer-updates/s")
+    out = {"rate_rps": rate, "load": args.serve_load, "mean_updates_per_request": mean_work, **summ}
+    m = min(args.plain_serve_requests, n)
+    if m > 0:
+        prefix = reqs[:m]
+        ex = S.GpuExecutor()
+        try:
+            brep = S.Server(ex, chunk_steps=32).run(prefix, warmup_fraction=0.0, prepare=S.serve_prepare(ex))
+        finally:
+            ex.close()
+        prep = S.serve_plain(prefix)
+        prep.warmup_fraction = 0.0
+        ps, bs = prep.summary(), brep.summary()
+        out["prefix_requests"] = m
+        out["prefix_batched"] = {k: bs[k] for k in ("p50_s", "p99_s", "tracer_updates_per_s", "wall_s")}
+        out["prefix_plain"] = {k: ps[k] for k in ("p50_s", "p99_s", "tracer_updates_per_s", "wall_s")}
+        log(f"prefix of {m}: batched p50 {bs['p50_s']:.3f}s p99 {bs['p99_s']:.3f}s; "
+            f"plain p50 {ps['p50_s']:.3f}s p99 {ps['p99_s']:.3f}s")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -160,8 +204,14 @@ def main():
     log(f"building batch of {len(specs)} instances ({args.precision})")
     t_setup = time.time()
     b, total, cells = build_batch(B, specs, precision, torch)
+    tuned = None
     if args.tile or args.block or args.grid:
         B.sic_batch_set_tuning(b, args.tile, args.block, args.grid)
+    elif args.autotune:
+        t0 = time.time()
+        best, best_ms = B.sic_batch_autotune(b, 3)
+        tuned = {"best": best, "ms_per_step": best_ms, "seconds": time.time() - t0}
+        log(f"autotune: {best} {best_ms:.3f} ms/step ({time.time() - t0:.1f}s)")
     tuning = B.sic_batch_get_tuning(b)
     log(f"resident tracers {total:.3e}, setup {time.time() - t_setup:.1f}s, tuning {tuning}")
 
@@ -188,6 +238,11 @@ def main():
                  "steps": 5, "batched_over_plain": value / rate}
         log(f"plain: {rate:.4e} tracer-updates/s over {len(sub)} instances")
 
+    serve = None
+    if args.serve_seconds > 0:
+        from paper_1506_07207_amd import serve as S
+        serve = serving(B, S, I, value, args, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         rate, n_inst, secs = cpu_baseline(specs, args.cpu_seconds)
@@ -212,12 +267,13 @@ def main():
         "config": {"workload": f"batched mix of {len(specs)} SIC 1D1V instances (Landau/two-stream, "
                                "32-512 sheets x 64-2048 tracers, 64-1024 cells), one shared step",
                    "instances": len(specs), "tracers": total, "cells": cells, "precision": args.precision,
-                   "tuning": tuning},
+                   "tuning": tuning, "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
         "plain": plain,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

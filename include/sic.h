@@ -236,6 +236,17 @@ const char *sic_batch_last_error(const sic_batch *b);
 sic_status sic_batch_set_timing(sic_batch *b, int32_t timing);
 sic_status sic_batch_last_timing(const sic_batch *b, double *tracer_ms, double *solve_ms);
 
+/* Autotuner.  Times every candidate launch shape (chunks per work item,
+ * threads per workgroup, persistent grid size) for steps_per_trial steps on
+ * the handle's own resident simulations, with HIP events around each kernel,
+ * then restores the simulations to their state before the call (the trial
+ * steps leave no trace; the device briefly holds a second copy of the state)
+ * and applies the fastest shape.  best / best_ms (may be NULL) receive it and
+ * its time per step.  Synchronous; SIC_ENOMEM if the state copy does not
+ * fit. */
+sic_status sic_autotune(sic_sim *sim, int32_t steps_per_trial, sic_tuning *best, double *best_ms);
+sic_status sic_batch_autotune(sic_batch *b, int32_t steps_per_trial, sic_tuning *best, double *best_ms);
+
 /* Single-simulation timing, as sic_batch_set_timing / sic_batch_last_timing. */
 sic_status sic_set_timing(sic_sim *sim, int32_t timing);
 sic_status sic_last_timing(const sic_sim *sim, double *tracer_ms, double *solve_ms);

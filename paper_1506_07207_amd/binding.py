@@ -96,6 +96,8 @@ _SIGS = {
     "sic_batch_set_timing": (_I32, [_P, _I32]),
     "sic_batch_last_timing": (_I32, [_P, _P, _P]),
     "sic_copy_bandwidth": (_I32, [_I64, _I32, _P, _P]),
+    "sic_autotune": (_I32, [_P, _I32, _P, _P]),
+    "sic_batch_autotune": (_I32, [_P, _I32, _P, _P]),
 }
 
 
@@ -412,6 +414,21 @@ def sic_batch_get_tuning(b) -> dict:
     t = sic_tuning()
     _check(load().sic_batch_get_tuning(b, ctypes.byref(t)), "sic_batch_get_tuning", b, batch=True)
     return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks)
+
+
+def sic_autotune(h, steps_per_trial: int = 3):
+    t = sic_tuning()
+    ms = ctypes.c_double(0)
+    _check(load().sic_autotune(h, int(steps_per_trial), ctypes.byref(t), ctypes.byref(ms)), "sic_autotune", h)
+    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks), ms.value
+
+
+def sic_batch_autotune(b, steps_per_trial: int = 3):
+    t = sic_tuning()
+    ms = ctypes.c_double(0)
+    _check(load().sic_batch_autotune(b, int(steps_per_trial), ctypes.byref(t), ctypes.byref(ms)),
+           "sic_batch_autotune", b, batch=True)
+    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks), ms.value
 
 
 def sic_batch_set_timing(b, on: bool):

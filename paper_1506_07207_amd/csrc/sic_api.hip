@@ -368,19 +368,158 @@ sic_status clear_slot_items(Pool *p, int32_t slot) {
   return upload_item_count(p);
 }
 
-// Re-lays out every live slot's items (after a tuning change).
+sic_status run_fused(Pool *p, int64_t n);
+
+// Re-lays out every live slot's items (after a tuning change) in one upload.
 sic_status relayout_items(Pool *p) {
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  p->item_alloc.init(p->item_cap);
+  std::vector<Item> its;
+  int tile = p->tile;
   for (int32_t i = 0; i < p->slot_cap; ++i) {
-    if (!p->slots[i].live) continue;
-    sic_status st = clear_slot_items(p, i);
-    if (st != SIC_OK) return st;
+    SlotHost &s = p->slots[i];
+    if (!s.live) {
+      p->slot_items_h[i] = make_int2(0, 0);
+      continue;
+    }
+    tile = slot_tile(p, s.n_chunks);
+    const int32_t n = (s.n_chunks + tile - 1) / tile;
+    const int64_t ib = p->item_alloc.alloc(n);
+    if (ib < 0 || ib != (int64_t)its.size()) return fail(p, SIC_ENOMEM, "work-item arena full");
+    for (int32_t k = 0; k < n; ++k) {
+      Item it;
+      it.inst = i;
+      it.chunk_begin = s.chunk_begin + k * tile;
+      it.chunk_end = s.chunk_begin + std::min(s.n_chunks, (k + 1) * tile);
+      it.pad = 0;
+      its.push_back(it);
+    }
+    s.item_begin = (int32_t)ib;
+    s.n_items = n;
+    p->slot_items_h[i] = make_int2((int32_t)ib, n);
   }
-  for (int32_t i = 0; i < p->slot_cap; ++i) {
-    if (!p->slots[i].live) continue;
-    sic_status st = place_slot_items(p, i);
-    if (st != SIC_OK) return st;
-  }
+  p->tile = tile;
+  if (!its.empty())
+    HIPCHK(p, hipMemcpyAsync(p->items, its.data(), sizeof(Item) * its.size(), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->slot_items, p->slot_items_h.data(), sizeof(int2) * p->slot_items_h.size(),
+                           hipMemcpyHostToDevice, p->stream));
   return upload_item_count(p);
+}
+
+// Device copy of everything a step modifies, so trial steps (autotuning) can
+// be undone.
+struct Snapshot {
+  std::vector<std::pair<void *, size_t>> bufs;  // (copy, bytes) per source buffer
+  std::vector<void *> srcs;
+  int parity = 0;
+};
+
+void snapshot_free(Snapshot &s) {
+  for (auto &b : s.bufs)
+    if (b.first) hipFree(b.first);
+  s.bufs.clear();
+  s.srcs.clear();
+}
+
+sic_status snapshot_take(Pool *p, Snapshot &s) {
+  const size_t mc = (size_t)p->slot_cap * p->max_cells * 8;
+  const size_t slots = (size_t)p->chunk_cap * kChunk * 8;
+  std::pair<void *, size_t> src[] = {
+      {p->xs, slots},
+      {p->vs, slots},
+      {p->halo[0], (size_t)p->chunk_cap * sizeof(double2)},
+      {p->halo[1], (size_t)p->chunk_cap * sizeof(double2)},
+      {p->meshP, mc},
+      {p->meshD, mc},
+      {p->meshE, mc},
+      {p->meshRho, mc},
+      {p->inst, sizeof(InstDesc) * (size_t)p->slot_cap},
+      {p->hist, sizeof(DiagRow) * (size_t)p->slot_cap * p->hist_rows},
+      {p->done, sizeof(int32_t) * (size_t)p->slot_cap},
+  };
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  for (auto &b : src) {
+    void *d = nullptr;
+    if (hipMalloc(&d, b.second) != hipSuccess) {
+      snapshot_free(s);
+      return fail(p, SIC_ENOMEM, "no device memory for the tuning snapshot");
+    }
+    s.bufs.push_back({d, b.second});
+    s.srcs.push_back(b.first);
+    HIPCHK(p, hipMemcpyAsync(d, b.first, b.second, hipMemcpyDeviceToDevice, p->stream));
+  }
+  s.parity = p->parity;
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return SIC_OK;
+}
+
+sic_status snapshot_restore(Pool *p, Snapshot &s) {
+  for (size_t i = 0; i < s.bufs.size(); ++i)
+    HIPCHK(p, hipMemcpyAsync(s.srcs[i], s.bufs[i].first, s.bufs[i].second, hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  p->parity = s.parity;
+  return SIC_OK;
+}
+
+// Times every candidate launch shape on the pool's own resident simulations
+// (HIP events around each kernel), then restores the state and keeps the
+// fastest shape.  Candidates: chunks per work item (LDS mesh merges per
+// tracer), threads per workgroup (waves sharing one LDS mesh) and persistent
+// grid size.
+sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *best_ms_out) {
+  if (steps < 1) return fail(p, SIC_EINVAL, "steps_per_trial < 1");
+  Snapshot snap;
+  sic_status st = snapshot_take(p, snap);
+  if (st != SIC_OK) return st;
+  const sic_tuning saved = p->tune;
+  const bool saved_timing = p->timing;
+  p->timing = true;
+  const int tiles[] = {32, 64, 128, 256};
+  const int blocks[] = {256, 512, 1024};
+  const int grids[] = {1024, 2048, 4096};
+  sic_tuning best = saved;
+  double best_ms = 1e300;
+  for (int t : tiles) {
+    if (!p->batch && t > 64) continue;
+    for (int b : blocks) {
+      if (t * kChunk < b) continue;  // every wave gets at least one chunk
+      for (int g : grids) {
+        sic_tuning cand{t, b, g, 0};
+        p->tune = cand;
+        destroy_graphs(p);
+        apply_launch_shape(p);
+        st = relayout_items(p);
+        if (st == SIC_OK) st = run_fused(p, 1);
+        if (st == SIC_OK) st = run_fused(p, steps);
+        if (st != SIC_OK) break;
+        const double ms = p->t_tracer + p->t_solve;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cand;
+        }
+      }
+      if (st != SIC_OK) break;
+    }
+    if (st != SIC_OK) break;
+  }
+  p->timing = saved_timing;
+  sic_status rs = snapshot_restore(p, snap);
+  snapshot_free(snap);
+  p->tune = (st == SIC_OK) ? best : saved;
+  destroy_graphs(p);
+  apply_launch_shape(p);
+  sic_status ls = relayout_items(p);
+  if (st != SIC_OK) return st;
+  if (rs != SIC_OK) return rs;
+  if (ls != SIC_OK) return ls;
+  if (best_out) {
+    best_out->tile_chunks = p->tile;
+    best_out->block_threads = p->block;
+    best_out->grid_blocks = p->grid;
+    best_out->reserved = 0;
+  }
+  if (best_ms_out) *best_ms_out = best_ms;
+  return SIC_OK;
 }
 
 TracerArgs tracer_args(Pool *p, int mode, int slot) {
@@ -1163,6 +1302,16 @@ void sic_batch_destroy(sic_batch *b) {
 }
 
 const char *sic_batch_last_error(const sic_batch *b) { return b ? b->pool->err.c_str() : g_last_error.c_str(); }
+
+sic_status sic_autotune(sic_sim *sim, int32_t steps_per_trial, sic_tuning *best, double *best_ms) {
+  if (!sim) return SIC_EINVAL;
+  return pool_autotune(sim->pool, steps_per_trial, best, best_ms);
+}
+
+sic_status sic_batch_autotune(sic_batch *b, int32_t steps_per_trial, sic_tuning *best, double *best_ms) {
+  if (!b) return SIC_EINVAL;
+  return pool_autotune(b->pool, steps_per_trial, best, best_ms);
+}
 
 sic_status sic_batch_set_timing(sic_batch *b, int32_t timing) {
   if (!b) return SIC_EINVAL;

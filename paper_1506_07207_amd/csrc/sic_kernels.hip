@@ -796,9 +796,15 @@ static hipError_t set_lds_limit(size_t bytes) {
                              b);
 }
 
+// The limit is a property of the kernel function, shared by every pool in
+// the process, so it only ever grows.
 int set_tracer_lds_limit(int prec, size_t lds) {
+  static size_t granted[3] = {65536, 65536, 65536};
+  if (prec < 0 || prec > 2) return (int)hipErrorInvalidValue;
+  if (lds <= granted[prec]) return 0;
   hipError_t e = prec == kFP64 ? set_lds_limit<kFP64>(lds)
                                : (prec == kSplitF32 ? set_lds_limit<kSplitF32>(lds) : set_lds_limit<kSplitU32>(lds));
+  if (e == hipSuccess) granted[prec] = lds;
   return (int)e;
 }
 
