@@ -38,6 +38,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(precision, instances):
+    """HBM bytes per tracer-kernel launch from the committed rocprofv3 counter
+    summary, valid only for the profiled workload and only while the kernel
+    source is the one that was profiled (None otherwise)."""
+    import hashlib
+
+    if precision != "fp64" or instances != 4096:
+        return None
+    summ = os.path.join(ROOT, "profiles", "k_tracers_fp64_mixed4096_traffic.md")
+    src = os.path.join(ROOT, "paper_1506_07207_amd", "csrc", "sic_kernels.hip")
+    try:
+        kv = dict(line.strip().split("=", 1) for line in open(summ) if "=" in line and " " not in line.strip())
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256_16") != digest:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,7 +289,7 @@ def main():
                    "instances": len(specs), "tracers": total, "cells": cells, "precision": args.precision,
                    "tuning": tuning, "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": profiled_traffic(args.precision, args.instances),
                      "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
         "plain": plain,

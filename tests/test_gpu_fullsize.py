@@ -1,0 +1,126 @@
+"""Parity at the full workload sizes, on outputs the oracle can afford:
+single steps of the full two-stream configuration and of a large served job,
+sampled instances of the 4096-instance mixed batch in the launch shape the
+benchmark times, and a full-length two-stream run at reduced tracer count."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1506_07207_amd import binding as B
+from paper_1506_07207_amd import inputs as I
+from tests.parity import envelope_rel, periodic_diff, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _one_step(p, prec):
+    with B.Simulation(p, precision=prec, history_rows=16) as s:
+        s.step(1)
+        x, v, step = s.state()
+        d = s.diagnostics()
+    return x, v, d
+
+
+@pytest.mark.parametrize("prec", [B.SIC_FP64, B.SIC_SPLIT_U32])
+def test_two_stream_full_size_single_step(prec):
+    p = I.two_stream()  # 512 sheets x 4096 tracers, 1024 cells
+    print(f"case two_stream full size prec={prec}", flush=True)
+    ref = O.run_problem(p, 1)
+    x, v, d = _one_step(p, prec)
+    dx = p.L / p.n_cells
+    if prec == B.SIC_FP64:
+        assert np.max(periodic_diff(x, ref["x"], p.L)) < 1e-12 * p.L
+        assert abs(d["last"]["W_E"] - ref["hist"][1, 2]) < 1e-10 * ref["hist"][1, 2]
+        assert rel_inf(d["E"], ref["E"]) < 1e-10
+    else:
+        assert np.max(periodic_diff(x, ref["x"], p.L)) < 2.0 ** -30 * dx
+        assert abs(d["last"]["W_E"] - ref["hist"][1, 2]) < 1e-6 * ref["hist"][1, 2]
+    rho_o = ref["Q"] / dx - ref["Q"].sum() / p.L
+    assert np.max(np.abs(d["rho"] - rho_o)) < 1e-10
+
+
+def test_two_stream_full_length_reduced_tracers():
+    """2000 steps of the two-stream configuration with 64 sheets x 1024
+    tracers: the split (uint32 fraction) form stays within 1e-6 of the FP64
+    oracle in field energy over the whole run; the FP64 form within 1e-10
+    until the nonlinear vortex (t ~ 75) starts to amplify rounding
+    differences, after which the first step over 1e-10 is reported."""
+    p = I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=2000)
+    print("case two_stream 64x1024, 2000 steps", flush=True)
+    ref = O.run_problem(p)
+    Wr = ref["hist"][:, 2]
+    res = {}
+    for prec in (B.SIC_FP64, B.SIC_SPLIT_U32):
+        with B.Simulation(p, precision=prec) as s:
+            s.step(p.n_steps)
+            res[prec] = s.diagnostics()["history"]["W_E"]
+    err_u32 = envelope_rel(res[B.SIC_SPLIT_U32], Wr, p.dt)
+    P = int(math.ceil(2 * math.pi / p.dt))
+    env = np.array([np.max(Wr[max(0, i - P): i + P + 1]) for i in range(len(Wr))])
+    e64 = np.abs(res[B.SIC_FP64] - Wr) / env
+    over = np.nonzero(e64 > 1e-10)[0]
+    first = int(over[0]) if len(over) else None
+    print(f"split_u32 envelope error {err_u32:.3e}; fp64 max {e64.max():.3e}, first step over 1e-10: {first}",
+          flush=True)
+    assert err_u32 < 1e-6
+    assert np.max(e64[:1500]) < 1e-10
+
+
+def test_mixed_batch_sampled_instances():
+    """All 4096 instances resident and stepped together (default launch shape
+    of the benchmark); a sample of them is compared with the oracle run alone."""
+    specs = I.batch_mix(4096)
+    total = sum(s.tracers for s in specs)
+    b = B.sic_batch_create(total, len(specs), 1024, history_rows=64)
+    import torch
+
+    try:
+        for s in specs:
+            p = s.build()
+            x0 = torch.from_numpy(p.line).cuda().repeat(p.n_sheets)
+            v0 = torch.from_numpy(p.sheet_v).cuda().repeat_interleave(int(p.n_tracers[0]))
+            B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x0, v0, p.n_steps)
+        steps = 6
+        B.sic_batch_step(b, steps)
+        work = np.array([s.tracers for s in specs])
+        rng = np.random.default_rng(1)
+        small = np.nonzero(work < 60000)[0]
+        sample = list(rng.choice(small, size=6, replace=False)) + [int(np.argmax(work))]
+        for i in sample:
+            p = specs[i].build()
+            ref = O.run_problem(p, steps)
+            r = B.sic_batch_result(b, int(i), p.n_cells)
+            h = r["history"]
+            assert h["step"][-1] == steps
+            err = np.max(np.abs(h["W_E"] - ref["hist"][:, 2]) / np.max(ref["hist"][:, 2]))
+            assert err < 1e-10, (i, err)
+            assert rel_inf(r["E"], ref["E"]) < 1e-10
+    finally:
+        B.sic_batch_destroy(b)
+
+
+def test_large_job_single_step():
+    """A served large job: 2048 sheets x 16384 tracers on 4096 cells (FP64)."""
+    spec = I.BatchSpec("landau", 0.4, 0.05, 2048, 16384, 4096, 0.08, 1)
+    p = spec.build()
+    print(f"case large job {p.total_tracers} tracers", flush=True)
+    ref = O.run_problem(p, 1)
+    import torch
+
+    x0 = torch.from_numpy(p.line).cuda().repeat(p.n_sheets)
+    v0 = torch.from_numpy(p.sheet_v).cuda().repeat_interleave(int(p.n_tracers[0]))
+    with B.Simulation(p, history_rows=8, x0=x0, v0=v0) as s:
+        s.step(1)
+        d = s.diagnostics()
+        xs = torch.empty(p.total_tracers, dtype=torch.float64, device="cuda")
+        vs = torch.empty_like(xs)
+        B.sic_get_state(s.h, p.total_tracers, xs, vs)
+    h = d["history"]
+    for n in range(2):
+        assert abs(h["W_E"][n] - ref["hist"][n, 2]) < 1e-10 * ref["hist"][n, 2]
+    idx = np.random.default_rng(2).choice(p.total_tracers, 4096, replace=False)
+    xs_h = xs.cpu().numpy()
+    assert np.max(periodic_diff(xs_h[idx], ref["x"][idx], p.L)) < 1e-12 * p.L
+    assert rel_inf(d["E"], ref["E"]) < 1e-10
