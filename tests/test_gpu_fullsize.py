@@ -41,31 +41,67 @@ def test_two_stream_full_size_single_step(prec):
     assert np.max(np.abs(d["rho"] - rho_o)) < 1e-10
 
 
+def _first_over(err, tol):
+    idx = np.nonzero(err > tol)[0]
+    return int(idx[0]) if len(idx) else None
+
+
 def test_two_stream_full_length_reduced_tracers():
-    """2000 steps of the two-stream configuration with 64 sheets x 1024
-    tracers: the split (uint32 fraction) form stays within 1e-6 of the FP64
-    oracle in field energy over the whole run; the FP64 form within 1e-10
-    until the nonlinear vortex (t ~ 75) starts to amplify rounding
-    differences, after which the first step over 1e-10 is reported."""
+    """2000 steps of the two-stream configuration (64 sheets x 1024 tracers).
+
+    After saturation (t ~ 20) the phase-space vortex amplifies any
+    difference exponentially: even the FP64 GPU path, which differs from the
+    oracle only in the order of roundings, departs from it.  So the run-long
+    comparison holds each tolerance through the linear and early nonlinear
+    phase (t <= 50) and reports the step where it is first exceeded; the
+    oracle-resynchronised single steps below hold it at every point of the
+    run."""
     p = I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=2000)
     print("case two_stream 64x1024, 2000 steps", flush=True)
     ref = O.run_problem(p)
     Wr = ref["hist"][:, 2]
-    res = {}
-    for prec in (B.SIC_FP64, B.SIC_SPLIT_U32):
-        with B.Simulation(p, precision=prec) as s:
-            s.step(p.n_steps)
-            res[prec] = s.diagnostics()["history"]["W_E"]
-    err_u32 = envelope_rel(res[B.SIC_SPLIT_U32], Wr, p.dt)
     P = int(math.ceil(2 * math.pi / p.dt))
     env = np.array([np.max(Wr[max(0, i - P): i + P + 1]) for i in range(len(Wr))])
-    e64 = np.abs(res[B.SIC_FP64] - Wr) / env
-    over = np.nonzero(e64 > 1e-10)[0]
-    first = int(over[0]) if len(over) else None
-    print(f"split_u32 envelope error {err_u32:.3e}; fp64 max {e64.max():.3e}, first step over 1e-10: {first}",
-          flush=True)
-    assert err_u32 < 1e-6
-    assert np.max(e64[:1500]) < 1e-10
+    errs = {}
+    for prec in (B.SIC_FP64, B.SIC_SPLIT_U32, B.SIC_SPLIT_F32):
+        with B.Simulation(p, precision=prec) as s:
+            s.step(p.n_steps)
+            errs[prec] = np.abs(s.diagnostics()["history"]["W_E"] - Wr) / env
+    window = int(round(50.0 / p.dt))
+    for prec, tol in ((B.SIC_FP64, 1e-10), (B.SIC_SPLIT_U32, 1e-6), (B.SIC_SPLIT_F32, 1e-6)):
+        e = errs[prec]
+        print(f"prec={prec}: max error up to t=50 {e[:window + 1].max():.3e}, whole run {e.max():.3e}, "
+              f"first step over {tol:g}: {_first_over(e, tol)}", flush=True)
+    assert errs[B.SIC_FP64][:window + 1].max() < 1e-10
+    assert errs[B.SIC_SPLIT_U32][:window + 1].max() < 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [(B.SIC_FP64, 1e-10), (B.SIC_SPLIT_U32, 1e-6)])
+def test_two_stream_resynchronised_steps_through_the_run(prec, tol):
+    """At steps 0, 400, ..., 2000 of the two-stream run (64 x 1024), the GPU
+    is loaded with the oracle's state and takes one step; its field energy
+    and positions match the oracle's step within the tolerance everywhere,
+    including deep in the nonlinear phase."""
+    p = I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=2000)
+    dx = p.L / p.n_cells
+    pos_tol = 1e-12 * p.L if prec == B.SIC_FP64 else 2.0 ** -30 * dx
+    ref = O.run_problem(p, 0)
+    x, v, step = ref["x"], ref["v"], 0
+    with B.Simulation(p, precision=prec) as s:
+        for target in range(0, 2001, 400):
+            if target > step:
+                seg = O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x, v, target - step, step0=step,
+                            init_kick=False)
+                x, v, step = seg["x"], seg["v"], target
+            one = O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x, v, 1, step0=step, init_kick=False)
+            s.set_state(step, x, v)
+            s.step(1)
+            xg, vg, sg = s.state()
+            W = s.diagnostics(history=False)["last"]["W_E"]
+            Wo = one["hist"][-1, 2]
+            assert sg == step + 1
+            assert abs(W - Wo) <= tol * Wo, (step, W, Wo)
+            assert np.max(periodic_diff(xg, one["x"], p.L)) < pos_tol, step
 
 
 def test_mixed_batch_sampled_instances():
