@@ -61,6 +61,11 @@ def lib():
         L.orc_gather_many.argtypes = [d, ctypes.c_int, P, i64, P, P]
         L.orc_push.restype = None
         L.orc_push.argtypes = [d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, P, P]
+        L.orc_deposit_linear.restype = None
+        L.orc_deposit_linear.argtypes = [d, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_run_order.restype = ctypes.c_int
+        L.orc_run_order.argtypes = [ctypes.c_int, d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, i64,
+                                    ctypes.c_int, i64, P, P, P, P, P]
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, i64, ctypes.c_int, i64,
                               P, P, P, P, P]
@@ -98,12 +103,14 @@ def deposit_segment(a: float, b: float, q: float, L: float, nc: int) -> np.ndarr
     return Q
 
 
-def deposit(L, nc, n_tracers, q, closed, x):
-    """Charge per cell Q_j (dx * density, mean not removed) and the longest segment."""
+def deposit(L, nc, n_tracers, q, closed, x, order=0):
+    """Charge per cell Q_j (dx * density, mean not removed) and the longest
+    segment; order 0: piecewise-constant segments, 1: piecewise-linear."""
     nt, qq, cl, xx = _i32(n_tracers), _f64(q), _i32(closed), _f64(x)
     Q = np.zeros(int(nc))
     ms = ctypes.c_double(0.0)
-    lib().orc_deposit(float(L), int(nc), len(nt), _p(nt), _p(qq), _p(cl), _p(xx), _p(Q), ctypes.byref(ms))
+    fn = lib().orc_deposit_linear if order == 1 else lib().orc_deposit
+    fn(float(L), int(nc), len(nt), _p(nt), _p(qq), _p(cl), _p(xx), _p(Q), ctypes.byref(ms))
     return Q, ms.value
 
 
@@ -135,7 +142,7 @@ def push(L, nc, dt, n_tracers, q, E, x, v):
     return xx, vv, ke.value, mom.value
 
 
-def run(L, nc, dt, n_tracers, q, closed, x0, v0, n_steps, step0=0, init_kick=True):
+def run(L, nc, dt, n_tracers, q, closed, x0, v0, n_steps, step0=0, init_kick=True, order=0):
     """Full run.  Returns dict(hist=[n_steps+1, 8], x, v (= v^{N-1/2}), Q, E)."""
     nt, qq, cl = _i32(n_tracers), _f64(q), _i32(closed)
     xx, vv = _f64(x0), _f64(v0)
@@ -145,16 +152,16 @@ def run(L, nc, dt, n_tracers, q, closed, x0, v0, n_steps, step0=0, init_kick=Tru
     hist = np.zeros((int(n_steps) + 1, ROW))
     xo, vo = np.zeros(n), np.zeros(n)
     Qo, Eo = np.zeros(int(nc)), np.zeros(int(nc))
-    rc = lib().orc_run(float(L), int(nc), float(dt), len(nt), _p(nt), _p(qq), _p(cl), _p(xx), _p(vv),
-                       int(step0), 1 if init_kick else 0, int(n_steps), _p(hist), _p(xo), _p(vo), _p(Qo),
-                       _p(Eo))
+    rc = lib().orc_run_order(int(order), float(L), int(nc), float(dt), len(nt), _p(nt), _p(qq), _p(cl), _p(xx),
+                             _p(vv), int(step0), 1 if init_kick else 0, int(n_steps), _p(hist), _p(xo), _p(vo),
+                             _p(Qo), _p(Eo))
     if rc != 0:
         raise MemoryError("oracle run failed")
     return dict(hist=hist, x=xo, v=vo, Q=Qo, E=Eo)
 
 
-def run_problem(problem, n_steps=None):
+def run_problem(problem, n_steps=None, order=0):
     """Run an ``inputs.Problem`` for ``n_steps`` (default: its own step count)."""
     steps = problem.n_steps if n_steps is None else n_steps
     return run(problem.L, problem.n_cells, problem.dt, problem.n_tracers, problem.q, problem.closed,
-               problem.x0, problem.v0, steps)
+               problem.x0, problem.v0, steps, order=order)

@@ -173,6 +173,81 @@ void orc_deposit(double L, int nc, int n_sheets, const int32_t *n_tracers, const
     if (max_segment) *max_segment = maxseg;
 }
 
+/* Piecewise-linear segments (section 2.5, eqs. "piecewise_linear" and
+ * "gradient_rho_estimate").  Segment i of a sheet carries the density
+ *     rho_i(x) = rho0_i + (x - c_i) g_i   on its extent,
+ * with rho0_i = q / |segment i| and c_i its centroid.  The gradient is the
+ * central difference of the neighbouring segments' rho0 over their centroid
+ * separation, g_i = (rho0_{i+1} - rho0_{i-1}) / (c_{i+1} - c_{i-1}), and is
+ * left out (g_i = 0) where the centroids c_{i-1}, c_i, c_{i+1} are not in
+ * monotone order (the corner of a fold), where a neighbouring segment is
+ * missing (ends of an open sheet) or where a segment of the three has zero
+ * length.  Centroid separations take the shorter way round the box.  Every
+ * cell receives the exact integral of rho_i over its overlap with the
+ * segment; the linear term integrates to zero over the segment, so each
+ * segment still deposits exactly q.  Segments are laid out in unwrapped
+ * coordinates [lo, hi] around their first tracer; a cell index outside
+ * 0..nc-1 is taken modulo nc. */
+void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                        const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    double dx = L / nc;
+    double maxseg = 0.0;
+    memset(Q, 0, sizeof(double) * (size_t)nc);
+    int64_t base = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        int nt = n_tracers[s];
+        int nseg = closed[s] ? nt : nt - 1;
+        double *a = (double *)malloc(sizeof(double) * (size_t)nseg);
+        double *d = (double *)malloc(sizeof(double) * (size_t)nseg);
+        double *c = (double *)malloc(sizeof(double) * (size_t)nseg);
+        double *r0 = (double *)malloc(sizeof(double) * (size_t)nseg);
+        for (int t = 0; t < nseg; ++t) {
+            int u = (t + 1 == nt) ? 0 : t + 1;
+            a[t] = x[base + t];
+            d[t] = orc_min_image(a[t], x[base + u], L);
+            c[t] = a[t] + 0.5 * d[t];
+            r0[t] = d[t] != 0.0 ? q[s] / fabs(d[t]) : 0.0;
+            if (fabs(d[t]) > maxseg) maxseg = fabs(d[t]);
+        }
+        for (int t = 0; t < nseg; ++t) {
+            if (d[t] == 0.0) {
+                Q[orc_point_cell(a[t], L, nc)] += q[s];
+                continue;
+            }
+            double g = 0.0;
+            int has_prev = closed[s] ? (nseg >= 3) : (t > 0);
+            int has_next = closed[s] ? (nseg >= 3) : (t + 1 < nseg);
+            if (has_prev && has_next) {
+                int tp = (t == 0) ? nseg - 1 : t - 1;
+                int tn = (t + 1 == nseg) ? 0 : t + 1;
+                if (d[tp] != 0.0 && d[tn] != 0.0) {
+                    double dm = orc_min_image(c[t], c[tp], L); /* c_{i-1} - c_i */
+                    double dp = orc_min_image(c[t], c[tn], L); /* c_{i+1} - c_i */
+                    if ((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))
+                        g = (r0[tn] - r0[tp]) / (dp - dm);
+                }
+            }
+            double lo = d[t] > 0.0 ? a[t] : a[t] + d[t];
+            double hi = d[t] > 0.0 ? a[t] + d[t] : a[t];
+            long j0 = (long)floor(lo / dx) - 1, j1 = (long)floor(hi / dx) + 1;
+            for (long j = j0; j <= j1; ++j) {
+                double fa = (double)j * dx, fb = (double)(j + 1) * dx;
+                double al = lo > fa ? lo : fa;
+                double be = hi < fb ? hi : fb;
+                if (be > al) {
+                    /* exact integral of r0 + (x - c) g over [al, be] */
+                    double w = be - al;
+                    Q[mod_cell(j, nc)] += r0[t] * w + g * w * (0.5 * (al + be) - c[t]);
+                }
+            }
+        }
+        free(a); free(d); free(c); free(r0);
+        base += nt;
+    }
+    if (max_segment) *max_segment = maxseg;
+}
+
 /* Solve the periodic 3-point Poisson equation
  *     (Phi_{j+1} - 2 Phi_j + Phi_{j-1}) / dx^2 = -rho_j,  rho_j = Q_j/dx - nbar,
  * and return the centred-difference field E_j = -(Phi_{j+1} - Phi_{j-1})/(2 dx)
@@ -302,9 +377,29 @@ static double row_flags(double L, int nc, const double *E, double maxseg)
  * hist holds (n_steps + 1) rows of ORC_ROW doubles; the KE and momentum of
  * the last row need the next push and are NaN.  Final positions, v^{N-1/2},
  * charge per cell and field are returned when the pointers are non-null. */
+int orc_run_order(int order, double L, int nc, double dt, int n_sheets, const int32_t *n_tracers,
+                  const double *q, const int32_t *closed, const double *x0, const double *v0, int64_t step0,
+                  int init_kick, int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out,
+                  double *E_out);
+
+static void deposit_order(int order, double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                          const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    if (order == 1) orc_deposit_linear(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
+    else orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
+}
+
 int orc_run(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
             const int32_t *closed, const double *x0, const double *v0, int64_t step0, int init_kick,
             int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out, double *E_out)
+{
+    return orc_run_order(0, L, nc, dt, n_sheets, n_tracers, q, closed, x0, v0, step0, init_kick, n_steps, hist,
+                         x_out, v_out, Q_out, E_out);
+}
+
+int orc_run_order(int order, double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
+                  const int32_t *closed, const double *x0, const double *v0, int64_t step0, int init_kick,
+                  int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out, double *E_out)
 {
     int64_t n = 0;
     for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
@@ -316,7 +411,7 @@ int orc_run(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers,
     for (int64_t i = 0; i < n; ++i) { x[i] = orc_wrap(x0[i], L); v[i] = v0[i]; }
 
     double W, qt, ms;
-    orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
+    deposit_order(order, L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
     orc_solve(L, nc, Q, E, &W, &qt);
     if (init_kick) {
         for (int64_t i = 0; i < n; ++i) v[i] = v[i] - 0.5 * dt * orc_gather(L, nc, E, x[i]);
@@ -329,7 +424,7 @@ int orc_run(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers,
         orc_push(L, nc, dt, n_sheets, n_tracers, q, E, x, v, &ke, &mom);
         hist[it * ORC_ROW + 3] = ke;
         hist[it * ORC_ROW + 4] = mom;
-        orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
+        deposit_order(order, L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
         orc_solve(L, nc, Q, E, &W, &qt);
         row = hist + (it + 1) * ORC_ROW;
         row[0] = (double)(step0 + it + 1); row[1] = (double)(step0 + it + 1) * dt; row[2] = W;

@@ -38,3 +38,54 @@ def exact_deposit(L, nc, sheets):
                 if right > left:
                     Q[j % nc] += q * (right - left) / length
     return Q
+
+
+def _min_image(d, L):
+    if d >= L / 2:
+        return d - L
+    if d < -L / 2:
+        return d + L
+    return d
+
+
+def exact_deposit_linear(L, nc, sheets):
+    """Piecewise-linear segments (section 2.5) in exact rational arithmetic:
+    segment i carries rho0_i + (x - c_i) g_i with rho0_i = q / length_i, c_i
+    its midpoint, and g_i the central difference of the neighbours' rho0 over
+    their centroid separation when the three centroids are in monotone order
+    (else 0); each cell gets the exact integral over its overlap."""
+    L = Fraction(L)
+    dx = L / nc
+    Q = [Fraction(0)] * nc
+    for q, closed, xs in sheets:
+        q = Fraction(q)
+        n = len(xs)
+        nseg = n if closed else n - 1
+        segs = []
+        for t in range(nseg):
+            a = Fraction(xs[t])
+            d = _min_image(Fraction(xs[(t + 1) % n]) - a, L)
+            segs.append((a, d, a + d / 2, (q / abs(d)) if d != 0 else None))
+        for t, (a, d, c, r0) in enumerate(segs):
+            if d == 0:
+                Q[(math.ceil(a / dx) - 1) % nc] += q
+                continue
+            g = Fraction(0)
+            has_prev = (nseg >= 3) if closed else t > 0
+            has_next = (nseg >= 3) if closed else t + 1 < nseg
+            if has_prev and has_next:
+                ap, dp_, cp, rp = segs[(t - 1) % nseg]
+                an, dn_, cn, rn = segs[(t + 1) % nseg]
+                if rp is not None and rn is not None:
+                    dm = _min_image(cp - c, L)
+                    dpp = _min_image(cn - c, L)
+                    if (dm < 0 < dpp) or (dpp < 0 < dm):
+                        g = (rn - rp) / (dpp - dm)
+            lo, hi = (a, a + d) if d > 0 else (a + d, a)
+            for j in range(math.floor(lo / dx) - 1, math.floor(hi / dx) + 2):
+                al = max(lo, j * dx)
+                be = min(hi, (j + 1) * dx)
+                if be > al:
+                    w = be - al
+                    Q[j % nc] += r0 * w + g * w * ((al + be) / 2 - c)
+    return Q
