@@ -81,7 +81,8 @@ typedef struct sic_config {
     double L;              /* box length, > 0 */
     double dt;             /* time step, > 0 */
     int32_t precision;     /* sic_precision */
-    int32_t deposit_order; /* 0: piecewise-constant segments (section 2.3); others SIC_ENOTSUP */
+    int32_t deposit_order; /* 0: piecewise-constant segments (section 2.3); 1: piecewise-linear
+                              segments with the fold-corner check (section 2.5); others SIC_ENOTSUP */
     int64_t history_rows;  /* capacity of the per-simulation diagnostics ring; 0: 65536 */
 } sic_config;
 
@@ -189,9 +190,11 @@ typedef struct sic_batch sic_batch;
 
 /* budget_tracers: maximum resident tracers over all slots; max_slots: maximum
  * resident simulations; max_cells: largest n_cells admitted (<= SIC_MAX_CELLS);
- * history_rows: diagnostics rows kept per slot (ring; 0: 4096).  Synchronous. */
+ * precision and deposit_order: shared by every admitted simulation (as in
+ * sic_config); history_rows: diagnostics rows kept per slot (ring; 0: 4096).
+ * Synchronous. */
 sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t max_cells, int32_t precision,
-                            int64_t history_rows, void *hip_stream, sic_batch **out);
+                            int32_t deposit_order, int64_t history_rows, void *hip_stream, sic_batch **out);
 
 /* Admits one simulation that will run n_steps steps (n_steps < 0: until
  * released).  Ingests it as sic_init does.  Returns SIC_EBUSY when no slot is

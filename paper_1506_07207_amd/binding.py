@@ -81,7 +81,7 @@ _SIGS = {
     "sic_get_tuning": (_I32, [_P, _P]),
     "sic_set_timing": (_I32, [_P, _I32]),
     "sic_last_timing": (_I32, [_P, _P, _P]),
-    "sic_batch_create": (_I32, [_I64, _I32, _I32, _I32, _I64, _P, _P]),
+    "sic_batch_create": (_I32, [_I64, _I32, _I32, _I32, _I32, _I64, _P, _P]),
     "sic_batch_admit": (_I32, [_P, _P, _P, _I32, _P, _P, _I32, _I64, _P]),
     "sic_batch_step": (_I32, [_P, _I64]),
     "sic_batch_poll": (_I32, [_P, _P, _I32, _P]),
@@ -319,21 +319,22 @@ def sic_copy_bandwidth(n_bytes: int, iters: int = 5, stream=None) -> float:
 
 # ------------------------------------------------------------------ batch
 
-def sic_batch_create(budget_tracers, max_slots, max_cells, precision=SIC_FP64, history_rows=0, stream=None):
+def sic_batch_create(budget_tracers, max_slots, max_cells, precision=SIC_FP64, history_rows=0, stream=None,
+                     deposit_order=0):
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     h = ctypes.c_void_p()
     rc = load().sic_batch_create(int(budget_tracers), int(max_slots), int(max_cells), int(precision),
-                                 int(history_rows), _stream_ptr(stream), ctypes.byref(h))
+                                 int(deposit_order), int(history_rows), _stream_ptr(stream), ctypes.byref(h))
     _check(rc, "sic_batch_create")
     return h
 
 
 def sic_batch_admit(b, L, n_cells, dt, n_tracers, q, closed, x0, v0, n_steps, precision=SIC_FP64,
-                    raise_busy=True):
+                    raise_busy=True, deposit_order=0):
     """Returns the slot, or None when the batch is full (SIC_EBUSY) and raise_busy is False."""
     lib = load()
-    cfg = make_config(L, n_cells, dt, precision)
+    cfg = make_config(L, n_cells, dt, precision, deposit_order=deposit_order)
     sheets = make_sheets(n_tracers, q, closed)
     px, kx, kx_ = _as_f64(x0)
     pv, kv, kv_ = _as_f64(v0)
@@ -452,12 +453,14 @@ def sic_batch_destroy(b):
 class Simulation:
     """Owns one sic_sim handle for an ``inputs.Problem``-like object."""
 
-    def __init__(self, problem, precision=SIC_FP64, history_rows=0, stream=None, x0=None, v0=None):
+    def __init__(self, problem, precision=SIC_FP64, history_rows=0, stream=None, x0=None, v0=None,
+                 deposit_order=0):
         self.problem = problem
         self.n = int(np.sum(problem.n_tracers, dtype=np.int64))
         self.h = sic_init(problem.L, problem.n_cells, problem.dt, problem.n_tracers, problem.q, problem.closed,
                           problem.x0 if x0 is None else x0, problem.v0 if v0 is None else v0,
-                          precision=precision, history_rows=history_rows, stream=stream)
+                          precision=precision, history_rows=history_rows, stream=stream,
+                          deposit_order=deposit_order)
 
     def step(self, n):
         sic_step(self.h, n)

@@ -105,6 +105,7 @@ struct SlotHost {
 
 struct Pool {
   int prec = 0;
+  int order = 0;  // deposit order: 0 piecewise-constant, 1 piecewise-linear segments
   bool batch = false;
   hipStream_t stream = nullptr;  // caller's stream
   hipStream_t cap = nullptr;     // private capture stream
@@ -117,6 +118,8 @@ struct Pool {
   uint64_t *xs = nullptr;
   double *vs = nullptr;
   double2 *halo[2] = {nullptr, nullptr};
+  double2 *halo3[2] = {nullptr, nullptr};  // order 1
+  int2 *links = nullptr;
   ChunkDesc *chunks = nullptr;
   Item *items = nullptr;
   int32_t *n_items = nullptr;
@@ -125,6 +128,7 @@ struct Pool {
   Partial *partials = nullptr;
   void *meshP = nullptr;
   void *meshD = nullptr;
+  void *meshR = nullptr;  // order 1
   double *meshE = nullptr;
   double *meshRho = nullptr;
   DiagRow *hist = nullptr;
@@ -203,19 +207,25 @@ void pool_free(Pool *p) {
   destroy_graphs(p);
   for (auto &s : p->slots)
     if (s.d_in_off) hipFree(s.d_in_off);
-  void *bufs[] = {p->xs,         p->vs,       p->halo[0], p->halo[1], p->chunks, p->items,  p->n_items,
-                  p->inst,       p->slot_items, p->partials, p->meshP, p->meshD,  p->meshE,  p->meshRho,
-                  p->hist,       p->done,     p->slot_ids};
+  void *bufs[] = {p->xs,       p->vs,       p->halo[0],    p->halo[1], p->halo3[0], p->halo3[1], p->links,
+                  p->chunks,   p->items,    p->n_items,    p->inst,    p->slot_items, p->partials, p->meshP,
+                  p->meshD,    p->meshR,    p->meshE,      p->meshRho, p->hist,     p->done,     p->slot_ids};
   for (void *b : bufs)
     if (b) hipFree(b);
   if (p->cap) hipStreamDestroy(p->cap);
   delete p;
 }
 
-sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells, int64_t chunk_cap,
+sic_status pool_create(int prec, int order, bool batch, int32_t slot_cap, int32_t max_cells, int64_t chunk_cap,
                        int64_t hist_rows, int64_t budget, void *stream, Pool **out, std::string *err) {
+  if (chunk_cap >= ((int64_t)1 << 29)) {  // chunk links pack a chunk index into 29 bits
+    if (err) *err = "tracer arena too large";
+    g_last_error = "tracer arena too large";
+    return SIC_ENOMEM;
+  }
   Pool *p = new Pool();
   p->prec = prec;
+  p->order = order;
   p->batch = batch;
   p->stream = (hipStream_t)stream;
   p->slot_cap = slot_cap;
@@ -224,7 +234,7 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   p->item_cap = chunk_cap / kMinTile + slot_cap + 1;
   p->hist_rows = hist_rows;
   p->budget = budget;
-  p->lds_bytes = tracer_lds_size(prec, max_cells, kMaxTile);
+  p->lds_bytes = tracer_lds_size(prec, order, max_cells, kMaxTile);
   p->slots.resize(slot_cap);
   p->slot_items_h.assign(slot_cap, make_int2(0, 0));
   p->alloc.init(chunk_cap);
@@ -245,6 +255,11 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   ALLOC(p->vs, slotsz);
   ALLOC(p->halo[0], (size_t)chunk_cap);
   ALLOC(p->halo[1], (size_t)chunk_cap);
+  ALLOC(p->links, (size_t)chunk_cap);
+  if (order == 1) {
+    ALLOC(p->halo3[0], 3 * (size_t)chunk_cap);
+    ALLOC(p->halo3[1], 3 * (size_t)chunk_cap);
+  }
   ALLOC(p->chunks, (size_t)chunk_cap);
   ALLOC(p->items, (size_t)p->item_cap);
   ALLOC(p->n_items, 1);
@@ -258,6 +273,11 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
     p->meshP = mp;
     ALLOC(md, mc);
     p->meshD = md;
+    if (order == 1) {
+      long long *mr = nullptr;
+      ALLOC(mr, mc);
+      p->meshR = mr;
+    }
     ALLOC(p->meshE, mc);
     ALLOC(p->meshRho, mc);
   }
@@ -271,6 +291,7 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   const size_t mc = (size_t)slot_cap * max_cells;
   e = hipMemsetAsync(p->meshP, 0, mc * 8, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->meshD, 0, mc * 8, p->stream);
+  if (e == hipSuccess && p->meshR) e = hipMemsetAsync(p->meshR, 0, mc * 8, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->meshE, 0, mc * 8, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->meshRho, 0, mc * 8, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->inst, 0, sizeof(InstDesc) * (size_t)slot_cap, p->stream);
@@ -286,7 +307,7 @@ sic_status pool_create(int prec, bool batch, int32_t slot_cap, int32_t max_cells
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return bail(std::string("init copy: ") + hipGetErrorString(e), SIC_EDEVICE);
   if (p->lds_bytes > 65536) {
-    int le = set_tracer_lds_limit(prec, p->lds_bytes);
+    int le = set_tracer_lds_limit(prec, order, p->lds_bytes);
     if (le != 0) return bail(std::string("LDS limit: ") + hipGetErrorString((hipError_t)le), SIC_ENOTSUP);
   }
   *out = p;
@@ -429,6 +450,9 @@ sic_status snapshot_take(Pool *p, Snapshot &s) {
       {p->vs, slots},
       {p->halo[0], (size_t)p->chunk_cap * sizeof(double2)},
       {p->halo[1], (size_t)p->chunk_cap * sizeof(double2)},
+      {p->halo3[0], p->halo3[0] ? 3 * (size_t)p->chunk_cap * sizeof(double2) : 0},
+      {p->halo3[1], p->halo3[1] ? 3 * (size_t)p->chunk_cap * sizeof(double2) : 0},
+      {p->meshR, p->meshR ? mc : 0},
       {p->meshP, mc},
       {p->meshD, mc},
       {p->meshE, mc},
@@ -439,6 +463,7 @@ sic_status snapshot_take(Pool *p, Snapshot &s) {
   };
   HIPCHK(p, hipStreamSynchronize(p->stream));
   for (auto &b : src) {
+    if (!b.first || b.second == 0) continue;
     void *d = nullptr;
     if (hipMalloc(&d, b.second) != hipSuccess) {
       snapshot_free(s);
@@ -530,15 +555,15 @@ TracerArgs tracer_args(Pool *p, int mode, int slot) {
   a.n_items = one ? &(p->slot_items + slot)->y : p->n_items;
   a.inst = p->inst;
   a.chunks = p->chunks;
+  a.links = p->links;
   a.xs = p->xs;
   a.vs = p->vs;
-  if (mode == (kPush | kDeposit)) {
-    a.halo_in = p->halo[p->parity];
-    a.halo_out = p->halo[p->parity ^ 1];
-  } else {
-    a.halo_in = p->halo[p->parity];
-    a.halo_out = p->halo[p->parity];
-  }
+  const int out_parity = (mode == (kPush | kDeposit)) ? p->parity ^ 1 : p->parity;
+  a.halo_in = p->halo[p->parity];
+  a.halo_out = p->halo[out_parity];
+  a.halo3_in = p->halo3[p->parity];
+  a.halo3_out = p->halo3[out_parity];
+  a.meshR = p->meshR;
   a.meshP = p->meshP;
   a.meshD = p->meshD;
   a.meshE = p->meshE;
@@ -557,6 +582,8 @@ SolveArgs solve_args(Pool *p, int flags, int slot) {
   a.partials = p->partials;
   a.meshP = p->meshP;
   a.meshD = p->meshD;
+  a.meshR = p->meshR;
+  a.order = p->order;
   a.meshE = p->meshE;
   a.meshRho = p->meshRho;
   a.hist = p->hist;
@@ -573,8 +600,8 @@ int grid_for(Pool *p, int slot) {
 
 sic_status launch_tracer_mode(Pool *p, int mode, int slot, hipStream_t st) {
   TracerArgs a = tracer_args(p, mode, slot);
-  const size_t lds = tracer_lds_size(p->prec, p->max_cells, p->tile);
-  LAUNCHCHK(p, launch_tracers(p->prec, mode, a, grid_for(p, slot), p->block, lds, st));
+  const size_t lds = tracer_lds_size(p->prec, p->order, p->max_cells, p->tile);
+  LAUNCHCHK(p, launch_tracers(p->prec, mode, p->order, a, grid_for(p, slot), p->block, lds, st));
   return SIC_OK;
 }
 
@@ -680,7 +707,8 @@ sic_status validate(Pool *p, const sic_config *cfg, const sic_sheet *sheets, int
   if (!(cfg->L > 0.0) || !finite(cfg->L)) return fail(p, SIC_EINVAL, "L must be positive and finite");
   if (!(cfg->dt > 0.0) || !finite(cfg->dt)) return fail(p, SIC_EINVAL, "dt must be positive and finite");
   if (cfg->precision < 0 || cfg->precision > 2) return fail(p, SIC_EINVAL, "unknown precision");
-  if (cfg->deposit_order != 0) return fail(p, SIC_ENOTSUP, "only deposit_order 0 is implemented");
+  if (cfg->deposit_order != 0 && cfg->deposit_order != 1)
+    return fail(p, SIC_ENOTSUP, "deposit_order must be 0 (constant) or 1 (linear segments)");
   if (cfg->history_rows < 0) return fail(p, SIC_EINVAL, "history_rows < 0");
   if (n_sheets < 1) return fail(p, SIC_EINVAL, "need at least one sheet");
   for (int32_t s = 0; s < n_sheets; ++s) {
@@ -703,6 +731,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   sic_status st = validate(p, cfg, sheets, n_sheets, x0, v0);
   if (st != SIC_OK) return st;
   if (cfg->precision != p->prec) return fail(p, SIC_EINVAL, "precision differs from the batch precision");
+  if (cfg->deposit_order != p->order) return fail(p, SIC_EINVAL, "deposit_order differs from the batch's");
   if (cfg->n_cells > p->max_cells) return fail(p, SIC_EINVAL, "n_cells above the batch max_cells");
   if (mem_kind != SIC_MEM_HOST && mem_kind != SIC_MEM_DEVICE) return fail(p, SIC_EINVAL, "bad mem_kind");
 
@@ -761,6 +790,35 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
       }
       c += nch;
       in += nt;
+    }
+  }
+  // Links to the tracer before each chunk and the one two past its end
+  // (piecewise-linear segments); a closed sheet of fewer than 3 tracers has
+  // no gradient, so it gets no links.
+  std::vector<int2> lk((size_t)n_ch, make_int2(-1, -1));
+  {
+    int64_t c = 0;
+    for (int32_t s = 0; s < n_sheets; ++s) {
+      const int32_t nt = sheets[s].n_tracers;
+      const int32_t nch = (nt + kChunk - 1) / kChunk;
+      const int32_t first = (int32_t)(cb + c);
+      const bool closed = sheets[s].closed != 0;
+      const bool grad = !closed || nt >= 3;
+      for (int32_t k = 0; k < nch && grad; ++k) {
+        int2 &L = lk[(size_t)(c + k)];
+        if (k > 0) L.x = ((first + k - 1) << 2) | kHaloLast;
+        else if (closed) L.x = ((first + nch - 1) << 2) | kHaloLast;
+        const int32_t P = cd[(size_t)(c + k)].partner;
+        if (P >= 0) {
+          const int32_t pk = P - first;
+          if (cd[(size_t)(c + pk)].n_valid >= 2) L.y = (P << 2) | kHaloSecond;
+          else {
+            const int32_t PP = cd[(size_t)(c + pk)].partner;
+            if (PP >= 0) L.y = (PP << 2) | kHaloFirst;
+          }
+        }
+      }
+      c += nch;
     }
   }
   sh.live = true;
@@ -836,6 +894,8 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   if (e == hipSuccess)
     e = hipMemcpyAsync(sh.d_in_off, sh.chunk_in_off.data(), sizeof(int64_t) * (size_t)n_ch, hipMemcpyHostToDevice,
                        p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->links + cb, lk.data(), sizeof(int2) * (size_t)n_ch, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(p->done + slot, &zero, sizeof(zero), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -858,8 +918,9 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   ia.xs = p->xs;
   ia.vs = p->vs;
   ia.halo = p->halo[p->parity];
+  ia.halo3 = p->halo3[p->parity];
   int le = launch_ingest(p->prec, ia, p->stream);
-  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->inst, p->slot_ids + slot, 1, p->stream);
+  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
   if (le != 0) {
     if (stage) hipFree(stage);
     return fail(p, SIC_EDEVICE, std::string("ingest: ") + hipGetErrorString((hipError_t)le));
@@ -1011,9 +1072,10 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
   ia.xs = p->xs;
   ia.vs = p->vs;
   ia.halo = p->halo[p->parity];
+  ia.halo3 = p->halo3[p->parity];
   int le = (e == hipSuccess) ? launch_ingest(p->prec, ia, p->stream) : 0;
   if (le == 0 && e == hipSuccess)
-    le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->inst, p->slot_ids + slot, 1, p->stream);
+    le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
   hipError_t e2 = hipStreamSynchronize(p->stream);
   if (stage) hipFree(stage);
   if (e != hipSuccess || e2 != hipSuccess || le != 0) return fail(p, SIC_EDEVICE, "set_state failed");
@@ -1026,7 +1088,7 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
 sic_status sim_deposit(Pool *p) {
   SlotHost &sh = p->slots[0];
   if (sh.state == kDeposited) {
-    LAUNCHCHK(p, launch_zero_mesh(p->prec, p->meshP, p->meshD, p->inst, p->slot_ids, 1, p->stream));
+    LAUNCHCHK(p, launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids, 1, p->stream));
   }
   sic_status st = launch_tracer_mode(p, kDeposit, -1, p->stream);
   if (st != SIC_OK) return st;
@@ -1114,7 +1176,7 @@ sic_status sic_init(const sic_config *cfg, const sic_sheet *sheets, int32_t n_sh
   const int64_t rows = cfg->history_rows > 0 ? std::max<int64_t>(2, cfg->history_rows) : 65536;
   Pool *p = nullptr;
   std::string err;
-  st = pool_create(cfg->precision, false, 1, cfg->n_cells, n_ch, rows, 0, hip_stream, &p, &err);
+  st = pool_create(cfg->precision, cfg->deposit_order, false, 1, cfg->n_cells, n_ch, rows, 0, hip_stream, &p, &err);
   if (st != SIC_OK) return st;
   int32_t slot = -1;
   st = pool_admit(p, cfg, sheets, n_sheets, x0, v0, mem_kind, -1, &slot);
@@ -1201,18 +1263,19 @@ sic_status sic_last_timing(const sic_sim *sim, double *tracer_ms, double *solve_
 
 // ---- batch ----
 sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t max_cells, int32_t precision,
-                            int64_t history_rows, void *hip_stream, sic_batch **out) {
+                            int32_t deposit_order, int64_t history_rows, void *hip_stream, sic_batch **out) {
   if (!out) return SIC_EINVAL;
   *out = nullptr;
   if (budget_tracers < 2 || max_slots < 1 || max_cells < 1 || max_cells > SIC_MAX_CELLS) return SIC_EINVAL;
   if (precision < 0 || precision > 2 || history_rows < 0) return SIC_EINVAL;
+  if (deposit_order != 0 && deposit_order != 1) return SIC_ENOTSUP;
   const int64_t rows = history_rows > 0 ? std::max<int64_t>(2, history_rows) : 4096;
   // arena: the budget plus the padding of partly filled last chunks
   const int64_t chunks = (budget_tracers + kChunk - 1) / kChunk + budget_tracers / 512 + 8 * (int64_t)max_slots;
   Pool *p = nullptr;
   std::string err;
-  sic_status st = pool_create(precision, true, max_slots, max_cells, chunks, rows, budget_tracers, hip_stream, &p,
-                              &err);
+  sic_status st = pool_create(precision, deposit_order, true, max_slots, max_cells, chunks, rows, budget_tracers,
+                              hip_stream, &p, &err);
   if (st != SIC_OK) return st;
   st = upload_item_count(p);
   if (st != SIC_OK) {

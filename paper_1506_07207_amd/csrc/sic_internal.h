@@ -84,11 +84,22 @@ struct alignas(64) DiagRow {
   int64_t flags;
 };
 
+// Links from a chunk to single tracers of other chunks (piecewise-linear
+// segments need two tracers past a chunk's end and one before its start):
+// (chunk << 2) | which, which = 0 first, 1 second, 2 last tracer of that
+// chunk; -1 when there is no such tracer (ends of an open sheet, or a closed
+// sheet too short to have a gradient).
+enum HaloWhich : int { kHaloFirst = 0, kHaloSecond = 1, kHaloLast = 2 };
+
 struct TracerArgs {
   const Item *items;
   const int32_t *n_items;  // device-side item count
   const InstDesc *inst;
   const ChunkDesc *chunks;
+  const int2 *links;       // per chunk (prev link, next-but-one link); order 1
+  const double2 *halo3_in; // per chunk: first, second, last tracer; order 1
+  double2 *halo3_out;
+  void *meshR;             // second-difference array for linear ramps; order 1
   uint64_t *xs;            // word 0 per slot
   double *vs;              // word 1 per slot
   const double2 *halo_in;  // (x word as bits, v) per chunk
@@ -109,12 +120,14 @@ struct SolveArgs {
   const Partial *partials;
   void *meshP;
   void *meshD;
+  void *meshR;               // order 1 only
   double *meshE;
   double *meshRho;           // n_j - nbar of the newest solve
   DiagRow *hist;
   int32_t *done;             // per slot: set to 1 when a batch run finishes
   int32_t flags;
   int32_t respect_active;
+  int32_t order;             // deposit order of the pool (0 or 1)
 };
 
 struct IngestArgs {
@@ -128,6 +141,7 @@ struct IngestArgs {
   uint64_t *xs;
   double *vs;
   double2 *halo;
+  double2 *halo3;  // order 1 (NULL otherwise)
 };
 
 struct ExtractArgs {
@@ -143,15 +157,15 @@ struct ExtractArgs {
 };
 
 // Launchers (sic_kernels.hip).  All return hipError_t as int.
-int launch_tracers(int prec, int mode, const TracerArgs &a, int grid, int block, size_t lds_bytes,
+int launch_tracers(int prec, int mode, int order, const TracerArgs &a, int grid, int block, size_t lds_bytes,
                    void *stream);
-int set_tracer_lds_limit(int prec, size_t lds_bytes);
-size_t tracer_lds_size(int prec, int mesh_cells, int tile_cap);
+int set_tracer_lds_limit(int prec, int order, size_t lds_bytes);
+size_t tracer_lds_size(int prec, int order, int mesh_cells, int tile_cap);
 int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream);
 int launch_ingest(int prec, const IngestArgs &a, void *stream);
 int launch_extract(int prec, const ExtractArgs &a, void *stream);
-int launch_zero_mesh(int prec, void *meshP, void *meshD, const InstDesc *inst, const int32_t *slot_list,
-                     int n_blocks, void *stream);
+int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
+                     const int32_t *slot_list, int n_blocks, void *stream);
 int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream);
 
 }  // namespace sic

@@ -244,6 +244,137 @@ __device__ __forceinline__ double deposit_split(uint64_t wa, uint64_t wb, long l
   return ad;
 }
 
+// ---- piecewise-linear segments (section 2.5) ----
+//
+// Segment i (tracer i to tracer i+1) carries rho(u) = rho0 + (u - c) g in mesh
+// units, rho0 = q / length, c its centroid, g the central difference of the
+// neighbouring segments' rho0 over their centroid separation, or 0 at a fold
+// corner (centroids not monotone), at an open sheet's end, or when any of the
+// three segments has zero length.  Each end cell gets the integral over its
+// overlap; the fully covered cells l..h get rho0 + g (j + 1/2 - c), a linear
+// ramp A + B (j - l) added through the difference arrays D (constant part)
+// and R (second difference of the ramp), so a segment still costs O(1).
+
+// Ramp A + B (j - l) on cells l..h of one period (0 <= l <= h < nc).
+template <class T>
+__device__ __forceinline__ void add_ramp_nowrap(T *sD, T *sR, int l, int h, T A, T B, int nc) {
+  lds_add(sD + l, A);
+  if (h + 1 < nc) lds_add(sD + h + 1, (T)(0 - (A + B * (T)(h - l))));
+  if (l + 1 <= h) {  // the slope needs a run of two cells or more
+    lds_add(sR + l + 1, B);
+    if (h + 1 < nc) lds_add(sR + h + 1, (T)(0 - B));
+  }
+}
+
+// Ramp on unwrapped cells lo..hi (0 <= hi - lo < nc).
+template <class T>
+__device__ __forceinline__ void add_ramp(T *sD, T *sR, int lo, int hi, T A, T B, int nc) {
+  const int l = wrap_cell(lo, nc);
+  const int h = l + min(hi - lo, nc - 1);
+  if (h < nc) {
+    add_ramp_nowrap(sD, sR, l, h, A, B, nc);
+  } else {
+    add_ramp_nowrap(sD, sR, l, nc - 1, A, B, nc);
+    add_ramp_nowrap(sD, sR, 0, h - nc, (T)(A + B * (T)(nc - l)), B, nc);
+  }
+}
+
+__device__ __forceinline__ double min_image_cells(double d, double half_nc, double nc) {
+  if (d >= half_nc) d -= nc;
+  else if (d < -half_nc) d += nc;
+  return d;
+}
+
+// Geometry of the segment from mesh position ua to ub (minimum image):
+// start, signed length and centroid in mesh units.
+struct SegGeo {
+  double u, d, c;
+};
+
+__device__ __forceinline__ SegGeo seg_geo_mesh(double ua, double ub, double half_nc, double nc) {
+  SegGeo s;
+  s.u = ua;
+  s.d = min_image_cells(ub - ua, half_nc, nc);
+  s.c = ua + 0.5 * s.d;
+  return s;
+}
+
+// Gradient of segment i from its neighbours (qd: segment charge in the
+// accumulator's units).
+__device__ __forceinline__ double linear_gradient(const SegGeo &m, const SegGeo &i, const SegGeo &p, bool have_m,
+                                                  bool have_p, double qd, double half_nc, double nc) {
+  if (!(have_m && have_p) || m.d == 0.0 || p.d == 0.0) return 0.0;
+  const double dm = min_image_cells(m.c - i.c, half_nc, nc);
+  const double dp = min_image_cells(p.c - i.c, half_nc, nc);
+  if (!((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))) return 0.0;
+  return (qd / fabs(p.d) - qd / fabs(m.d)) / (dp - dm);
+}
+
+// FP64: deposit segment i given its geometry and gradient (mesh units).
+__device__ __forceinline__ void deposit_linear_fp64(double a_phys, const SegGeo &sg, double g, double q,
+                                                    const Geo &geo, double *sP, double *sD, double *sR) {
+  if (sg.d == 0.0) {
+    const int c = wrap_cell((int)ceil(a_phys / geo.dx) - 1, geo.nc);
+    lds_add(sP + c, q);
+    return;
+  }
+  const double u0 = sg.d > 0.0 ? sg.u : sg.u + sg.d;
+  const double u1 = sg.d > 0.0 ? sg.u + sg.d : sg.u;
+  const double len = u1 - u0;
+  const double f0 = floor(u0);
+  const int c0 = (int)f0;
+  const int c1 = (int)ceil(u1) - 1;
+  if (!(len > 0.0) || c1 <= c0) {
+    lds_add(sP + wrap_cell(c0, geo.nc), q);
+    return;
+  }
+  const double r0 = q / len;
+  const double e0 = f0 + 1.0;
+  const double w0 = e0 - u0;
+  const double w1 = u1 - (double)c1;
+  lds_add(sP + wrap_cell(c0, geo.nc), w0 * (r0 + g * (0.5 * (u0 + e0) - sg.c)));
+  lds_add(sP + wrap_cell(c1, geo.nc), w1 * (r0 + g * (0.5 * ((double)c1 + u1) - sg.c)));
+  if (c1 - c0 >= 2) {
+    const double A = r0 + g * ((double)(c0 + 1) + 0.5 - sg.c);
+    add_ramp(sD, sR, c0 + 1, c1 - 1, A, g, geo.nc);
+  }
+}
+
+// Split form: fixed-point pieces, the last end cell takes the remainder so
+// the segment deposits exactly q_fix.
+__device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, const SegGeo &sg, double g,
+                                                     long long qf, const Geo &geo, unsigned long long *sP,
+                                                     unsigned long long *sD, unsigned long long *sR) {
+  if (sg.d == 0.0) {
+    const int c = wrap_cell(frac_a == 0.0 ? cell_a - 1 : cell_a, geo.nc);
+    lds_add(sP + c, (unsigned long long)qf);
+    return;
+  }
+  const double u0 = sg.d > 0.0 ? sg.u : sg.u + sg.d;
+  const double u1 = sg.d > 0.0 ? sg.u + sg.d : sg.u;
+  const double len = u1 - u0;
+  const double f0 = floor(u0);
+  const int c0 = (int)f0;
+  const int c1 = (int)ceil(u1) - 1;
+  if (!(len > 0.0) || c1 <= c0) {
+    lds_add(sP + wrap_cell(c0, geo.nc), (unsigned long long)qf);
+    return;
+  }
+  const double r0 = (double)qf / len;
+  const double e0 = f0 + 1.0;
+  const long long p0 = llrint((e0 - u0) * (r0 + g * (0.5 * (u0 + e0) - sg.c)));
+  long long p1 = qf - p0;
+  if (c1 - c0 >= 2) {
+    const long long n = c1 - c0 - 1;
+    const long long A = llrint(r0 + g * ((double)(c0 + 1) + 0.5 - sg.c));
+    const long long B = llrint(g);
+    add_ramp(sD, sR, c0 + 1, c1 - 1, (unsigned long long)A, (unsigned long long)B, geo.nc);
+    p1 -= n * A + B * (n * (n - 1) / 2);
+  }
+  lds_add(sP + wrap_cell(c0, geo.nc), (unsigned long long)p0);
+  lds_add(sP + wrap_cell(c1, geo.nc), (unsigned long long)p1);
+}
+
 __device__ __forceinline__ double nan_max(double a, double b) {
   // max that propagates NaN (a non-finite segment must reach the flags)
   return (b > a || b != b) ? b : a;
@@ -266,25 +397,32 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------
 // Tracer kernel
 // ---------------------------------------------------------------------------
-// Per-item LDS layout (bytes): P, D accumulators and the field E for
-// mesh_cells cells; the item's chunk descriptors and the halo copies of their
-// partner chunks for tile_cap chunks; 48 doubles for the block reduction.
-template <class Acc>
+// Per-item LDS layout (bytes): P, D (and for linear segments R) accumulators
+// and the field E for mesh_cells cells; for tile_cap chunks the item's chunk
+// descriptors and the halo copies of the tracers next to each chunk (one for
+// constant segments; three, plus the links, for linear ones); 48 doubles for
+// the block reduction.
+template <class Acc, int ORDER>
 __host__ __device__ constexpr size_t tracer_lds_bytes(int mesh_cells, int tile_cap) {
-  return 2 * (size_t)mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
-         (size_t)tile_cap * (sizeof(ChunkDesc) + sizeof(double2)) + 48 * sizeof(double);
+  return (size_t)(2 + ORDER) * mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
+         (size_t)tile_cap * (sizeof(ChunkDesc) + (ORDER ? 3 : 1) * sizeof(double2) + (ORDER ? sizeof(int2) : 0)) +
+         48 * sizeof(double);
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, int ORDER>
 __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   acc_t *sP = reinterpret_cast<acc_t *>(smem);
   acc_t *sD = sP + a.mesh_cells;
-  double *sE = reinterpret_cast<double *>(sD + a.mesh_cells);
+  acc_t *sR = sD + a.mesh_cells;  // order 1 only
+  double *sE = reinterpret_cast<double *>(sR + (ORDER ? a.mesh_cells : 0));
   ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sE + a.mesh_cells);
-  double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);
-  double *sRed = reinterpret_cast<double *>(sHalo + a.tile_cap);  // 3 x 16 waves
+  double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);  // order 0: next tracer; order 1: next
+  double2 *sHalo2 = sHalo + a.tile_cap;                               // order 1: next but one
+  double2 *sHaloP = sHalo2 + a.tile_cap;                              // order 1: previous
+  int2 *sLinks = reinterpret_cast<int2 *>(sHalo + (ORDER ? 3 : 1) * a.tile_cap);
+  double *sRed = reinterpret_cast<double *>(sLinks + (ORDER ? a.tile_cap : 0));  // 3 x 16 waves
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -317,15 +455,26 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       if constexpr (kDep) {
         sP[i] = (acc_t)0;
         sD[i] = (acc_t)0;
+        if constexpr (ORDER) sR[i] = (acc_t)0;
       }
       if constexpr (kField) sE[i] = a.meshE[I.mesh_off + i];
     }
-    for (int i = tid; i < nch; i += blockDim.x) sDesc[i] = a.chunks[cb + i];
+    for (int i = tid; i < nch; i += blockDim.x) {
+      sDesc[i] = a.chunks[cb + i];
+      if constexpr (ORDER && kDep) sLinks[i] = a.links[cb + i];
+    }
     __syncthreads();
     if constexpr (kDep) {
       for (int i = tid; i < nch; i += blockDim.x) {
         const int pc = sDesc[i].partner;
-        if (pc >= 0) sHalo[i] = a.halo_in[pc];
+        if constexpr (ORDER) {
+          const int2 lk = sLinks[i];
+          if (pc >= 0) sHalo[i] = a.halo3_in[3 * pc + kHaloFirst];
+          if (lk.y >= 0) sHalo2[i] = a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)];
+          if (lk.x >= 0) sHaloP[i] = a.halo3_in[3 * (lk.x >> 2) + (lk.x & 3)];
+        } else {
+          if (pc >= 0) sHalo[i] = a.halo_in[pc];
+        }
       }
       __syncthreads();
     }
@@ -366,9 +515,76 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           a.xs[s] = xw;
           a.vs[s] = v;
         }
-        if (lane == 0) a.halo_out[cb + kk] = make_double2(__longlong_as_double((long long)xw), v);
+        const double2 hv2 = make_double2(__longlong_as_double((long long)xw), v);
+        if constexpr (ORDER) {
+          const size_t hb = 3 * (size_t)(cb + kk);
+          if (lane == 0) a.halo3_out[hb + kHaloFirst] = hv2;
+          if (lane == 1) a.halo3_out[hb + kHaloSecond] = hv2;
+          if (lane == n_valid - 1) a.halo3_out[hb + kHaloLast] = hv2;
+        } else {
+          if (lane == 0) a.halo_out[cb + kk] = hv2;
+        }
       }
-      if constexpr (kDep) {
+      if constexpr (kDep && ORDER) {
+        // Tracers i-1, i+1, i+2 of segment i: lane shuffles inside the chunk,
+        // halo copies (moved from their pre-step state when this kernel also
+        // moves) past its ends.
+        const int2 lk = sLinks[kk];
+        auto moved = [&](const double2 h) -> uint64_t {
+          uint64_t w = (uint64_t)__double_as_longlong(h.x);
+          if constexpr (kMove) {
+            const double e = gather_field(sE, mesh_pos<PREC>(w, g.inv_dx), g.nc);
+            w = drift<PREC>(w, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
+          }
+          return w;
+        };
+        const bool have_n1 = ch.partner >= 0, have_n2 = lk.y >= 0, have_pv = lk.x >= 0;
+        const uint64_t hn1 = have_n1 ? moved(sHalo[kk]) : 0ull;
+        const uint64_t hn2 = have_n2 ? moved(sHalo2[kk]) : 0ull;
+        const uint64_t hpv = have_pv ? moved(sHaloP[kk]) : 0ull;
+        const uint64_t up1 = (uint64_t)__shfl_up((long long)xw, 1, 64);
+        const uint64_t dn1 = (uint64_t)__shfl_down((long long)xw, 1, 64);
+        const uint64_t dn2 = (uint64_t)__shfl_down((long long)xw, 2, 64);
+        const uint64_t xm1 = lane > 0 ? up1 : hpv;
+        const bool has_m1 = lane > 0 || have_pv;
+        const uint64_t xp1 = lane < n_valid - 1 ? dn1 : hn1;
+        const bool has_p1 = lane < n_valid - 1 || have_n1;
+        const uint64_t xp2 = lane < n_valid - 2 ? dn2 : (lane == n_valid - 2 ? hn1 : hn2);
+        const bool has_p2 = lane < n_valid - 2 || (lane == n_valid - 2 ? have_n1 : have_n2);
+        if (valid && has_p1) {
+          const double half_nc = 0.5 * (double)g.nc, ncd = (double)g.nc;
+          const double um1 = mesh_pos<PREC>(xm1, g.inv_dx);
+          const double u0 = mesh_pos<PREC>(xw, g.inv_dx);
+          const double up1d = mesh_pos<PREC>(xp1, g.inv_dx);
+          const double up2 = mesh_pos<PREC>(xp2, g.inv_dx);
+          SegGeo sg = seg_geo_mesh(u0, up1d, half_nc, ncd);
+          if constexpr (PREC == kFP64) {
+            // the segment itself takes the physical minimum image, as the
+            // constant scheme does
+            const double xa = __longlong_as_double((long long)xw);
+            double d = __longlong_as_double((long long)xp1) - xa;
+            if (d >= g.half_L) d -= g.L;
+            else if (d < -g.half_L) d += g.L;
+            sg.d = d * g.inv_dx;
+            sg.c = sg.u + 0.5 * sg.d;
+          }
+          const SegGeo sm = seg_geo_mesh(um1, u0, half_nc, ncd);
+          const SegGeo sp = seg_geo_mesh(up1d, up2, half_nc, ncd);
+          const double qd = PREC == kFP64 ? ch.q : (double)ch.q_fix;
+          const double grad = linear_gradient(sm, sg, sp, has_m1, has_p2, qd, half_nc, ncd);
+          const double len = fabs(sg.d) * g.dx;
+          if (len <= g.half_L) {
+            if constexpr (PREC == kFP64) {
+              deposit_linear_fp64(__longlong_as_double((long long)xw), sg, grad, ch.q, g, sP, sD, sR);
+            } else {
+              deposit_linear_split(split_cell(xw), split_frac<PREC>(split_bits(xw)), sg, grad, ch.q_fix, g, sP,
+                                   sD, sR);
+            }
+          }
+          ms = nan_max(ms, len);
+        }
+      }
+      if constexpr (kDep && !ORDER) {
         uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
         const bool tail = (lane == n_valid - 1);
         bool has_seg = valid;
@@ -454,15 +670,26 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           if constexpr (PREC == kFP64) unsafeAtomicAdd(gD + i, d);
           else atomicAdd(gD + i, d);
         }
+        if constexpr (ORDER) {
+          acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + I.mesh_off;
+          const acc_t r = sR[i];
+          if (r != (acc_t)0) {
+            if constexpr (PREC == kFP64) unsafeAtomicAdd(gR + i, r);
+            else atomicAdd(gR + i, r);
+          }
+        }
       }
     }
     __syncthreads();
   }
 }
 
-size_t tracer_lds_size(int prec, int mesh_cells, int tile_cap) {
-  return prec == kFP64 ? tracer_lds_bytes<double>(mesh_cells, tile_cap)
-                       : tracer_lds_bytes<unsigned long long>(mesh_cells, tile_cap);
+size_t tracer_lds_size(int prec, int order, int mesh_cells, int tile_cap) {
+  if (order)
+    return prec == kFP64 ? tracer_lds_bytes<double, 1>(mesh_cells, tile_cap)
+                         : tracer_lds_bytes<unsigned long long, 1>(mesh_cells, tile_cap);
+  return prec == kFP64 ? tracer_lds_bytes<double, 0>(mesh_cells, tile_cap)
+                       : tracer_lds_bytes<unsigned long long, 0>(mesh_cells, tile_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,9 +794,44 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
     }
     dsum += dv[k];
   }
-  acc_t dbase;
-  if constexpr (PREC == kFP64) dbase = block_incl_scan(dsum, sWd) - dsum;
-  else dbase = block_incl_scan(dsum, sWi) - dsum;
+  auto scan = [&](acc_t v) -> acc_t {
+    if constexpr (PREC == kFP64) return block_incl_scan(v, sWd);
+    else return block_incl_scan(v, sWi);
+  };
+  const acc_t dbase = scan(dsum) - dsum;
+  // Linear ramps of piecewise-linear segments: the charge adds the second
+  // prefix sum of R (zero for piecewise-constant segments).
+  acc_t r2[kMaxCellsPerThread];
+#pragma unroll
+  for (int k = 0; k < kMaxCellsPerThread; ++k) r2[k] = (acc_t)0;
+  if (a.order) {
+    acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + Ip->mesh_off;
+    acc_t rsum = (acc_t)0;
+#pragma unroll
+    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+      const int j = j0 + k;
+      if (k < per && j < nc) {
+        r2[k] = gR[j];
+        gR[j] = (acc_t)0;
+      }
+      rsum += r2[k];
+    }
+    const acc_t base1 = scan(rsum) - rsum;
+    acc_t run1 = base1, s1sum = (acc_t)0;
+#pragma unroll
+    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+      run1 += r2[k];
+      r2[k] = run1;
+      if ((k < per) && (j0 + k < nc)) s1sum += run1;
+    }
+    const acc_t base2 = scan(s1sum) - s1sum;
+    acc_t run2 = base2;
+#pragma unroll
+    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+      if ((k < per) && (j0 + k < nc)) run2 += r2[k];
+      r2[k] = run2;
+    }
+  }
   double Q[kMaxCellsPerThread];
   acc_t qsum_acc = (acc_t)0;
   {
@@ -577,7 +839,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
 #pragma unroll
     for (int k = 0; k < kMaxCellsPerThread; ++k) {
       run += dv[k];
-      const acc_t qa = pv[k] + run;
+      const acc_t qa = pv[k] + run + r2[k];
       const bool in = (k < per) && (j0 + k < nc);
       if constexpr (PREC == kFP64) Q[k] = in ? qa : 0.0;
       else Q[k] = in ? (double)qa * q_unit : 0.0;
@@ -713,7 +975,13 @@ __global__ void __launch_bounds__(256) k_ingest(IngestArgs a) {
   }
   a.xs[s] = w;
   a.vs[s] = v;
-  if (lane == 0) a.halo[c] = make_double2(__longlong_as_double((long long)w), v);
+  const double2 hv = make_double2(__longlong_as_double((long long)w), v);
+  if (lane == 0) a.halo[c] = hv;
+  if (a.halo3) {
+    if (lane == 0) a.halo3[3 * (size_t)c + kHaloFirst] = hv;
+    if (lane == 1) a.halo3[3 * (size_t)c + kHaloSecond] = hv;
+    if (lane == ch.n_valid - 1) a.halo3[3 * (size_t)c + kHaloLast] = hv;
+  }
 }
 
 template <int PREC>
@@ -739,16 +1007,18 @@ __global__ void __launch_bounds__(256) k_extract(ExtractArgs a) {
 }
 
 template <int PREC>
-__global__ void __launch_bounds__(256) k_zero_mesh(void *meshP, void *meshD, const InstDesc *inst,
+__global__ void __launch_bounds__(256) k_zero_mesh(void *meshP, void *meshD, void *meshR, const InstDesc *inst,
                                                    const int32_t *slot_list) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
   const int slot = slot_list ? slot_list[blockIdx.x] : (int)blockIdx.x;
   const InstDesc &I = inst[slot];
   acc_t *P = reinterpret_cast<acc_t *>(meshP) + I.mesh_off;
   acc_t *D = reinterpret_cast<acc_t *>(meshD) + I.mesh_off;
+  acc_t *R = meshR ? reinterpret_cast<acc_t *>(meshR) + I.mesh_off : nullptr;
   for (int j = threadIdx.x; j < I.n_cells; j += blockDim.x) {
     P[j] = (acc_t)0;
     D[j] = (acc_t)0;
+    if (R) R[j] = (acc_t)0;
   }
 }
 
@@ -760,20 +1030,20 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, d
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, int ORDER>
 static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
   switch (mode) {
     case kDeposit:
-      hipLaunchKernelGGL((k_tracers<PREC, kDeposit>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kDeposit, ORDER>), dim3(grid), dim3(block), lds, st, a);
       break;
     case kPush:
-      hipLaunchKernelGGL((k_tracers<PREC, kPush>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kPush, ORDER>), dim3(grid), dim3(block), lds, st, a);
       break;
     case kPush | kDeposit:
-      hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit, ORDER>), dim3(grid), dim3(block), lds, st, a);
       break;
     case kKickHalf:
-      hipLaunchKernelGGL((k_tracers<PREC, kKickHalf>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kKickHalf, ORDER>), dim3(grid), dim3(block), lds, st, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -781,40 +1051,52 @@ static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int bloc
   return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, int ORDER>
 static hipError_t set_lds_limit(size_t bytes) {
-  hipError_t e = hipSuccess;
   const int b = (int)bytes;
-  e = hipFuncSetAttribute((const void *)k_tracers<PREC, kDeposit>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_tracers<PREC, kPush>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_tracers<PREC, kPush | kDeposit>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_tracers<PREC, kKickHalf>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             b);
+  const void *fns[] = {(const void *)k_tracers<PREC, kDeposit, ORDER>, (const void *)k_tracers<PREC, kPush, ORDER>,
+                       (const void *)k_tracers<PREC, kPush | kDeposit, ORDER>,
+                       (const void *)k_tracers<PREC, kKickHalf, ORDER>};
+  for (const void *f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // The limit is a property of the kernel function, shared by every pool in
 // the process, so it only ever grows.
-int set_tracer_lds_limit(int prec, size_t lds) {
-  static size_t granted[3] = {65536, 65536, 65536};
-  if (prec < 0 || prec > 2) return (int)hipErrorInvalidValue;
-  if (lds <= granted[prec]) return 0;
-  hipError_t e = prec == kFP64 ? set_lds_limit<kFP64>(lds)
-                               : (prec == kSplitF32 ? set_lds_limit<kSplitF32>(lds) : set_lds_limit<kSplitU32>(lds));
-  if (e == hipSuccess) granted[prec] = lds;
+int set_tracer_lds_limit(int prec, int order, size_t lds) {
+  static size_t granted[3][2] = {{65536, 65536}, {65536, 65536}, {65536, 65536}};
+  if (prec < 0 || prec > 2 || order < 0 || order > 1) return (int)hipErrorInvalidValue;
+  if (lds <= granted[prec][order]) return 0;
+  hipError_t e;
+  if (order == 0)
+    e = prec == kFP64 ? set_lds_limit<kFP64, 0>(lds)
+                      : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 0>(lds) : set_lds_limit<kSplitU32, 0>(lds));
+  else
+    e = prec == kFP64 ? set_lds_limit<kFP64, 1>(lds)
+                      : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 1>(lds) : set_lds_limit<kSplitU32, 1>(lds));
+  if (e == hipSuccess) granted[prec][order] = lds;
   return (int)e;
 }
 
-int launch_tracers(int prec, int mode, const TracerArgs &a, int grid, int block, size_t lds, void *stream) {
+int launch_tracers(int prec, int mode, int order, const TracerArgs &a, int grid, int block, size_t lds,
+                   void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (grid <= 0) return 0;
-  switch (prec) {
-    case kFP64: return (int)tracers_prec<kFP64>(mode, a, grid, block, lds, st);
-    case kSplitF32: return (int)tracers_prec<kSplitF32>(mode, a, grid, block, lds, st);
-    case kSplitU32: return (int)tracers_prec<kSplitU32>(mode, a, grid, block, lds, st);
+  if (order == 0) {
+    switch (prec) {
+      case kFP64: return (int)tracers_prec<kFP64, 0>(mode, a, grid, block, lds, st);
+      case kSplitF32: return (int)tracers_prec<kSplitF32, 0>(mode, a, grid, block, lds, st);
+      case kSplitU32: return (int)tracers_prec<kSplitU32, 0>(mode, a, grid, block, lds, st);
+    }
+  } else if (order == 1) {
+    switch (prec) {
+      case kFP64: return (int)tracers_prec<kFP64, 1>(mode, a, grid, block, lds, st);
+      case kSplitF32: return (int)tracers_prec<kSplitF32, 1>(mode, a, grid, block, lds, st);
+      case kSplitU32: return (int)tracers_prec<kSplitU32, 1>(mode, a, grid, block, lds, st);
+    }
   }
   return (int)hipErrorInvalidValue;
 }
@@ -857,14 +1139,15 @@ int launch_extract(int prec, const ExtractArgs &a, void *stream) {
   return (int)hipGetLastError();
 }
 
-int launch_zero_mesh(int prec, void *meshP, void *meshD, const InstDesc *inst, const int32_t *slot_list,
-                     int n_blocks, void *stream) {
+int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
+                     const int32_t *slot_list, int n_blocks, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n_blocks <= 0) return 0;
   if (prec == kFP64)
-    hipLaunchKernelGGL(k_zero_mesh<kFP64>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, inst, slot_list);
+    hipLaunchKernelGGL(k_zero_mesh<kFP64>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, meshR, inst, slot_list);
   else
-    hipLaunchKernelGGL(k_zero_mesh<kSplitF32>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, inst, slot_list);
+    hipLaunchKernelGGL(k_zero_mesh<kSplitF32>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, meshR, inst,
+                       slot_list);
   return (int)hipGetLastError();
 }
 
