@@ -63,6 +63,8 @@ def lib():
         L.orc_push.argtypes = [d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, P, P]
         L.orc_deposit_linear.restype = None
         L.orc_deposit_linear.argtypes = [d, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_deposit_cic.restype = None
+        L.orc_deposit_cic.argtypes = [d, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
         L.orc_run_order.restype = ctypes.c_int
         L.orc_run_order.argtypes = [ctypes.c_int, d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, i64,
                                     ctypes.c_int, i64, P, P, P, P, P]
@@ -105,11 +107,12 @@ def deposit_segment(a: float, b: float, q: float, L: float, nc: int) -> np.ndarr
 
 def deposit(L, nc, n_tracers, q, closed, x, order=0):
     """Charge per cell Q_j (dx * density, mean not removed) and the longest
-    segment; order 0: piecewise-constant segments, 1: piecewise-linear."""
+    segment; order 0: piecewise-constant segments, 1: piecewise-linear,
+    2: first-order (W_1) weighting of constant segments."""
     nt, qq, cl, xx = _i32(n_tracers), _f64(q), _i32(closed), _f64(x)
     Q = np.zeros(int(nc))
     ms = ctypes.c_double(0.0)
-    fn = lib().orc_deposit_linear if order == 1 else lib().orc_deposit
+    fn = {0: lib().orc_deposit, 1: lib().orc_deposit_linear, 2: lib().orc_deposit_cic}[order]
     fn(float(L), int(nc), len(nt), _p(nt), _p(qq), _p(cl), _p(xx), _p(Q), ctypes.byref(ms))
     return Q, ms.value
 

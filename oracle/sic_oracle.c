@@ -248,6 +248,65 @@ void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers
     if (max_segment) *max_segment = maxseg;
 }
 
+/* First-order weighting of segments (section 2.4): every slice of a
+ * segment's box function is assigned to the grid points X_j = (j + 1/2) dx
+ * with the first-order weight W_1(x - X_j) = max(0, 1 - |x - X_j| / dx), so
+ * grid point j receives h * integral over the segment of W_1(x - X_j) dx,
+ * h = q / length.  The hat is linear between its kinks X_j - dx, X_j,
+ * X_j + dx, so the integral is taken piece by piece with the trapezoid rule,
+ * which is exact for linear integrands.  A zero-length segment is a point
+ * charge: W_1 weights of the point.  The result is the charge per grid point
+ * (dx * density), as for the other deposits. */
+static double hat(double x, double X, double dx)
+{
+    double w = 1.0 - fabs(x - X) / dx;
+    return w > 0.0 ? w : 0.0;
+}
+
+void orc_deposit_cic(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                     const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    double dx = L / nc;
+    double maxseg = 0.0;
+    memset(Q, 0, sizeof(double) * (size_t)nc);
+    int64_t base = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        int nt = n_tracers[s];
+        int nseg = closed[s] ? nt : nt - 1;
+        for (int t = 0; t < nseg; ++t) {
+            int u = (t + 1 == nt) ? 0 : t + 1;
+            double a = x[base + t];
+            double d = orc_min_image(a, x[base + u], L);
+            if (fabs(d) > maxseg) maxseg = fabs(d);
+            if (d == 0.0) {
+                long j0 = (long)floor(a / dx - 0.5);
+                for (long j = j0; j <= j0 + 1; ++j)
+                    Q[mod_cell(j, nc)] += q[s] * hat(a, ((double)j + 0.5) * dx, dx);
+                continue;
+            }
+            double lo = d > 0.0 ? a : a + d, hi = d > 0.0 ? a + d : a;
+            double h = q[s] / (hi - lo);
+            long j0 = (long)floor(lo / dx - 0.5) - 1, j1 = (long)floor(hi / dx - 0.5) + 2;
+            for (long j = j0; j <= j1; ++j) {
+                double X = ((double)j + 0.5) * dx;
+                double knots[5] = {lo, X - dx, X, X + dx, hi};
+                double acc = 0.0;
+                /* pieces between consecutive kinks that lie inside [lo, hi] */
+                double prev = lo;
+                for (int k = 1; k < 5; ++k) {
+                    double nxt = knots[k];
+                    if (k < 4 && (nxt <= lo || nxt >= hi)) continue;
+                    if (nxt > prev) acc += 0.5 * (hat(prev, X, dx) + hat(nxt, X, dx)) * (nxt - prev);
+                    prev = nxt;
+                }
+                if (acc > 0.0) Q[mod_cell(j, nc)] += h * acc;
+            }
+        }
+        base += nt;
+    }
+    if (max_segment) *max_segment = maxseg;
+}
+
 /* Solve the periodic 3-point Poisson equation
  *     (Phi_{j+1} - 2 Phi_j + Phi_{j-1}) / dx^2 = -rho_j,  rho_j = Q_j/dx - nbar,
  * and return the centred-difference field E_j = -(Phi_{j+1} - Phi_{j-1})/(2 dx)
@@ -386,6 +445,7 @@ static void deposit_order(int order, double L, int nc, int n_sheets, const int32
                           const int32_t *closed, const double *x, double *Q, double *max_segment)
 {
     if (order == 1) orc_deposit_linear(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
+    else if (order == 2) orc_deposit_cic(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
     else orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
 }
 

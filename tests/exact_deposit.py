@@ -89,3 +89,43 @@ def exact_deposit_linear(L, nc, sheets):
                     w = be - al
                     Q[j % nc] += r0 * w + g * w * ((al + be) / 2 - c)
     return Q
+
+
+def _hat_antiderivative(t):
+    """Integral of max(0, 1 - |s|) from -infinity to t."""
+    if t <= -1:
+        return Fraction(0)
+    if t <= 0:
+        return (1 + t) ** 2 / 2
+    if t <= 1:
+        return 1 - (1 - t) ** 2 / 2
+    return Fraction(1)
+
+
+def exact_deposit_cic(L, nc, sheets):
+    """First-order weighting of segments (section 2.4) in exact arithmetic,
+    through the antiderivative of the hat: grid point j (at (j + 1/2) dx)
+    gets h dx [H((hi - X_j)/dx) - H((lo - X_j)/dx)], h = q / length; a
+    zero-length segment gives its point the hat weights."""
+    L = Fraction(L)
+    dx = L / nc
+    Q = [Fraction(0)] * nc
+    for q, closed, xs in sheets:
+        q = Fraction(q)
+        n = len(xs)
+        nseg = n if closed else n - 1
+        for t in range(nseg):
+            a = Fraction(xs[t])
+            d = _min_image(Fraction(xs[(t + 1) % n]) - a, L)
+            if d == 0:
+                for j in range(math.floor(a / dx) - 2, math.floor(a / dx) + 3):
+                    w = 1 - abs(a - (j + Fraction(1, 2)) * dx) / dx
+                    if w > 0:
+                        Q[j % nc] += q * w
+                continue
+            lo, hi = (a, a + d) if d > 0 else (a + d, a)
+            h = q / (hi - lo)
+            for j in range(math.floor(lo / dx) - 2, math.floor(hi / dx) + 3):
+                X = (j + Fraction(1, 2)) * dx
+                Q[j % nc] += h * dx * (_hat_antiderivative((hi - X) / dx) - _hat_antiderivative((lo - X) / dx))
+    return Q
