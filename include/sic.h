@@ -82,7 +82,9 @@ typedef struct sic_config {
     double dt;             /* time step, > 0 */
     int32_t precision;     /* sic_precision */
     int32_t deposit_order; /* 0: piecewise-constant segments (section 2.3); 1: piecewise-linear
-                              segments with the fold-corner check (section 2.5); others SIC_ENOTSUP */
+                              segments with the fold-corner check (section 2.5); 2: first-order
+                              (W_1) weighting of constant segments to the grid points (section
+                              2.4); others SIC_ENOTSUP */
     int64_t history_rows;  /* capacity of the per-simulation diagnostics ring; 0: 65536 */
 } sic_config;
 

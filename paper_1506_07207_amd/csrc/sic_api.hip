@@ -707,8 +707,8 @@ sic_status validate(Pool *p, const sic_config *cfg, const sic_sheet *sheets, int
   if (!(cfg->L > 0.0) || !finite(cfg->L)) return fail(p, SIC_EINVAL, "L must be positive and finite");
   if (!(cfg->dt > 0.0) || !finite(cfg->dt)) return fail(p, SIC_EINVAL, "dt must be positive and finite");
   if (cfg->precision < 0 || cfg->precision > 2) return fail(p, SIC_EINVAL, "unknown precision");
-  if (cfg->deposit_order != 0 && cfg->deposit_order != 1)
-    return fail(p, SIC_ENOTSUP, "deposit_order must be 0 (constant) or 1 (linear segments)");
+  if (cfg->deposit_order < 0 || cfg->deposit_order > 2)
+    return fail(p, SIC_ENOTSUP, "deposit_order must be 0 (constant), 1 (linear segments) or 2 (first-order weighting)");
   if (cfg->history_rows < 0) return fail(p, SIC_EINVAL, "history_rows < 0");
   if (n_sheets < 1) return fail(p, SIC_EINVAL, "need at least one sheet");
   for (int32_t s = 0; s < n_sheets; ++s) {
@@ -1268,7 +1268,7 @@ sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t m
   *out = nullptr;
   if (budget_tracers < 2 || max_slots < 1 || max_cells < 1 || max_cells > SIC_MAX_CELLS) return SIC_EINVAL;
   if (precision < 0 || precision > 2 || history_rows < 0) return SIC_EINVAL;
-  if (deposit_order != 0 && deposit_order != 1) return SIC_ENOTSUP;
+  if (deposit_order < 0 || deposit_order > 2) return SIC_ENOTSUP;
   const int64_t rows = history_rows > 0 ? std::max<int64_t>(2, history_rows) : 4096;
   // arena: the budget plus the padding of partly filled last chunks
   const int64_t chunks = (budget_tracers + kChunk - 1) / kChunk + budget_tracers / 512 + 8 * (int64_t)max_slots;

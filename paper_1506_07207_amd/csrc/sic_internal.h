@@ -127,7 +127,7 @@ struct SolveArgs {
   int32_t *done;             // per slot: set to 1 when a batch run finishes
   int32_t flags;
   int32_t respect_active;
-  int32_t order;             // deposit order of the pool (0 or 1)
+  int32_t order;             // deposit order of the pool (0, 1 or 2); R exists only for 1
 };
 
 struct IngestArgs {

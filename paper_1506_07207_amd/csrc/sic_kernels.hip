@@ -375,6 +375,111 @@ __device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, 
   lds_add(sP + wrap_cell(c1, geo.nc), (unsigned long long)p1);
 }
 
+// ---- first-order weighting of segments (section 2.4) ----
+//
+// Every slice of the box is assigned to the grid points (cell centres) with
+// the hat W_1.  With s = u - 1/2 (grid point j at s = j) and r the charge per
+// mesh unit, grid point j receives r [H(s1 - j) - H(s0 - j)], H the
+// antiderivative of the unit hat.  Hats fully inside the segment
+// (j in [ceil(s0) + 1, floor(s1) - 1]) receive r through the difference
+// array; the remaining contributions are on grid points floor(s0),
+// floor(s0) + 1, floor(s1), floor(s1) + 1.
+
+__device__ __forceinline__ double hat_antiderivative(double t) {
+  if (t <= -1.0) return 0.0;
+  if (t <= 0.0) return 0.5 * (1.0 + t) * (1.0 + t);
+  if (t <= 1.0) return 1.0 - 0.5 * (1.0 - t) * (1.0 - t);
+  return 1.0;
+}
+
+// Visits the partial grid points j of a segment [s0, s1] (s1 > s0) in
+// order, calling f(j, integral of the hat of j over the segment); returns the
+// run of fully covered hats in [full_lo, full_hi].
+template <class F>
+__device__ __forceinline__ void cic_partials(double s0, double s1, int &full_lo, int &full_hi, F f) {
+  const int f0 = (int)floor(s0);
+  const int f1 = (int)floor(s1);
+  full_lo = (int)ceil(s0) + 1;
+  full_hi = f1 - 1;
+  const int cand[4] = {f0, f0 + 1, f1, f1 + 1};
+  int last = f0 - 1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int j = cand[k];
+    if (j <= last) continue;  // duplicate
+    last = j;
+    if (j >= full_lo && j <= full_hi) continue;  // a fully covered hat
+    f(j, hat_antiderivative(s1 - (double)j) - hat_antiderivative(s0 - (double)j));
+  }
+}
+
+__device__ __forceinline__ void deposit_cic_fp64(double u_a, double d_mesh, double q, const Geo &g, double *sP,
+                                                 double *sD) {
+  if (d_mesh == 0.0) {  // a point: its hat weights
+    const double s = u_a - 0.5;
+    const double f = floor(s);
+    const double w = s - f;
+    lds_add(sP + wrap_cell((int)f, g.nc), q * (1.0 - w));
+    lds_add(sP + wrap_cell((int)f + 1, g.nc), q * w);
+    return;
+  }
+  const double s0 = (d_mesh > 0.0 ? u_a : u_a + d_mesh) - 0.5;
+  const double s1 = (d_mesh > 0.0 ? u_a + d_mesh : u_a) - 0.5;
+  if (!(s1 > s0)) {
+    const double f = floor(s0);
+    const double w = s0 - f;
+    lds_add(sP + wrap_cell((int)f, g.nc), q * (1.0 - w));
+    lds_add(sP + wrap_cell((int)f + 1, g.nc), q * w);
+    return;
+  }
+  const double r = q / (s1 - s0);
+  int lo, hi;
+  cic_partials(s0, s1, lo, hi, [&](int j, double h) { lds_add(sP + wrap_cell(j, g.nc), r * h); });
+  if (hi >= lo) add_run(sD, lo, hi, r, g.nc);
+}
+
+__device__ __forceinline__ void deposit_cic_split(double u_a, double d_mesh, long long qf, const Geo &g,
+                                                  unsigned long long *sP, unsigned long long *sD) {
+  const double qd = (double)qf;
+  if (d_mesh == 0.0) {
+    const double s = u_a - 0.5;
+    const double f = floor(s);
+    const long long p1 = llrint(qd * (s - f));
+    lds_add(sP + wrap_cell((int)f, g.nc), (unsigned long long)(qf - p1));
+    lds_add(sP + wrap_cell((int)f + 1, g.nc), (unsigned long long)p1);
+    return;
+  }
+  const double s0 = (d_mesh > 0.0 ? u_a : u_a + d_mesh) - 0.5;
+  const double s1 = (d_mesh > 0.0 ? u_a + d_mesh : u_a) - 0.5;
+  if (!(s1 > s0)) {
+    const double f = floor(s0);
+    const long long p1 = llrint(qd * (s0 - f));
+    lds_add(sP + wrap_cell((int)f, g.nc), (unsigned long long)(qf - p1));
+    lds_add(sP + wrap_cell((int)f + 1, g.nc), (unsigned long long)p1);
+    return;
+  }
+  const double r = qd / (s1 - s0);
+  int lo, hi;
+  long long rest = qf;
+  int last_j = 0;
+  long long last_p = 0;
+  bool have = false;
+  cic_partials(s0, s1, lo, hi, [&](int j, double h) {
+    if (have) lds_add(sP + wrap_cell(last_j, g.nc), (unsigned long long)last_p);
+    last_j = j;
+    last_p = llrint(r * h);
+    rest -= last_p;
+    have = true;
+  });
+  if (hi >= lo) {
+    const long long G = llrint(r);
+    add_run(sD, lo, hi, (unsigned long long)G, g.nc);
+    rest -= (long long)(hi - lo + 1) * G;
+  }
+  // the last partial grid point takes the remainder: exactly qf in total
+  lds_add(sP + wrap_cell(last_j, g.nc), (unsigned long long)(last_p + rest));
+}
+
 __device__ __forceinline__ double nan_max(double a, double b) {
   // max that propagates NaN (a non-finite segment must reach the flags)
   return (b > a || b != b) ? b : a;
@@ -402,10 +507,14 @@ __device__ __forceinline__ double wave_max(double v) {
 // descriptors and the halo copies of the tracers next to each chunk (one for
 // constant segments; three, plus the links, for linear ones); 48 doubles for
 // the block reduction.
+// ORDER: 0 piecewise-constant segments, 1 piecewise-linear segments (ramp
+// array R and three halo copies per chunk), 2 first-order weighting of
+// constant segments.
 template <class Acc, int ORDER>
 __host__ __device__ constexpr size_t tracer_lds_bytes(int mesh_cells, int tile_cap) {
-  return (size_t)(2 + ORDER) * mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
-         (size_t)tile_cap * (sizeof(ChunkDesc) + (ORDER ? 3 : 1) * sizeof(double2) + (ORDER ? sizeof(int2) : 0)) +
+  return (size_t)(2 + (ORDER == 1)) * mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
+         (size_t)tile_cap *
+             (sizeof(ChunkDesc) + (ORDER == 1 ? 3 : 1) * sizeof(double2) + (ORDER == 1 ? sizeof(int2) : 0)) +
          48 * sizeof(double);
 }
 
@@ -415,14 +524,15 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   acc_t *sP = reinterpret_cast<acc_t *>(smem);
   acc_t *sD = sP + a.mesh_cells;
-  acc_t *sR = sD + a.mesh_cells;  // order 1 only
-  double *sE = reinterpret_cast<double *>(sR + (ORDER ? a.mesh_cells : 0));
+  constexpr bool kLin = ORDER == 1;
+  acc_t *sR = sD + a.mesh_cells;  // linear segments only
+  double *sE = reinterpret_cast<double *>(sR + (kLin ? a.mesh_cells : 0));
   ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sE + a.mesh_cells);
   double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);  // order 0: next tracer; order 1: next
   double2 *sHalo2 = sHalo + a.tile_cap;                               // order 1: next but one
   double2 *sHaloP = sHalo2 + a.tile_cap;                              // order 1: previous
-  int2 *sLinks = reinterpret_cast<int2 *>(sHalo + (ORDER ? 3 : 1) * a.tile_cap);
-  double *sRed = reinterpret_cast<double *>(sLinks + (ORDER ? a.tile_cap : 0));  // 3 x 16 waves
+  int2 *sLinks = reinterpret_cast<int2 *>(sHalo + (kLin ? 3 : 1) * a.tile_cap);
+  double *sRed = reinterpret_cast<double *>(sLinks + (kLin ? a.tile_cap : 0));  // 3 x 16 waves
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -455,19 +565,19 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       if constexpr (kDep) {
         sP[i] = (acc_t)0;
         sD[i] = (acc_t)0;
-        if constexpr (ORDER) sR[i] = (acc_t)0;
+        if constexpr (kLin) sR[i] = (acc_t)0;
       }
       if constexpr (kField) sE[i] = a.meshE[I.mesh_off + i];
     }
     for (int i = tid; i < nch; i += blockDim.x) {
       sDesc[i] = a.chunks[cb + i];
-      if constexpr (ORDER && kDep) sLinks[i] = a.links[cb + i];
+      if constexpr (kLin && kDep) sLinks[i] = a.links[cb + i];
     }
     __syncthreads();
     if constexpr (kDep) {
       for (int i = tid; i < nch; i += blockDim.x) {
         const int pc = sDesc[i].partner;
-        if constexpr (ORDER) {
+        if constexpr (kLin) {
           const int2 lk = sLinks[i];
           if (pc >= 0) sHalo[i] = a.halo3_in[3 * pc + kHaloFirst];
           if (lk.y >= 0) sHalo2[i] = a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)];
@@ -516,7 +626,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           a.vs[s] = v;
         }
         const double2 hv2 = make_double2(__longlong_as_double((long long)xw), v);
-        if constexpr (ORDER) {
+        if constexpr (kLin) {
           const size_t hb = 3 * (size_t)(cb + kk);
           if (lane == 0) a.halo3_out[hb + kHaloFirst] = hv2;
           if (lane == 1) a.halo3_out[hb + kHaloSecond] = hv2;
@@ -525,7 +635,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           if (lane == 0) a.halo_out[cb + kk] = hv2;
         }
       }
-      if constexpr (kDep && ORDER) {
+      if constexpr (kDep && kLin) {
         // Tracers i-1, i+1, i+2 of segment i: lane shuffles inside the chunk,
         // halo copies (moved from their pre-step state when this kernel also
         // moves) past its ends.
@@ -584,7 +694,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           ms = nan_max(ms, len);
         }
       }
-      if constexpr (kDep && !ORDER) {
+      if constexpr (kDep && !kLin) {
         uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
         const bool tail = (lane == n_valid - 1);
         bool has_seg = valid;
@@ -604,7 +714,27 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         }
         if (has_seg) {
           double len;
-          if constexpr (PREC == kFP64) {
+          if constexpr (ORDER == 2) {
+            // first-order weighting: geometry in mesh units, minimum image as
+            // for the constant scheme
+            double ua, dm;
+            if constexpr (PREC == kFP64) {
+              const double xa = __longlong_as_double((long long)xw);
+              double d = __longlong_as_double((long long)pw) - xa;
+              if (d >= g.half_L) d -= g.L;
+              else if (d < -g.half_L) d += g.L;
+              ua = xa * g.inv_dx;
+              dm = d * g.inv_dx;
+            } else {
+              ua = mesh_pos<PREC>(xw, g.inv_dx);
+              dm = min_image_cells(mesh_pos<PREC>(pw, g.inv_dx) - ua, 0.5 * (double)g.nc, (double)g.nc);
+            }
+            len = fabs(dm) * g.dx;
+            if (len <= g.half_L) {
+              if constexpr (PREC == kFP64) deposit_cic_fp64(ua, dm, ch.q, g, sP, sD);
+              else deposit_cic_split(ua, dm, ch.q_fix, g, sP, sD);
+            }
+          } else if constexpr (PREC == kFP64) {
             len = deposit_fp64(__longlong_as_double((long long)xw), __longlong_as_double((long long)pw), ch.q, g,
                                sP, sD);
           } else {
@@ -670,7 +800,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           if constexpr (PREC == kFP64) unsafeAtomicAdd(gD + i, d);
           else atomicAdd(gD + i, d);
         }
-        if constexpr (ORDER) {
+        if constexpr (kLin) {
           acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + I.mesh_off;
           const acc_t r = sR[i];
           if (r != (acc_t)0) {
@@ -685,7 +815,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
 }
 
 size_t tracer_lds_size(int prec, int order, int mesh_cells, int tile_cap) {
-  if (order)
+  if (order == 1)
     return prec == kFP64 ? tracer_lds_bytes<double, 1>(mesh_cells, tile_cap)
                          : tracer_lds_bytes<unsigned long long, 1>(mesh_cells, tile_cap);
   return prec == kFP64 ? tracer_lds_bytes<double, 0>(mesh_cells, tile_cap)
@@ -804,7 +934,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   acc_t r2[kMaxCellsPerThread];
 #pragma unroll
   for (int k = 0; k < kMaxCellsPerThread; ++k) r2[k] = (acc_t)0;
-  if (a.order) {
+  if (a.order == 1 && a.meshR != nullptr) {  // only piecewise-linear segments have ramps
     acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + Ip->mesh_off;
     acc_t rsum = (acc_t)0;
 #pragma unroll
@@ -1067,16 +1197,19 @@ static hipError_t set_lds_limit(size_t bytes) {
 // The limit is a property of the kernel function, shared by every pool in
 // the process, so it only ever grows.
 int set_tracer_lds_limit(int prec, int order, size_t lds) {
-  static size_t granted[3][2] = {{65536, 65536}, {65536, 65536}, {65536, 65536}};
-  if (prec < 0 || prec > 2 || order < 0 || order > 1) return (int)hipErrorInvalidValue;
+  static size_t granted[3][3] = {{65536, 65536, 65536}, {65536, 65536, 65536}, {65536, 65536, 65536}};
+  if (prec < 0 || prec > 2 || order < 0 || order > 2) return (int)hipErrorInvalidValue;
   if (lds <= granted[prec][order]) return 0;
   hipError_t e;
   if (order == 0)
     e = prec == kFP64 ? set_lds_limit<kFP64, 0>(lds)
                       : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 0>(lds) : set_lds_limit<kSplitU32, 0>(lds));
-  else
+  else if (order == 1)
     e = prec == kFP64 ? set_lds_limit<kFP64, 1>(lds)
                       : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 1>(lds) : set_lds_limit<kSplitU32, 1>(lds));
+  else
+    e = prec == kFP64 ? set_lds_limit<kFP64, 2>(lds)
+                      : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 2>(lds) : set_lds_limit<kSplitU32, 2>(lds));
   if (e == hipSuccess) granted[prec][order] = lds;
   return (int)e;
 }
@@ -1096,6 +1229,12 @@ int launch_tracers(int prec, int mode, int order, const TracerArgs &a, int grid,
       case kFP64: return (int)tracers_prec<kFP64, 1>(mode, a, grid, block, lds, st);
       case kSplitF32: return (int)tracers_prec<kSplitF32, 1>(mode, a, grid, block, lds, st);
       case kSplitU32: return (int)tracers_prec<kSplitU32, 1>(mode, a, grid, block, lds, st);
+    }
+  } else if (order == 2) {
+    switch (prec) {
+      case kFP64: return (int)tracers_prec<kFP64, 2>(mode, a, grid, block, lds, st);
+      case kSplitF32: return (int)tracers_prec<kSplitF32, 2>(mode, a, grid, block, lds, st);
+      case kSplitU32: return (int)tracers_prec<kSplitU32, 2>(mode, a, grid, block, lds, st);
     }
   }
   return (int)hipErrorInvalidValue;

@@ -60,12 +60,12 @@ def test_invalid_arguments_are_rejected_before_any_device_work(lib):
     assert _init_status(n_tracers=[1], x0=np.zeros(1), v0=np.zeros(1)) == 1
     assert _init_status(q=[float("nan")]) == 1
     assert _init_status(precision=7) == 1
-    assert _init_status(deposit_order=2) == 6
+    assert _init_status(deposit_order=3) == 6
     h = ctypes.c_void_p()
     assert lib.sic_init(None, None, 0, None, None, 0, None, ctypes.byref(h)) == 1
     assert lib.sic_batch_create(0, 1, 8, 0, 0, 0, None, ctypes.byref(h)) == 1
     assert lib.sic_batch_create(100, 1, B.SIC_MAX_CELLS + 1, 0, 0, 0, None, ctypes.byref(h)) == 1
-    assert lib.sic_batch_create(100, 1, 8, 0, 2, 0, None, ctypes.byref(h)) == 6
+    assert lib.sic_batch_create(100, 1, 8, 0, 3, 0, None, ctypes.byref(h)) == 6
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
