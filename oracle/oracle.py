@@ -60,11 +60,21 @@ def lib():
         L.orc_gather_many.restype = None
         L.orc_gather_many.argtypes = [d, ctypes.c_int, P, i64, P, P]
         L.orc_push.restype = None
-        L.orc_push.argtypes = [d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, P, P]
+        L.orc_push.argtypes = [d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, P, P, P]
+        L.orc_push_c.restype = None
+        L.orc_push_c.argtypes = [d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, P, P, P]
         L.orc_deposit_linear.restype = None
         L.orc_deposit_linear.argtypes = [d, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
         L.orc_deposit_cic.restype = None
         L.orc_deposit_cic.argtypes = [d, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        for name in ("orc_deposit_c", "orc_deposit_linear_c", "orc_deposit_cic_c"):
+            getattr(L, name).restype = None
+            getattr(L, name).argtypes = [d, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_refine.restype = i64
+        L.orc_refine.argtypes = [d, d, ctypes.c_int, P, P, P, P, P, i64]
+        L.orc_run_seg.restype = ctypes.c_int
+        L.orc_run_seg.argtypes = [ctypes.c_int, d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, i64, ctypes.c_int,
+                                  i64, d, i64, P, P, P, P, P, P]
         L.orc_run_order.restype = ctypes.c_int
         L.orc_run_order.argtypes = [ctypes.c_int, d, ctypes.c_int, d, ctypes.c_int, P, P, P, P, P, i64,
                                     ctypes.c_int, i64, P, P, P, P, P]
@@ -105,16 +115,47 @@ def deposit_segment(a: float, b: float, q: float, L: float, nc: int) -> np.ndarr
     return Q
 
 
-def deposit(L, nc, n_tracers, q, closed, x, order=0):
+def uniform_charges(n_tracers, q, closed):
+    """Per-segment charges of sheets whose segments all carry the sheet's
+    charge: entry t belongs to the segment that starts at tracer t; the last
+    tracer of an open sheet starts no segment and gets 0."""
+    nt, cl = _i32(n_tracers), _i32(closed)
+    c = np.repeat(_f64(q), nt)
+    ends = np.cumsum(nt) - 1
+    c[ends[cl == 0]] = 0.0
+    return c
+
+
+def deposit(L, nc, n_tracers, q, closed, x, order=0, c=None):
     """Charge per cell Q_j (dx * density, mean not removed) and the longest
     segment; order 0: piecewise-constant segments, 1: piecewise-linear,
-    2: first-order (W_1) weighting of constant segments."""
+    2: first-order (W_1) weighting of constant segments.  ``c`` (per-segment
+    charges, one per tracer) replaces the per-sheet ``q`` when given."""
     nt, qq, cl, xx = _i32(n_tracers), _f64(q), _i32(closed), _f64(x)
     Q = np.zeros(int(nc))
     ms = ctypes.c_double(0.0)
-    fn = {0: lib().orc_deposit, 1: lib().orc_deposit_linear, 2: lib().orc_deposit_cic}[order]
-    fn(float(L), int(nc), len(nt), _p(nt), _p(qq), _p(cl), _p(xx), _p(Q), ctypes.byref(ms))
+    if c is None:
+        fn = {0: lib().orc_deposit, 1: lib().orc_deposit_linear, 2: lib().orc_deposit_cic}[order]
+        fn(float(L), int(nc), len(nt), _p(nt), _p(qq), _p(cl), _p(xx), _p(Q), ctypes.byref(ms))
+    else:
+        cc = _f64(c)
+        fn = {0: lib().orc_deposit_c, 1: lib().orc_deposit_linear_c, 2: lib().orc_deposit_cic_c}[order]
+        fn(float(L), int(nc), len(nt), _p(nt), _p(cl), _p(cc), _p(xx), _p(Q), ctypes.byref(ms))
     return Q, ms.value
+
+
+def refine(L, l_max, n_tracers, closed, x, v, c):
+    """One refinement pass; returns (n_tracers, x, v, c, inserted)."""
+    nt, cl = _i32(n_tracers).copy(), _i32(closed)
+    n = len(x)
+    cap = 2 * n
+    xx, vv, cc = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    xx[:n], vv[:n], cc[:n] = _f64(x), _f64(v), _f64(c)
+    added = lib().orc_refine(float(L), float(l_max), len(nt), _p(nt), _p(cl), _p(xx), _p(vv), _p(cc), cap)
+    if added < 0:
+        raise MemoryError("refinement failed")
+    m = n + added
+    return nt, xx[:m].copy(), vv[:m].copy(), cc[:m].copy(), int(added)
 
 
 def solve(L, nc, Q):
@@ -134,14 +175,19 @@ def gather(L, nc, E, x):
     return out
 
 
-def push(L, nc, dt, n_tracers, q, E, x, v):
+def push(L, nc, dt, n_tracers, q, closed, E, x, v, c=None):
     """One leapfrog move with field E; returns new (x, v), KE and momentum."""
-    nt, qq, EE = _i32(n_tracers), _f64(q), _f64(E)
+    nt, qq, cl, EE = _i32(n_tracers), _f64(q), _i32(closed), _f64(E)
     xx, vv = _f64(x).copy(), _f64(v).copy()
     ke = ctypes.c_double(0.0)
     mom = ctypes.c_double(0.0)
-    lib().orc_push(float(L), int(nc), float(dt), len(nt), _p(nt), _p(qq), _p(EE), _p(xx), _p(vv),
-                   ctypes.byref(ke), ctypes.byref(mom))
+    if c is None:
+        lib().orc_push(float(L), int(nc), float(dt), len(nt), _p(nt), _p(qq), _p(cl), _p(EE), _p(xx), _p(vv),
+                       ctypes.byref(ke), ctypes.byref(mom))
+    else:
+        cc = _f64(c)
+        lib().orc_push_c(float(L), int(nc), float(dt), len(nt), _p(nt), _p(cl), _p(cc), _p(EE), _p(xx), _p(vv),
+                         ctypes.byref(ke), ctypes.byref(mom))
     return xx, vv, ke.value, mom.value
 
 
@@ -161,6 +207,36 @@ def run(L, nc, dt, n_tracers, q, closed, x0, v0, n_steps, step0=0, init_kick=Tru
     if rc != 0:
         raise MemoryError("oracle run failed")
     return dict(hist=hist, x=xo, v=vo, Q=Qo, E=Eo)
+
+
+def run_seg(L, nc, dt, n_tracers, closed, c, x0, v0, n_steps, step0=0, init_kick=True, order=0, l_max=0.0,
+            capacity=None):
+    """Full run with per-segment charges ``c`` and, when ``l_max`` > 0,
+    refinement after every move.  Returns dict(hist, count (tracers after
+    each step), n_tracers, c, x, v, Q, E)."""
+    nt, cl = _i32(n_tracers).copy(), _i32(closed)
+    cc = _f64(c).copy()
+    xx, vv = _f64(x0), _f64(v0)
+    n = int(np.sum(nt, dtype=np.int64))
+    if len(xx) != n or len(vv) != n or len(cc) != n:
+        raise ValueError("x0/v0/c length must equal the total tracer count")
+    cap = n if capacity is None else max(int(capacity), n)
+    cbuf = np.zeros(cap)
+    cbuf[:n] = cc
+    hist = np.zeros((int(n_steps) + 1, ROW))
+    count = np.zeros(int(n_steps) + 1, dtype=np.int64)
+    xo, vo = np.zeros(cap), np.zeros(cap)
+    Qo, Eo = np.zeros(int(nc)), np.zeros(int(nc))
+    rc = lib().orc_run_seg(int(order), float(L), int(nc), float(dt), len(nt), _p(nt), _p(cl), _p(cbuf), _p(xx),
+                           _p(vv), int(step0), 1 if init_kick else 0, int(n_steps), float(l_max), cap, _p(hist),
+                           _p(count), _p(xo), _p(vo), _p(Qo), _p(Eo))
+    if rc == 1:
+        raise MemoryError("oracle run failed")
+    if rc == 2:
+        raise MemoryError("refinement exceeded the tracer capacity")
+    m = int(np.sum(nt, dtype=np.int64))
+    return dict(hist=hist, count=count, n_tracers=nt, c=cbuf[:m].copy(), x=xo[:m].copy(), v=vo[:m].copy(), Q=Qo,
+                E=Eo)
 
 
 def run_problem(problem, n_steps=None, order=0):

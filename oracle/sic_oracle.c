@@ -38,8 +38,12 @@
  *     keeps the total charge is acceptable);
  *   - a segment joins its tracers along the shorter way round the periodic
  *     box (minimum image); a separation of exactly L/2 is taken downwards;
- *   - every segment of sheet s carries the same charge q_s; a tracer carries
- *     mass q_s for kinetic energy and momentum;
+ *   - the segments are the particles of section 2.3 and carry the charge:
+ *     segment t of a sheet joins tracer t to tracer t+1 and carries c_t (in
+ *     the common case the same q_s for every segment of sheet s); each tracer
+ *     carries half the mass of each segment it bounds, m_t = (c_{t-1} + c_t)/2
+ *     (a missing segment at an open sheet's end counts 0), so the total mass
+ *     equals the total charge (equal charge-to-mass ratio);
  *   - KE^n = 1/2 sum q v^{n-1/2} v^{n+1/2} (the leapfrog-centred product),
  *     W_E^n = 1/2 dx sum_j E_j^2.
  */
@@ -154,8 +158,8 @@ double orc_deposit_segment(double a, double b, double q, double L, int nc, doubl
 /* Charge per cell Q_j = dx * rho_j (before the mean is removed) for all
  * sheets.  Sheets are stored one after another; a closed sheet also joins its
  * last tracer to its first (section 2.3, periodic closure).  Q is zeroed. */
-void orc_deposit(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
-                 const int32_t *closed, const double *x, double *Q, double *max_segment)
+void orc_deposit_c(double L, int nc, int n_sheets, const int32_t *n_tracers, const int32_t *closed,
+                   const double *c, const double *x, double *Q, double *max_segment)
 {
     double maxseg = 0.0;
     memset(Q, 0, sizeof(double) * (size_t)nc);
@@ -165,12 +169,38 @@ void orc_deposit(double L, int nc, int n_sheets, const int32_t *n_tracers, const
         int nseg = closed[s] ? nt : nt - 1;
         for (int t = 0; t < nseg; ++t) {
             int u = (t + 1 == nt) ? 0 : t + 1;
-            double len = orc_deposit_segment(x[base + t], x[base + u], q[s], L, nc, Q);
+            double len = orc_deposit_segment(x[base + t], x[base + u], c[base + t], L, nc, Q);
             if (len > maxseg) maxseg = len;
         }
         base += nt;
     }
     if (max_segment) *max_segment = maxseg;
+}
+
+/* Per-segment charges of sheets whose segments all carry the sheet's q_s
+ * (entry t is the segment that starts at tracer t; the last tracer of an
+ * open sheet starts none and gets 0).  Returns a malloc'ed array. */
+static double *uniform_charges(int n_sheets, const int32_t *n_tracers, const double *q, const int32_t *closed)
+{
+    int64_t n = 0;
+    for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
+    double *c = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!c) return NULL;
+    int64_t base = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        for (int t = 0; t < n_tracers[s]; ++t) c[base + t] = q[s];
+        if (!closed[s] && n_tracers[s] > 0) c[base + n_tracers[s] - 1] = 0.0;
+        base += n_tracers[s];
+    }
+    return c;
+}
+
+void orc_deposit(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                 const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    double *c = uniform_charges(n_sheets, n_tracers, q, closed);
+    orc_deposit_c(L, nc, n_sheets, n_tracers, closed, c, x, Q, max_segment);
+    free(c);
 }
 
 /* Piecewise-linear segments (section 2.5, eqs. "piecewise_linear" and
@@ -188,8 +218,8 @@ void orc_deposit(double L, int nc, int n_sheets, const int32_t *n_tracers, const
  * segment still deposits exactly q.  Segments are laid out in unwrapped
  * coordinates [lo, hi] around their first tracer; a cell index outside
  * 0..nc-1 is taken modulo nc. */
-void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
-                        const int32_t *closed, const double *x, double *Q, double *max_segment)
+void orc_deposit_linear_c(double L, int nc, int n_sheets, const int32_t *n_tracers, const int32_t *closed,
+                          const double *cq, const double *x, double *Q, double *max_segment)
 {
     double dx = L / nc;
     double maxseg = 0.0;
@@ -207,12 +237,12 @@ void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers
             a[t] = x[base + t];
             d[t] = orc_min_image(a[t], x[base + u], L);
             c[t] = a[t] + 0.5 * d[t];
-            r0[t] = d[t] != 0.0 ? q[s] / fabs(d[t]) : 0.0;
+            r0[t] = d[t] != 0.0 ? cq[base + t] / fabs(d[t]) : 0.0;
             if (fabs(d[t]) > maxseg) maxseg = fabs(d[t]);
         }
         for (int t = 0; t < nseg; ++t) {
             if (d[t] == 0.0) {
-                Q[orc_point_cell(a[t], L, nc)] += q[s];
+                Q[orc_point_cell(a[t], L, nc)] += cq[base + t];
                 continue;
             }
             double g = 0.0;
@@ -248,6 +278,14 @@ void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers
     if (max_segment) *max_segment = maxseg;
 }
 
+void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                        const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    double *c = uniform_charges(n_sheets, n_tracers, q, closed);
+    orc_deposit_linear_c(L, nc, n_sheets, n_tracers, closed, c, x, Q, max_segment);
+    free(c);
+}
+
 /* First-order weighting of segments (section 2.4): every slice of a
  * segment's box function is assigned to the grid points X_j = (j + 1/2) dx
  * with the first-order weight W_1(x - X_j) = max(0, 1 - |x - X_j| / dx), so
@@ -263,8 +301,8 @@ static double hat(double x, double X, double dx)
     return w > 0.0 ? w : 0.0;
 }
 
-void orc_deposit_cic(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
-                     const int32_t *closed, const double *x, double *Q, double *max_segment)
+void orc_deposit_cic_c(double L, int nc, int n_sheets, const int32_t *n_tracers, const int32_t *closed,
+                       const double *c, const double *x, double *Q, double *max_segment)
 {
     double dx = L / nc;
     double maxseg = 0.0;
@@ -281,11 +319,11 @@ void orc_deposit_cic(double L, int nc, int n_sheets, const int32_t *n_tracers, c
             if (d == 0.0) {
                 long j0 = (long)floor(a / dx - 0.5);
                 for (long j = j0; j <= j0 + 1; ++j)
-                    Q[mod_cell(j, nc)] += q[s] * hat(a, ((double)j + 0.5) * dx, dx);
+                    Q[mod_cell(j, nc)] += c[base + t] * hat(a, ((double)j + 0.5) * dx, dx);
                 continue;
             }
             double lo = d > 0.0 ? a : a + d, hi = d > 0.0 ? a + d : a;
-            double h = q[s] / (hi - lo);
+            double h = c[base + t] / (hi - lo);
             long j0 = (long)floor(lo / dx - 0.5) - 1, j1 = (long)floor(hi / dx - 0.5) + 2;
             for (long j = j0; j <= j1; ++j) {
                 double X = ((double)j + 0.5) * dx;
@@ -305,6 +343,14 @@ void orc_deposit_cic(double L, int nc, int n_sheets, const int32_t *n_tracers, c
         base += nt;
     }
     if (max_segment) *max_segment = maxseg;
+}
+
+void orc_deposit_cic(double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
+                     const int32_t *closed, const double *x, double *Q, double *max_segment)
+{
+    double *c = uniform_charges(n_sheets, n_tracers, q, closed);
+    orc_deposit_cic_c(L, nc, n_sheets, n_tracers, closed, c, x, Q, max_segment);
+    free(c);
 }
 
 /* Solve the periodic 3-point Poisson equation
@@ -386,25 +432,36 @@ void orc_gather_many(double L, int nc, const double *E, int64_t n, const double 
     for (int64_t i = 0; i < n; ++i) out[i] = orc_gather(L, nc, E, x[i]);
 }
 
-/* Per-tracer mass: every tracer of sheet s carries q_s. */
-static void sheet_of_tracers(int n_sheets, const int32_t *n_tracers, const double *q, double *mass)
+/* Per-tracer mass: half of each segment the tracer bounds,
+ * m_t = (c_{t-1} + c_t) / 2, with the closing segment of a closed sheet
+ * joining its last tracer to its first and nothing beyond an open sheet's
+ * ends. */
+static void tracer_masses(int n_sheets, const int32_t *n_tracers, const int32_t *closed, const double *c,
+                          double *mass)
 {
     int64_t base = 0;
     for (int s = 0; s < n_sheets; ++s) {
-        for (int t = 0; t < n_tracers[s]; ++t) mass[base + t] = q[s];
-        base += n_tracers[s];
+        int nt = n_tracers[s];
+        for (int t = 0; t < nt; ++t) {
+            double right = (closed[s] || t + 1 < nt) ? c[base + t] : 0.0;
+            double left = 0.0;
+            if (t > 0) left = c[base + t - 1];
+            else if (closed[s]) left = c[base + nt - 1];
+            mass[base + t] = 0.5 * (left + right);
+        }
+        base += nt;
     }
 }
 
 /* One leapfrog move with the field E^n: kick then drift.  Returns KE^n and
  * momentum^n through the pointers (centred on x^n). */
-void orc_push(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
-              const double *E, double *x, double *v, double *ke, double *mom)
+void orc_push_c(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const int32_t *closed,
+                const double *c, const double *E, double *x, double *v, double *ke, double *mom)
 {
     int64_t n = 0;
     for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
     double *mass = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    sheet_of_tracers(n_sheets, n_tracers, q, mass);
+    tracer_masses(n_sheets, n_tracers, closed, c, mass);
     double k = 0.0, p = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         double e = orc_gather(L, nc, E, x[i]);
@@ -417,6 +474,74 @@ void orc_push(double L, int nc, double dt, int n_sheets, const int32_t *n_tracer
     free(mass);
     if (ke) *ke = k;
     if (mom) *mom = p;
+}
+
+void orc_push(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
+              const int32_t *closed, const double *E, double *x, double *v, double *ke, double *mom)
+{
+    double *c = uniform_charges(n_sheets, n_tracers, q, closed);
+    orc_push_c(L, nc, dt, n_sheets, n_tracers, closed, c, E, x, v, ke, mom);
+    free(c);
+}
+
+/* Refinement (section 2.6): every segment longer than l_max gets a new
+ * tracer at its centre (along the shorter way round the box), with the mean
+ * of its end tracers' velocities; the two halves each carry half of the
+ * segment's charge.  One pass over the segments as they are when called (a
+ * segment longer than 2 l_max is halved once; the check runs again after the
+ * next move).  n_tracers, x, v and c (capacity cap entries each) are updated
+ * in place; returns the number of tracers inserted, or -1 (nothing changed)
+ * if the result would not fit in cap. */
+int64_t orc_refine(double L, double l_max, int n_sheets, int32_t *n_tracers, const int32_t *closed, double *x,
+                   double *v, double *c, int64_t cap)
+{
+    int64_t n = 0, add = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        int nt = n_tracers[s];
+        int nseg = closed[s] ? nt : nt - 1;
+        for (int t = 0; t < nseg; ++t) {
+            int u = (t + 1 == nt) ? 0 : t + 1;
+            if (fabs(orc_min_image(x[n + t], x[n + u], L)) > l_max) ++add;
+        }
+        n += nt;
+    }
+    if (add == 0) return 0;
+    if (n + add > cap) return -1;
+    double *nx = (double *)malloc(sizeof(double) * (size_t)(n + add));
+    double *nv = (double *)malloc(sizeof(double) * (size_t)(n + add));
+    double *ncq = (double *)malloc(sizeof(double) * (size_t)(n + add));
+    if (!nx || !nv || !ncq) { free(nx); free(nv); free(ncq); return -1; }
+    int64_t base = 0, out = 0;
+    for (int s = 0; s < n_sheets; ++s) {
+        int nt = n_tracers[s];
+        int nseg = closed[s] ? nt : nt - 1;
+        int64_t first = out;
+        for (int t = 0; t < nt; ++t) {
+            nx[out] = x[base + t];
+            nv[out] = v[base + t];
+            ncq[out] = c[base + t];
+            ++out;
+            if (t < nseg) {
+                int u = (t + 1 == nt) ? 0 : t + 1;
+                double d = orc_min_image(x[base + t], x[base + u], L);
+                if (fabs(d) > l_max) {
+                    double half = 0.5 * c[base + t];
+                    ncq[out - 1] = half;
+                    nx[out] = orc_wrap(x[base + t] + 0.5 * d, L);
+                    nv[out] = 0.5 * (v[base + t] + v[base + u]);
+                    ncq[out] = half;
+                    ++out;
+                }
+            }
+        }
+        n_tracers[s] = (int32_t)(out - first);
+        base += nt;
+    }
+    memcpy(x, nx, sizeof(double) * (size_t)out);
+    memcpy(v, nv, sizeof(double) * (size_t)out);
+    memcpy(c, ncq, sizeof(double) * (size_t)out);
+    free(nx); free(nv); free(ncq);
+    return add;
 }
 
 static double row_flags(double L, int nc, const double *E, double maxseg)
@@ -433,20 +558,86 @@ static double row_flags(double L, int nc, const double *E, double maxseg)
  * velocities: x0 is wrapped into [0, L), the field E^0 is computed and the
  * velocities are moved back half a step, v^{-1/2} = v^0 - dt/2 E^0(x^0).
  * With init_kick = 0, v0 is already v^{-1/2} at step step0 (a resumed state).
- * hist holds (n_steps + 1) rows of ORC_ROW doubles; the KE and momentum of
- * the last row need the next push and are NaN.  Final positions, v^{N-1/2},
- * charge per cell and field are returned when the pointers are non-null. */
-int orc_run_order(int order, double L, int nc, double dt, int n_sheets, const int32_t *n_tracers,
-                  const double *q, const int32_t *closed, const double *x0, const double *v0, int64_t step0,
-                  int init_kick, int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out,
-                  double *E_out);
-
-static void deposit_order(int order, double L, int nc, int n_sheets, const int32_t *n_tracers, const double *q,
-                          const int32_t *closed, const double *x, double *Q, double *max_segment)
+ * Each step is: push with E^n (KE^n and momentum^n), refinement of the moved
+ * sheets when l_max > 0, deposit of x^{n+1}, solve.  hist holds (n_steps + 1)
+ * rows of ORC_ROW doubles; the KE and momentum of the last row need the next
+ * push and are NaN.  n_tracers and c (per-segment charges) are updated in
+ * place when refinement inserts tracers; x_out and v_out then need room for
+ * cap entries.  count_out (optional, n_steps + 1 entries) receives the total
+ * tracer count after each step.  Returns 0, 1 when out of memory, 2 when
+ * refinement would exceed cap tracers (the run stops there). */
+static void deposit_by_order(int order, double L, int nc, int n_sheets, const int32_t *n_tracers,
+                             const int32_t *closed, const double *c, const double *x, double *Q, double *max_segment)
 {
-    if (order == 1) orc_deposit_linear(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
-    else if (order == 2) orc_deposit_cic(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
-    else orc_deposit(L, nc, n_sheets, n_tracers, q, closed, x, Q, max_segment);
+    if (order == 1) orc_deposit_linear_c(L, nc, n_sheets, n_tracers, closed, c, x, Q, max_segment);
+    else if (order == 2) orc_deposit_cic_c(L, nc, n_sheets, n_tracers, closed, c, x, Q, max_segment);
+    else orc_deposit_c(L, nc, n_sheets, n_tracers, closed, c, x, Q, max_segment);
+}
+
+int orc_run_seg(int order, double L, int nc, double dt, int n_sheets, int32_t *n_tracers, const int32_t *closed,
+                double *c, const double *x0, const double *v0, int64_t step0, int init_kick, int64_t n_steps,
+                double l_max, int64_t cap, double *hist, int64_t *count_out, double *x_out, double *v_out,
+                double *Q_out, double *E_out)
+{
+    int64_t n = 0;
+    for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
+    if (cap < n) cap = n;
+    double *x = (double *)calloc((size_t)(cap > 0 ? cap : 1), sizeof(double));
+    double *v = (double *)calloc((size_t)(cap > 0 ? cap : 1), sizeof(double));
+    double *Q = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *E = (double *)malloc(sizeof(double) * (size_t)nc);
+    if (!x || !v || !Q || !E) { free(x); free(v); free(Q); free(E); return 1; }
+    for (int64_t i = 0; i < n; ++i) { x[i] = orc_wrap(x0[i], L); v[i] = v0[i]; }
+
+    int rc = 0;
+    double W, qt, ms;
+    deposit_by_order(order, L, nc, n_sheets, n_tracers, closed, c, x, Q, &ms);
+    orc_solve(L, nc, Q, E, &W, &qt);
+    if (init_kick) {
+        for (int64_t i = 0; i < n; ++i) v[i] = v[i] - 0.5 * dt * orc_gather(L, nc, E, x[i]);
+    }
+    double *row = hist;
+    row[0] = (double)step0; row[1] = (double)step0 * dt; row[2] = W; row[3] = NAN; row[4] = NAN;
+    row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
+    if (count_out) count_out[0] = n;
+    for (int64_t it = 0; it < n_steps; ++it) {
+        double ke, mom;
+        orc_push_c(L, nc, dt, n_sheets, n_tracers, closed, c, E, x, v, &ke, &mom);
+        hist[it * ORC_ROW + 3] = ke;
+        hist[it * ORC_ROW + 4] = mom;
+        if (l_max > 0.0) {
+            int64_t added = orc_refine(L, l_max, n_sheets, n_tracers, closed, x, v, c, cap);
+            if (added < 0) { rc = 2; break; }
+            n += added;
+        }
+        deposit_by_order(order, L, nc, n_sheets, n_tracers, closed, c, x, Q, &ms);
+        orc_solve(L, nc, Q, E, &W, &qt);
+        row = hist + (it + 1) * ORC_ROW;
+        row[0] = (double)(step0 + it + 1); row[1] = (double)(step0 + it + 1) * dt; row[2] = W;
+        row[3] = NAN; row[4] = NAN; row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
+        if (count_out) count_out[it + 1] = n;
+    }
+    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);
+    if (v_out) memcpy(v_out, v, sizeof(double) * (size_t)n);
+    if (Q_out) memcpy(Q_out, Q, sizeof(double) * (size_t)nc);
+    if (E_out) memcpy(E_out, E, sizeof(double) * (size_t)nc);
+    free(x); free(v); free(Q); free(E);
+    return rc;
+}
+
+/* The run with every segment of sheet s carrying q_s and no refinement. */
+int orc_run_order(int order, double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
+                  const int32_t *closed, const double *x0, const double *v0, int64_t step0, int init_kick,
+                  int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out, double *E_out)
+{
+    double *c = uniform_charges(n_sheets, n_tracers, q, closed);
+    int32_t *nt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_sheets > 0 ? n_sheets : 1));
+    if (!c || !nt) { free(c); free(nt); return 1; }
+    memcpy(nt, n_tracers, sizeof(int32_t) * (size_t)n_sheets);
+    int rc = orc_run_seg(order, L, nc, dt, n_sheets, nt, closed, c, x0, v0, step0, init_kick, n_steps, 0.0, 0, hist,
+                         NULL, x_out, v_out, Q_out, E_out);
+    free(c); free(nt);
+    return rc;
 }
 
 int orc_run(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
@@ -455,45 +646,4 @@ int orc_run(double L, int nc, double dt, int n_sheets, const int32_t *n_tracers,
 {
     return orc_run_order(0, L, nc, dt, n_sheets, n_tracers, q, closed, x0, v0, step0, init_kick, n_steps, hist,
                          x_out, v_out, Q_out, E_out);
-}
-
-int orc_run_order(int order, double L, int nc, double dt, int n_sheets, const int32_t *n_tracers, const double *q,
-                  const int32_t *closed, const double *x0, const double *v0, int64_t step0, int init_kick,
-                  int64_t n_steps, double *hist, double *x_out, double *v_out, double *Q_out, double *E_out)
-{
-    int64_t n = 0;
-    for (int s = 0; s < n_sheets; ++s) n += n_tracers[s];
-    double *x = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    double *Q = (double *)malloc(sizeof(double) * (size_t)nc);
-    double *E = (double *)malloc(sizeof(double) * (size_t)nc);
-    if (!x || !v || !Q || !E) { free(x); free(v); free(Q); free(E); return 1; }
-    for (int64_t i = 0; i < n; ++i) { x[i] = orc_wrap(x0[i], L); v[i] = v0[i]; }
-
-    double W, qt, ms;
-    deposit_order(order, L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
-    orc_solve(L, nc, Q, E, &W, &qt);
-    if (init_kick) {
-        for (int64_t i = 0; i < n; ++i) v[i] = v[i] - 0.5 * dt * orc_gather(L, nc, E, x[i]);
-    }
-    double *row = hist;
-    row[0] = (double)step0; row[1] = (double)step0 * dt; row[2] = W; row[3] = NAN; row[4] = NAN;
-    row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
-    for (int64_t it = 0; it < n_steps; ++it) {
-        double ke, mom;
-        orc_push(L, nc, dt, n_sheets, n_tracers, q, E, x, v, &ke, &mom);
-        hist[it * ORC_ROW + 3] = ke;
-        hist[it * ORC_ROW + 4] = mom;
-        deposit_order(order, L, nc, n_sheets, n_tracers, q, closed, x, Q, &ms);
-        orc_solve(L, nc, Q, E, &W, &qt);
-        row = hist + (it + 1) * ORC_ROW;
-        row[0] = (double)(step0 + it + 1); row[1] = (double)(step0 + it + 1) * dt; row[2] = W;
-        row[3] = NAN; row[4] = NAN; row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
-    }
-    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);
-    if (v_out) memcpy(v_out, v, sizeof(double) * (size_t)n);
-    if (Q_out) memcpy(Q_out, Q, sizeof(double) * (size_t)nc);
-    if (E_out) memcpy(E_out, E, sizeof(double) * (size_t)nc);
-    free(x); free(v); free(Q); free(E);
-    return 0;
 }

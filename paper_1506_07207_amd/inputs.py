@@ -34,6 +34,8 @@ __all__ = [
     "landau",
     "two_stream",
     "cold_two_stream",
+    "landau_vertical",
+    "refinement_two_stream",
     "uniform_sheet",
     "random_sheets",
     "batch_mix",
@@ -63,6 +65,7 @@ class Problem:
     sheet_v: Optional[np.ndarray] = None  # float64 [M]
     x_full: Optional[np.ndarray] = None
     v_full: Optional[np.ndarray] = None
+    c_full: Optional[np.ndarray] = None  # float64 [T] per-segment charges (replace q)
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -88,6 +91,17 @@ class Problem:
     @property
     def uniform(self) -> bool:
         return self.x_full is None
+
+    @property
+    def seg_charges(self) -> np.ndarray:
+        """Charge of every segment, indexed by the tracer it starts at (the
+        last tracer of an open sheet starts none: 0)."""
+        if self.c_full is not None:
+            return self.c_full
+        c = np.repeat(self.q, self.n_tracers)
+        ends = np.cumsum(self.n_tracers.astype(np.int64)) - 1
+        c[ends[self.closed == 0]] = 0.0
+        return c
 
 
 def lagrangian_grid(n: int, L: float) -> np.ndarray:
@@ -204,6 +218,58 @@ def cold_two_stream(k: float = 0.5, v0: float = None, alpha: float = 1e-4, n_tra
     line = density_positions(n_tracers, L, k, alpha)
     return _uniform_problem("cold_two_stream", L, n_cells, dt, n_steps, line,
                             np.array([-v0, v0]), np.array([0.5, 0.5]), dict(k=k, alpha=alpha, v0=v0))
+
+
+def landau_vertical(k: float = 0.5, alpha: float = 0.01, n_streams: int = 26, n_positions: int = 160,
+                    n_cells: int = 40, dt: float = 0.1, n_steps: int = 300, vth: float = 1.0,
+                    vmax_units: float = 4.0) -> Problem:
+    """The Landau set-up of the phase-space geometry study (paper section
+    3.3.2) with vertically connected sheets: the tracers sit where the
+    horizontal set-up puts them (positions with density 1 + alpha cos(k x),
+    the same velocities for every position), but each open sheet joins the
+    tracers of one position across velocity.  The segment between velocities
+    v_m and v_{m+1} carries half the sum of the two tracers' Maxwellian
+    charges (the tracer-charge form of section 2.5), so the charge falls with
+    velocity along the sheet."""
+    L = 2.0 * math.pi / k
+    line = density_positions(n_positions, L, k, alpha)
+    v, w = maxwellian_sheets(n_streams, vth, vmax_units)
+    qt = w * (L / n_positions)
+    seg = np.zeros(n_streams)
+    seg[:-1] = 0.5 * (qt[:-1] + qt[1:])
+    m = n_positions
+    return Problem(
+        name="landau_vertical",
+        L=float(L),
+        n_cells=int(n_cells),
+        dt=float(dt),
+        n_steps=int(n_steps),
+        n_tracers=np.full(m, n_streams, dtype=np.int32),
+        q=np.zeros(m),
+        closed=np.zeros(m, dtype=np.int32),
+        x_full=np.repeat(line, n_streams),
+        v_full=np.tile(v, m),
+        c_full=np.tile(seg, m),
+        meta=dict(k=k, alpha=alpha, vth=vth),
+    )
+
+
+def refinement_two_stream(ppc: int = 10, n_cells: int = 100, k: float = 0.5, dt: float = 0.1,
+                          n_steps: int = 400, amplitude_cells: float = 0.01) -> Problem:
+    """The refinement experiment of section 2.6: two cold, counter-streaming
+    beams at the fastest-growing velocity (k v0 = (sqrt(3)/2) sqrt(1/2) for
+    beams of plasma frequency sqrt(1/2)), ``ppc`` tracers per cell per
+    stream, displaced by amplitude_cells * dx * sin(k q) at the box's
+    fundamental mode."""
+    L = 2.0 * math.pi / k
+    v0 = (math.sqrt(3.0) / 2.0) * math.sqrt(0.5) / k
+    n = ppc * n_cells
+    q = lagrangian_grid(n, L)
+    x = q + amplitude_cells * (L / n_cells) * np.sin(k * q)
+    x = np.mod(x, L)
+    x = np.where(x >= L, 0.0, x)
+    return _uniform_problem("refinement_two_stream", L, n_cells, dt, n_steps, x, np.array([-v0, v0]),
+                            np.array([0.5, 0.5]), dict(k=k, v0=v0, ppc=ppc))
 
 
 def uniform_sheet(n_tracers: int, n_cells: int, L: float, v: float = 0.0, shift: float = 0.0,

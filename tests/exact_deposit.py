@@ -9,16 +9,24 @@ from fractions import Fraction
 import math
 
 
+def _seg_charge(q, t):
+    """q is one charge for every segment of the sheet, or a list of
+    per-segment charges (entry t: the segment that starts at tracer t)."""
+    return Fraction(q[t]) if isinstance(q, (list, tuple)) else Fraction(q)
+
+
 def exact_deposit(L, nc, sheets):
-    """sheets: list of (q, closed, [x_t as Fraction]).  Returns [Fraction] * nc."""
+    """sheets: list of (q, closed, [x_t as Fraction]); q is a charge per
+    segment, or a list of them.  Returns [Fraction] * nc."""
     L = Fraction(L)
     dx = L / nc
     Q = [Fraction(0)] * nc
     for q, closed, xs in sheets:
-        q = Fraction(q)
+        qs = q
         n = len(xs)
         nseg = n if closed else n - 1
         for t in range(nseg):
+            q = _seg_charge(qs, t)
             a = Fraction(xs[t])
             b = Fraction(xs[(t + 1) % n])
             d = b - a
@@ -58,17 +66,17 @@ def exact_deposit_linear(L, nc, sheets):
     dx = L / nc
     Q = [Fraction(0)] * nc
     for q, closed, xs in sheets:
-        q = Fraction(q)
+        qs = q
         n = len(xs)
         nseg = n if closed else n - 1
         segs = []
         for t in range(nseg):
             a = Fraction(xs[t])
             d = _min_image(Fraction(xs[(t + 1) % n]) - a, L)
-            segs.append((a, d, a + d / 2, (q / abs(d)) if d != 0 else None))
+            segs.append((a, d, a + d / 2, (_seg_charge(qs, t) / abs(d)) if d != 0 else None))
         for t, (a, d, c, r0) in enumerate(segs):
             if d == 0:
-                Q[(math.ceil(a / dx) - 1) % nc] += q
+                Q[(math.ceil(a / dx) - 1) % nc] += _seg_charge(qs, t)
                 continue
             g = Fraction(0)
             has_prev = (nseg >= 3) if closed else t > 0
@@ -111,10 +119,11 @@ def exact_deposit_cic(L, nc, sheets):
     dx = L / nc
     Q = [Fraction(0)] * nc
     for q, closed, xs in sheets:
-        q = Fraction(q)
+        qs = q
         n = len(xs)
         nseg = n if closed else n - 1
         for t in range(nseg):
+            q = _seg_charge(qs, t)
             a = Fraction(xs[t])
             d = _min_image(Fraction(xs[(t + 1) % n]) - a, L)
             if d == 0:
