@@ -12,6 +12,8 @@
  *     also joins its last tracer to its first;
  *   - section 2.3, eqs. "overlap" and "rho_sum": the charge of every segment is
  *     deposited onto the periodic mesh by its exact overlap with each cell;
+ *   - section 2.6: optional refinement, a centre tracer inserted into every
+ *     segment that has grown longer than a set length;
  *   - the paragraph after eq. "j_sum": solve for the field, gather it to the
  *     tracers with linear (first-order) weighting (section 2.4) and move the
  *     tracers as PIC particles - here with a leapfrog.
@@ -44,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SIC_ABI_VERSION 1
+#define SIC_ABI_VERSION 2
 #define SIC_MAX_CELLS 4096
 
 typedef enum sic_status {
@@ -86,17 +88,37 @@ typedef struct sic_config {
                               (W_1) weighting of constant segments to the grid points (section
                               2.4); others SIC_ENOTSUP */
     int64_t history_rows;  /* capacity of the per-simulation diagnostics ring; 0: 65536 */
+    double l_max;          /* refinement length (section 2.6): after every move, each segment
+                              longer than l_max gets a new tracer at its centre with the mean
+                              velocity of its two tracers, and each half carries half of its
+                              charge; 0: no refinement.  Single simulations only (a batch
+                              admission with l_max > 0 returns SIC_ENOTSUP). */
+    int64_t max_tracers;   /* tracer capacity for refinement growth; 0: the initial count.  A
+                              refinement that would exceed it fails with SIC_ENOMEM and leaves
+                              the state unchanged. */
 } sic_config;
 
 typedef struct sic_sheet {
     int32_t n_tracers; /* >= 2 */
     int32_t closed;    /* 1: segment from the last tracer back to the first; 0: open chain */
-    double q_seg;      /* charge carried by every segment of the sheet (tracer mass too) */
+    double q_seg;      /* charge carried by every segment of the sheet, unless per-segment
+                          charges are given */
 } sic_sheet;
+
+/* Per-segment charges (section 2.3: the segments are the particles and carry
+ * the charge).  Where a call takes seg_charges, NULL means every segment of
+ * sheet s carries sheets[s].q_seg; otherwise it holds sum(n_tracers) doubles,
+ * sheet-major, and entry t of a sheet is the charge of the segment from tracer
+ * t to tracer t + 1 (for the last tracer of a closed sheet, the closing
+ * segment back to tracer 0; the entry of the last tracer of an open sheet is
+ * ignored and reads back as 0).  Tracer t carries mass (c_{t-1} + c_t) / 2,
+ * half of each segment it bounds (a missing segment counts 0), so the total
+ * mass is the total charge (equal charge-to-mass ratio). */
 
 /* One row of diagnostics, at step n (positions x^n, time t = n dt):
  *   W_E          = 1/2 dx sum_j E_j^2 (field energy, section 3 "E_pot");
- *   KE           = 1/2 sum q v^{n-1/2} v^{n+1/2}, momentum = sum q (v^{n-1/2}+v^{n+1/2})/2;
+ *   KE           = 1/2 sum m v^{n-1/2} v^{n+1/2}, momentum = sum m (v^{n-1/2}+v^{n+1/2})/2
+ *                  with the tracer masses m defined with the segment charges;
  *                  both need the push from step n, so the newest row has them
  *                  as NaN;
  *   total_charge = sum_j Q_j (charge conservation check);
@@ -118,10 +140,12 @@ typedef struct sic_sim sic_sim;
  * [0, L), the charge Q^0 is deposited, the field E^0 solved, and the
  * velocities are moved back half a step, v^{-1/2} = v0 - dt/2 E^0(x0)
  * (leapfrog start).  On return the simulation is at step 0 with its field
- * current.  x0 and v0 hold sum(n_tracers) values.  hip_stream: hipStream_t or
- * NULL.  Synchronous (returns after the ingest has run). */
+ * current.  x0 and v0 hold sum(n_tracers) values; seg_charges is NULL or the
+ * per-segment charges (see above), in the same memory as x0.  hip_stream:
+ * hipStream_t or NULL.  Synchronous (returns after the ingest has run). */
 sic_status sic_init(const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
-                    const double *v0, int32_t mem_kind, void *hip_stream, sic_sim **out);
+                    const double *v0, const double *seg_charges, int32_t mem_kind, void *hip_stream,
+                    sic_sim **out);
 
 /* Deposit (section 2.3): Q <- charge of every segment at the current
  * positions x^n, by exact box-cell overlap.  Allowed in any state.  Async. */
@@ -139,8 +163,38 @@ sic_status sic_push(sic_sim *sim);
 /* n_steps full steps.  Each step moves the tracers with the current field,
  * deposits the new positions and solves the new field, so on return the field
  * is current for the new step.  If the field is stale it is brought up to date
- * first.  Steps run as captured HIP graphs.  Async. */
+ * first.  Steps run as captured HIP graphs.  Async; with refinement on
+ * (l_max > 0) each step also runs sic_refine, which synchronises. */
 sic_status sic_step(sic_sim *sim, int64_t n_steps);
+
+/* One refinement pass (section 2.6) over the current positions: every segment
+ * longer than l_max (minimum-image length) gets a tracer at its centre, with
+ * the mean velocity of its two tracers, and both halves carry half its
+ * charge; a segment longer than 2 l_max is halved once per pass.  When a
+ * tracer was inserted, the new state is deposited and solved and the newest
+ * diagnostics row is rewritten with it.  *inserted (may be NULL) receives the
+ * number of tracers added.  Needs a simulation created with per-segment
+ * charges or l_max > 0 (else SIC_ENOTSUP); SIC_ENOMEM beyond max_tracers
+ * (state unchanged).  Synchronous. */
+sic_status sic_refine(sic_sim *sim, double l_max, int64_t *inserted);
+
+/* Tracers per sheet now (n_tracers_out: NULL or n_sheets entries) and their
+ * total; refinement changes them. */
+sic_status sic_get_layout(const sic_sim *sim, int32_t *n_tracers_out, int64_t *total);
+
+/* Per-segment charges now (sum of the current n_tracers doubles, in mem_kind
+ * memory; fixed-point charges of the split forms converted to float64).
+ * Synchronous. */
+sic_status sic_get_charges(sic_sim *sim, double *seg_charges, int32_t mem_kind);
+
+/* Replaces the tracer state with n_tracers[s] tracers per sheet (the sheets
+ * and their closure stay those given at creation): positions x^n, velocities
+ * v^{n-1/2}, per-segment charges (NULL: each sheet's q_seg from creation; a
+ * simulation created without per-segment charges and without refinement
+ * accepts only NULL) and step n.  The field becomes stale.  SIC_ENOMEM beyond
+ * the tracer capacity.  Synchronous. */
+sic_status sic_load_state(sic_sim *sim, int64_t step, const int32_t *n_tracers, const double *x,
+                          const double *v_half, const double *seg_charges, int32_t mem_kind);
 
 /* Synchronises the stream and reads diagnostics.  out (may be NULL) receives
  * the newest row.  rho_out / E_out (NULL or n_cells doubles, host memory)
@@ -190,21 +244,33 @@ sic_status sic_get_tuning(const sic_sim *sim, sic_tuning *t);
  * ---------------------------------------------------------------------- */
 typedef struct sic_batch sic_batch;
 
-/* budget_tracers: maximum resident tracers over all slots; max_slots: maximum
- * resident simulations; max_cells: largest n_cells admitted (<= SIC_MAX_CELLS);
+/* Batch flags. */
+#define SIC_BATCH_SEGMENT_CHARGES 1 /* store a charge per segment: admissions may pass
+                                       seg_charges (8 more bytes per tracer of budget, read
+                                       every step) */
+
+/* budget_tracers: maximum resident tracers over all slots (the tracer arena
+ * holds every sheet in whole 64-tracer chunks, with about 1/8 spare for the
+ * padding of partly filled last chunks: many sheets of fewer than 64 tracers
+ * can fill it before the budget, and admission then returns SIC_EBUSY);
+ * max_slots: maximum resident simulations; max_cells: largest n_cells
+ * admitted (<= SIC_MAX_CELLS);
  * precision and deposit_order: shared by every admitted simulation (as in
- * sic_config); history_rows: diagnostics rows kept per slot (ring; 0: 4096).
- * Synchronous. */
+ * sic_config); flags: SIC_BATCH_* bits; history_rows: diagnostics rows kept
+ * per slot (ring; 0: 4096).  Synchronous. */
 sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t max_cells, int32_t precision,
-                            int32_t deposit_order, int64_t history_rows, void *hip_stream, sic_batch **out);
+                            int32_t deposit_order, int32_t flags, int64_t history_rows, void *hip_stream,
+                            sic_batch **out);
 
 /* Admits one simulation that will run n_steps steps (n_steps < 0: until
- * released).  Ingests it as sic_init does.  Returns SIC_EBUSY when no slot is
- * free or its tracers do not fit the budget.  *slot receives the slot index.
- * Ordered on the batch stream; returns after the inputs have been copied. */
+ * released).  Ingests it as sic_init does.  seg_charges: NULL, or per-segment
+ * charges for a batch created with SIC_BATCH_SEGMENT_CHARGES (else
+ * SIC_ENOTSUP).  Returns SIC_EBUSY when no slot is free or its tracers do not
+ * fit the budget.  *slot receives the slot index.  Ordered on the batch
+ * stream; returns after the inputs have been copied. */
 sic_status sic_batch_admit(sic_batch *b, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets,
-                           const double *x0, const double *v0, int32_t mem_kind, int64_t n_steps,
-                           int32_t *slot);
+                           const double *x0, const double *v0, const double *seg_charges, int32_t mem_kind,
+                           int64_t n_steps, int32_t *slot);
 
 /* Advances every unfinished resident simulation by up to n_steps steps in
  * shared launches (captured HIP graphs); a simulation stops when its own step
@@ -222,6 +288,9 @@ sic_status sic_batch_result(sic_batch *b, int32_t slot, sic_diag *out, double *r
 /* Checkpoint of one slot, as sic_get_state. */
 sic_status sic_batch_get_state(sic_batch *b, int32_t slot, double *x, double *v_half, int64_t *step,
                                int32_t mem_kind);
+
+/* Per-segment charges of one slot, as sic_get_charges. */
+sic_status sic_batch_get_charges(sic_batch *b, int32_t slot, double *seg_charges, int32_t mem_kind);
 
 /* Frees a slot (finished or not) and its tracer budget.  Ordered on the stream. */
 sic_status sic_batch_release(sic_batch *b, int32_t slot);

@@ -21,7 +21,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsic.so")
 
-SIC_ABI_VERSION = 1
+SIC_ABI_VERSION = 2
+SIC_BATCH_SEGMENT_CHARGES = 1
 SIC_MAX_CELLS = 4096
 SIC_FP64, SIC_SPLIT_F32, SIC_SPLIT_U32 = 0, 1, 2
 SIC_MEM_HOST, SIC_MEM_DEVICE = 0, 1
@@ -43,7 +44,7 @@ class SicError(RuntimeError):
 class sic_config(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("n_cells", ctypes.c_int32), ("L", ctypes.c_double),
                 ("dt", ctypes.c_double), ("precision", ctypes.c_int32), ("deposit_order", ctypes.c_int32),
-                ("history_rows", ctypes.c_int64)]
+                ("history_rows", ctypes.c_int64), ("l_max", ctypes.c_double), ("max_tracers", ctypes.c_int64)]
 
 
 class sic_sheet(ctypes.Structure):
@@ -67,7 +68,11 @@ _I64 = ctypes.c_int64
 _SIGS = {
     "sic_abi_version": (_I32, []),
     "sic_status_str": (ctypes.c_char_p, [_I32]),
-    "sic_init": (_I32, [_P, _P, _I32, _P, _P, _I32, _P, _P]),
+    "sic_init": (_I32, [_P, _P, _I32, _P, _P, _P, _I32, _P, _P]),
+    "sic_refine": (_I32, [_P, ctypes.c_double, _P]),
+    "sic_get_layout": (_I32, [_P, _P, _P]),
+    "sic_get_charges": (_I32, [_P, _P, _I32]),
+    "sic_load_state": (_I32, [_P, _I64, _P, _P, _P, _P, _I32]),
     "sic_deposit": (_I32, [_P]),
     "sic_solve_field": (_I32, [_P]),
     "sic_push": (_I32, [_P]),
@@ -81,8 +86,9 @@ _SIGS = {
     "sic_get_tuning": (_I32, [_P, _P]),
     "sic_set_timing": (_I32, [_P, _I32]),
     "sic_last_timing": (_I32, [_P, _P, _P]),
-    "sic_batch_create": (_I32, [_I64, _I32, _I32, _I32, _I32, _I64, _P, _P]),
-    "sic_batch_admit": (_I32, [_P, _P, _P, _I32, _P, _P, _I32, _I64, _P]),
+    "sic_batch_create": (_I32, [_I64, _I32, _I32, _I32, _I32, _I32, _I64, _P, _P]),
+    "sic_batch_admit": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _I32, _I64, _P]),
+    "sic_batch_get_charges": (_I32, [_P, _I32, _P, _I32]),
     "sic_batch_step": (_I32, [_P, _I64]),
     "sic_batch_poll": (_I32, [_P, _P, _I32, _P]),
     "sic_batch_result": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
@@ -173,11 +179,12 @@ def _check(rc: int, where: str, handle=None, batch=False):
         raise SicError(rc, where, msg)
 
 
-def make_config(L, n_cells, dt, precision=SIC_FP64, history_rows=0, deposit_order=0) -> sic_config:
+def make_config(L, n_cells, dt, precision=SIC_FP64, history_rows=0, deposit_order=0, l_max=0.0,
+                max_tracers=0) -> sic_config:
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     return sic_config(SIC_ABI_VERSION, int(n_cells), float(L), float(dt), int(precision), int(deposit_order),
-                      int(history_rows))
+                      int(history_rows), float(l_max), int(max_tracers))
 
 
 def make_sheets(n_tracers, q, closed=None):
@@ -205,17 +212,18 @@ def sic_status_str(s: int) -> str:
 
 
 def sic_init(L, n_cells, dt, n_tracers, q, closed, x0, v0, precision=SIC_FP64, history_rows=0, stream=None,
-             deposit_order=0):
+             deposit_order=0, seg_charges=None, l_max=0.0, max_tracers=0):
     """Creates a simulation (see sic_init in include/sic.h); returns the handle."""
     lib = load()
-    cfg = make_config(L, n_cells, dt, precision, history_rows, deposit_order)
+    cfg = make_config(L, n_cells, dt, precision, history_rows, deposit_order, l_max, max_tracers)
     sheets = make_sheets(n_tracers, q, closed)
     px, kx, kx_ = _as_f64(x0)
     pv, kv, kv_ = _as_f64(v0)
-    if kx != kv:
-        raise ValueError("x0 and v0 must live in the same memory")
+    pc, kc, kc_ = _as_f64(seg_charges) if seg_charges is not None else (None, kx, None)
+    if kx != kv or kx != kc:
+        raise ValueError("x0, v0 and seg_charges must live in the same memory")
     h = ctypes.c_void_p()
-    rc = lib.sic_init(ctypes.byref(cfg), sheets, len(sheets), px, pv, kx, _stream_ptr(stream), ctypes.byref(h))
+    rc = lib.sic_init(ctypes.byref(cfg), sheets, len(sheets), px, pv, pc, kx, _stream_ptr(stream), ctypes.byref(h))
     _check(rc, "sic_init")
     return h
 
@@ -280,6 +288,41 @@ def sic_set_state(h, step: int, x, v_half):
     _check(lib.sic_set_state(h, int(step), px, pv, kx), "sic_set_state", h)
 
 
+def sic_refine(h, l_max: float) -> int:
+    """One refinement pass; returns the number of tracers inserted."""
+    n = ctypes.c_int64(0)
+    _check(load().sic_refine(h, float(l_max), ctypes.byref(n)), "sic_refine", h)
+    return n.value
+
+
+def sic_get_layout(h, n_sheets: int):
+    """(tracers per sheet, total)."""
+    nt = np.zeros(int(n_sheets), dtype=np.int32)
+    tot = ctypes.c_int64(0)
+    _check(load().sic_get_layout(h, nt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tot)), "sic_get_layout", h)
+    return nt, tot.value
+
+
+def sic_get_charges(h, n_tracers_total: int, out=None):
+    if out is None:
+        out = np.zeros(int(n_tracers_total))
+    pc, kc, _ = _as_f64(out)
+    _check(load().sic_get_charges(h, pc, kc), "sic_get_charges", h)
+    return out
+
+
+def sic_load_state(h, step: int, n_tracers, x, v_half, seg_charges=None):
+    lib = load()
+    nt = np.ascontiguousarray(n_tracers, dtype=np.int32)
+    px, kx, kx_ = _as_f64(x)
+    pv, kv, kv_ = _as_f64(v_half)
+    pc, kc, kc_ = _as_f64(seg_charges) if seg_charges is not None else (None, kx, None)
+    if kx != kv or kx != kc:
+        raise ValueError("x, v_half and seg_charges must live in the same memory")
+    _check(lib.sic_load_state(h, int(step), nt.ctypes.data_as(ctypes.c_void_p), px, pv, pc, kx), "sic_load_state",
+           h)
+
+
 def sic_destroy(h):
     if h:
         load().sic_destroy(h)
@@ -320,26 +363,30 @@ def sic_copy_bandwidth(n_bytes: int, iters: int = 5, stream=None) -> float:
 # ------------------------------------------------------------------ batch
 
 def sic_batch_create(budget_tracers, max_slots, max_cells, precision=SIC_FP64, history_rows=0, stream=None,
-                     deposit_order=0):
+                     deposit_order=0, flags=0):
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     h = ctypes.c_void_p()
     rc = load().sic_batch_create(int(budget_tracers), int(max_slots), int(max_cells), int(precision),
-                                 int(deposit_order), int(history_rows), _stream_ptr(stream), ctypes.byref(h))
+                                 int(deposit_order), int(flags), int(history_rows), _stream_ptr(stream),
+                                 ctypes.byref(h))
     _check(rc, "sic_batch_create")
     return h
 
 
 def sic_batch_admit(b, L, n_cells, dt, n_tracers, q, closed, x0, v0, n_steps, precision=SIC_FP64,
-                    raise_busy=True, deposit_order=0):
+                    raise_busy=True, deposit_order=0, seg_charges=None):
     """Returns the slot, or None when the batch is full (SIC_EBUSY) and raise_busy is False."""
     lib = load()
     cfg = make_config(L, n_cells, dt, precision, deposit_order=deposit_order)
     sheets = make_sheets(n_tracers, q, closed)
     px, kx, kx_ = _as_f64(x0)
     pv, kv, kv_ = _as_f64(v0)
+    pc, kc, kc_ = _as_f64(seg_charges) if seg_charges is not None else (None, kx, None)
+    if kx != kv or kx != kc:
+        raise ValueError("x0, v0 and seg_charges must live in the same memory")
     slot = ctypes.c_int32(-1)
-    rc = lib.sic_batch_admit(b, ctypes.byref(cfg), sheets, len(sheets), px, pv, kx, int(n_steps),
+    rc = lib.sic_batch_admit(b, ctypes.byref(cfg), sheets, len(sheets), px, pv, pc, kx, int(n_steps),
                              ctypes.byref(slot))
     if rc == 5 and not raise_busy:
         return None
@@ -394,6 +441,14 @@ def sic_batch_get_state(b, slot: int, n_tracers_total: int, out_x=None, out_v=No
     _check(lib.sic_batch_get_state(b, int(slot), px, pv, ctypes.byref(step), kx), "sic_batch_get_state", b,
            batch=True)
     return out_x, out_v, step.value
+
+
+def sic_batch_get_charges(b, slot: int, n_tracers_total: int, out=None):
+    if out is None:
+        out = np.zeros(int(n_tracers_total))
+    pc, kc, _ = _as_f64(out)
+    _check(load().sic_batch_get_charges(b, int(slot), pc, kc), "sic_batch_get_charges", b, batch=True)
+    return out
 
 
 def sic_batch_release(b, slot: int):
@@ -454,16 +509,39 @@ class Simulation:
     """Owns one sic_sim handle for an ``inputs.Problem``-like object."""
 
     def __init__(self, problem, precision=SIC_FP64, history_rows=0, stream=None, x0=None, v0=None,
-                 deposit_order=0):
+                 deposit_order=0, seg_charges=None, l_max=0.0, max_tracers=0):
         self.problem = problem
         self.n = int(np.sum(problem.n_tracers, dtype=np.int64))
+        if seg_charges is None:
+            seg_charges = getattr(problem, "c_full", None)
         self.h = sic_init(problem.L, problem.n_cells, problem.dt, problem.n_tracers, problem.q, problem.closed,
                           problem.x0 if x0 is None else x0, problem.v0 if v0 is None else v0,
                           precision=precision, history_rows=history_rows, stream=stream,
-                          deposit_order=deposit_order)
+                          deposit_order=deposit_order, seg_charges=seg_charges, l_max=l_max,
+                          max_tracers=max_tracers)
 
     def step(self, n):
         sic_step(self.h, n)
+        self._refresh_count()
+
+    def _refresh_count(self):
+        """Tracer total after refinement may have grown the sheets."""
+        _, self.n = sic_get_layout(self.h, len(self.problem.n_tracers))
+
+    def layout(self):
+        return sic_get_layout(self.h, len(self.problem.n_tracers))
+
+    def refine(self, l_max):
+        added = sic_refine(self.h, l_max)
+        self._refresh_count()
+        return added
+
+    def charges(self):
+        return sic_get_charges(self.h, self.n)
+
+    def load_state(self, step, n_tracers, x, v, seg_charges=None):
+        sic_load_state(self.h, step, n_tracers, x, v, seg_charges)
+        self.n = int(np.sum(n_tracers, dtype=np.int64))
 
     def deposit(self):
         sic_deposit(self.h)

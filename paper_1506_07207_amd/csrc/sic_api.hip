@@ -92,6 +92,12 @@ struct SlotHost {
   int32_t n_cells = 0;
   double L = 0.0, dt = 0.0;
   int64_t n_tracers = 0;
+  // sheets as they are now (refinement grows n_tracers_s)
+  std::vector<int32_t> n_tracers_s, closed_s;
+  std::vector<double> q_s;
+  double q_scale = 1.0;   // fixed-point units per unit charge (split forms)
+  double l_max = 0.0;     // refinement length; 0: off
+  int64_t max_tracers = 0;
   int32_t chunk_begin = 0, n_chunks = 0;
   int32_t item_begin = 0, n_items = 0;
   std::vector<int64_t> chunk_in_off;
@@ -105,7 +111,8 @@ struct SlotHost {
 
 struct Pool {
   int prec = 0;
-  int order = 0;  // deposit order: 0 piecewise-constant, 1 piecewise-linear segments
+  int order = 0;  // deposit order: 0 piecewise-constant, 1 piecewise-linear, 2 first-order weighting
+  bool seg = false;  // per-segment charges
   bool batch = false;
   hipStream_t stream = nullptr;  // caller's stream
   hipStream_t cap = nullptr;     // private capture stream
@@ -134,6 +141,17 @@ struct Pool {
   DiagRow *hist = nullptr;
   int32_t *done = nullptr;
   int32_t *slot_ids = nullptr;
+  uint64_t *segq = nullptr;      // per slot (seg)
+  uint64_t *cedge = nullptr;     // 2 per chunk (seg)
+  int64_t *edge_prev = nullptr;  // per chunk (seg)
+  // refinement scratch (allocated on first use)
+  int32_t *ref_cnt = nullptr;
+  uint64_t *ref_mask = nullptr;
+  int64_t *ref_off = nullptr;
+  uint64_t *ref_w = nullptr;
+  double *ref_v = nullptr;
+  uint64_t *ref_c = nullptr;
+  int64_t ref_stage_cap = 0;
 
   std::vector<SlotHost> slots;
   ChunkAllocator alloc;       // tracer chunks
@@ -207,17 +225,20 @@ void pool_free(Pool *p) {
   destroy_graphs(p);
   for (auto &s : p->slots)
     if (s.d_in_off) hipFree(s.d_in_off);
-  void *bufs[] = {p->xs,       p->vs,       p->halo[0],    p->halo[1], p->halo3[0], p->halo3[1], p->links,
-                  p->chunks,   p->items,    p->n_items,    p->inst,    p->slot_items, p->partials, p->meshP,
-                  p->meshD,    p->meshR,    p->meshE,      p->meshRho, p->hist,     p->done,     p->slot_ids};
+  void *bufs[] = {p->xs,        p->vs,       p->halo[0],  p->halo[1],  p->halo3[0],  p->halo3[1],
+                  p->links,     p->chunks,   p->items,    p->n_items,  p->inst,      p->slot_items,
+                  p->partials,  p->meshP,    p->meshD,    p->meshR,    p->meshE,     p->meshRho,
+                  p->hist,      p->done,     p->slot_ids, p->segq,     p->cedge,     p->edge_prev,
+                  p->ref_cnt,   p->ref_mask, p->ref_off,  p->ref_w,    p->ref_v,     p->ref_c};
   for (void *b : bufs)
     if (b) hipFree(b);
   if (p->cap) hipStreamDestroy(p->cap);
   delete p;
 }
 
-sic_status pool_create(int prec, int order, bool batch, int32_t slot_cap, int32_t max_cells, int64_t chunk_cap,
-                       int64_t hist_rows, int64_t budget, void *stream, Pool **out, std::string *err) {
+sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_cap, int32_t max_cells,
+                       int64_t chunk_cap, int64_t hist_rows, int64_t budget, void *stream, Pool **out,
+                       std::string *err) {
   if (chunk_cap >= ((int64_t)1 << 29)) {  // chunk links pack a chunk index into 29 bits
     if (err) *err = "tracer arena too large";
     g_last_error = "tracer arena too large";
@@ -226,6 +247,7 @@ sic_status pool_create(int prec, int order, bool batch, int32_t slot_cap, int32_
   Pool *p = new Pool();
   p->prec = prec;
   p->order = order;
+  p->seg = seg;
   p->batch = batch;
   p->stream = (hipStream_t)stream;
   p->slot_cap = slot_cap;
@@ -234,7 +256,7 @@ sic_status pool_create(int prec, int order, bool batch, int32_t slot_cap, int32_
   p->item_cap = chunk_cap / kMinTile + slot_cap + 1;
   p->hist_rows = hist_rows;
   p->budget = budget;
-  p->lds_bytes = tracer_lds_size(prec, order, max_cells, kMaxTile);
+  p->lds_bytes = tracer_lds_size(prec, order, seg, max_cells, kMaxTile);
   p->slots.resize(slot_cap);
   p->slot_items_h.assign(slot_cap, make_int2(0, 0));
   p->alloc.init(chunk_cap);
@@ -261,6 +283,11 @@ sic_status pool_create(int prec, int order, bool batch, int32_t slot_cap, int32_
     ALLOC(p->halo3[1], 3 * (size_t)chunk_cap);
   }
   ALLOC(p->chunks, (size_t)chunk_cap);
+  if (seg) {
+    ALLOC(p->segq, slotsz);
+    ALLOC(p->cedge, 2 * (size_t)chunk_cap);
+    ALLOC(p->edge_prev, (size_t)chunk_cap);
+  }
   ALLOC(p->items, (size_t)p->item_cap);
   ALLOC(p->n_items, 1);
   ALLOC(p->inst, (size_t)slot_cap);
@@ -307,7 +334,7 @@ sic_status pool_create(int prec, int order, bool batch, int32_t slot_cap, int32_
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return bail(std::string("init copy: ") + hipGetErrorString(e), SIC_EDEVICE);
   if (p->lds_bytes > 65536) {
-    int le = set_tracer_lds_limit(prec, order, p->lds_bytes);
+    int le = set_tracer_lds_limit(prec, order, seg, p->lds_bytes);
     if (le != 0) return bail(std::string("LDS limit: ") + hipGetErrorString((hipError_t)le), SIC_ENOTSUP);
   }
   *out = p;
@@ -568,6 +595,8 @@ TracerArgs tracer_args(Pool *p, int mode, int slot) {
   a.meshD = p->meshD;
   a.meshE = p->meshE;
   a.partials = p->partials + first;
+  a.segq = p->segq;
+  a.cedge = p->cedge;
   a.mesh_cells = p->max_cells;
   a.tile_cap = p->tile;
   a.respect_active = (p->batch && !one) ? 1 : 0;
@@ -600,8 +629,8 @@ int grid_for(Pool *p, int slot) {
 
 sic_status launch_tracer_mode(Pool *p, int mode, int slot, hipStream_t st) {
   TracerArgs a = tracer_args(p, mode, slot);
-  const size_t lds = tracer_lds_size(p->prec, p->order, p->max_cells, p->tile);
-  LAUNCHCHK(p, launch_tracers(p->prec, mode, p->order, a, grid_for(p, slot), p->block, lds, st));
+  const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
+  LAUNCHCHK(p, launch_tracers(p->prec, mode, p->order, p->seg, a, grid_for(p, slot), p->block, lds, st));
   return SIC_OK;
 }
 
@@ -710,6 +739,8 @@ sic_status validate(Pool *p, const sic_config *cfg, const sic_sheet *sheets, int
   if (cfg->deposit_order < 0 || cfg->deposit_order > 2)
     return fail(p, SIC_ENOTSUP, "deposit_order must be 0 (constant), 1 (linear segments) or 2 (first-order weighting)");
   if (cfg->history_rows < 0) return fail(p, SIC_EINVAL, "history_rows < 0");
+  if (!(cfg->l_max >= 0.0) || !finite(cfg->l_max)) return fail(p, SIC_EINVAL, "l_max must be >= 0 and finite");
+  if (cfg->max_tracers < 0) return fail(p, SIC_EINVAL, "max_tracers < 0");
   if (n_sheets < 1) return fail(p, SIC_EINVAL, "need at least one sheet");
   for (int32_t s = 0; s < n_sheets; ++s) {
     if (sheets[s].n_tracers < 2) return fail(p, SIC_EINVAL, "every sheet needs at least 2 tracers");
@@ -725,23 +756,177 @@ bool all_finite_host(const double *a, int64_t n) {
   return true;
 }
 
+// Chunk layout of one slot's sheets from chunk cb on: descriptors, input
+// offsets, piecewise-linear links and the slot of the tracer before each
+// chunk (charge edges).
+struct Layout {
+  std::vector<ChunkDesc> cd;
+  std::vector<int64_t> in_off;
+  std::vector<int2> links;
+  std::vector<int64_t> prev;
+};
+
+int64_t chunks_for(const std::vector<int32_t> &nt) {
+  int64_t n = 0;
+  for (int32_t t : nt) n += (t + kChunk - 1) / kChunk;
+  return n;
+}
+
+void build_layout(int32_t slot, int64_t cb, const std::vector<int32_t> &nt, const std::vector<int32_t> &closed,
+                  const std::vector<double> &q, double q_scale, bool fixed, Layout *L) {
+  const int64_t n_ch = chunks_for(nt);
+  L->cd.assign((size_t)n_ch, ChunkDesc{});
+  L->in_off.assign((size_t)n_ch, 0);
+  L->links.assign((size_t)n_ch, make_int2(-1, -1));
+  L->prev.assign((size_t)n_ch, -1);
+  int64_t c = 0, in = 0;
+  for (size_t s = 0; s < nt.size(); ++s) {
+    const int32_t n = nt[s];
+    const int32_t nch = (n + kChunk - 1) / kChunk;
+    const int64_t first = cb + c;
+    const bool cl = closed[s] != 0;
+    for (int32_t k = 0; k < nch; ++k) {
+      ChunkDesc &d = L->cd[(size_t)(c + k)];
+      d.q = q[s];
+      d.q_fix = fixed ? (int64_t)std::llrint(q[s] * q_scale) : 0;
+      d.n_valid = std::min(kChunk, n - k * kChunk);
+      d.inst = slot;
+      d.flags = (k == 0 && !cl) ? kChunkOpenStart : 0;
+      if (k + 1 < nch) d.partner = (int32_t)(first + k + 1);
+      else d.partner = cl ? (int32_t)first : -1;
+      L->in_off[(size_t)(c + k)] = in + (int64_t)k * kChunk;
+      // the tracer before this chunk's first: the previous chunk's last, or
+      // for a closed sheet's first chunk the sheet's last tracer
+      if (k > 0) L->prev[(size_t)(c + k)] = (first + k - 1) * kChunk + (kChunk - 1);
+      else if (cl) L->prev[(size_t)(c + k)] = (first + nch - 1) * kChunk + (n - (nch - 1) * kChunk - 1);
+    }
+    // Links to the tracer before each chunk and the one two past its end
+    // (piecewise-linear segments); a closed sheet of fewer than 3 tracers has
+    // no gradient, so it gets no links.
+    const bool grad = !cl || n >= 3;
+    for (int32_t k = 0; k < nch && grad; ++k) {
+      int2 &lk = L->links[(size_t)(c + k)];
+      if (k > 0) lk.x = (int32_t)(((first + k - 1) << 2) | kHaloLast);
+      else if (cl) lk.x = (int32_t)(((first + nch - 1) << 2) | kHaloLast);
+      const int32_t P = L->cd[(size_t)(c + k)].partner;
+      if (P >= 0) {
+        const int64_t pk = P - first;
+        if (L->cd[(size_t)(c + pk)].n_valid >= 2) lk.y = (P << 2) | kHaloSecond;
+        else {
+          const int32_t PP = L->cd[(size_t)(c + pk)].partner;
+          if (PP >= 0) lk.y = (PP << 2) | kHaloFirst;
+        }
+      }
+    }
+    c += nch;
+    in += n;
+  }
+}
+
+// Uploads a layout for chunks [cb, cb + n) of a slot (ordered on the stream).
+hipError_t upload_layout(Pool *p, SlotHost &sh, int64_t cb, const Layout &L) {
+  const size_t n = L.cd.size();
+  hipError_t e = hipSuccess;
+  if (sh.d_in_off) hipFree(sh.d_in_off);
+  sh.d_in_off = nullptr;
+  e = hipMalloc((void **)&sh.d_in_off, sizeof(int64_t) * std::max<size_t>(n, 1));
+  if (e != hipSuccess) {
+    sh.d_in_off = nullptr;
+    return e;
+  }
+  e = hipMemcpyAsync(p->chunks + cb, L.cd.data(), sizeof(ChunkDesc) * n, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sh.d_in_off, L.in_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->links + cb, L.links.data(), sizeof(int2) * n, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess && p->seg)
+    e = hipMemcpyAsync(p->edge_prev + cb, L.prev.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, p->stream);
+  return e;
+}
+
+// Places a slot's tracers from flat sheet-major inputs: float64 positions or
+// raw state words, velocities, and per-segment charges (float64, raw words,
+// or none: the sheet charges); then the charge edges.  keep_charges leaves
+// the charge words as they are (same layout, new positions).
+int ingest_slot(Pool *p, int32_t slot, const double *x, const uint64_t *w, const double *v, const double *c,
+                const uint64_t *cw, bool keep_charges = false) {
+  SlotHost &sh = p->slots[slot];
+  IngestArgs ia;
+  ia.x_in = x;
+  ia.w_in = w;
+  ia.v_in = v;
+  ia.c_in = c;
+  ia.cw_in = cw;
+  ia.segq = keep_charges ? nullptr : p->segq;
+  ia.q_scale = sh.q_scale;
+  ia.chunk_in_off = sh.d_in_off;
+  ia.chunk_begin = sh.chunk_begin;
+  ia.n_chunks = sh.n_chunks;
+  ia.chunks = p->chunks;
+  ia.inst = p->inst;
+  ia.xs = p->xs;
+  ia.vs = p->vs;
+  ia.halo = p->halo[p->parity];
+  ia.halo3 = p->halo3[p->parity];
+  int le = launch_ingest(p->prec, ia, p->stream);
+  if (le == 0 && p->seg && !keep_charges)
+    le = launch_charge_edges(p->chunks, p->edge_prev, p->segq, p->cedge, sh.chunk_begin, sh.n_chunks, p->stream);
+  return le;
+}
+
+// Sum of |charge| over the segments (fixed-point scale of the split forms).
+double total_abs_charge(const sic_sheet *sheets, int32_t n_sheets, const double *c_host) {
+  double total = 0.0;
+  int64_t base = 0;
+  for (int32_t s = 0; s < n_sheets; ++s) {
+    const int32_t nt = sheets[s].n_tracers;
+    const int32_t nseg = sheets[s].closed ? nt : nt - 1;
+    if (c_host) {
+      for (int32_t t = 0; t < nseg; ++t) total += std::fabs(c_host[base + t]);
+    } else {
+      total += std::fabs(sheets[s].q_seg) * (double)nseg;
+    }
+    base += nt;
+  }
+  return total;
+}
+
 // Admits one simulation into a free slot and ingests it (see sic_init).
 sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
-                      const double *v0, int32_t mem_kind, int64_t n_steps, int32_t *slot_out) {
+                      const double *v0, const double *c0, int32_t mem_kind, int64_t n_steps, int32_t *slot_out) {
   sic_status st = validate(p, cfg, sheets, n_sheets, x0, v0);
   if (st != SIC_OK) return st;
   if (cfg->precision != p->prec) return fail(p, SIC_EINVAL, "precision differs from the batch precision");
   if (cfg->deposit_order != p->order) return fail(p, SIC_EINVAL, "deposit_order differs from the batch's");
   if (cfg->n_cells > p->max_cells) return fail(p, SIC_EINVAL, "n_cells above the batch max_cells");
   if (mem_kind != SIC_MEM_HOST && mem_kind != SIC_MEM_DEVICE) return fail(p, SIC_EINVAL, "bad mem_kind");
+  if (c0 && !p->seg) return fail(p, SIC_ENOTSUP, "per-segment charges need a batch created for them");
+  if (p->batch && cfg->l_max != 0.0) return fail(p, SIC_ENOTSUP, "refinement is for single simulations");
 
-  int64_t n_tr = 0, n_ch = 0;
+  int64_t n_tr = 0;
+  std::vector<int32_t> nt((size_t)n_sheets), closed((size_t)n_sheets);
+  std::vector<double> q((size_t)n_sheets);
   for (int32_t s = 0; s < n_sheets; ++s) {
+    nt[(size_t)s] = sheets[s].n_tracers;
+    closed[(size_t)s] = sheets[s].closed;
+    q[(size_t)s] = sheets[s].q_seg;
     n_tr += sheets[s].n_tracers;
-    n_ch += (sheets[s].n_tracers + kChunk - 1) / kChunk;
   }
+  const int64_t n_ch = chunks_for(nt);
   if (mem_kind == SIC_MEM_HOST && (!all_finite_host(x0, n_tr) || !all_finite_host(v0, n_tr)))
     return fail(p, SIC_EINVAL, "non-finite initial position or velocity");
+  // per-segment charges on the host (finiteness, fixed-point scale)
+  std::vector<double> c_host;
+  if (c0) {
+    if (mem_kind == SIC_MEM_HOST) {
+      c_host.assign(c0, c0 + n_tr);
+    } else {
+      c_host.resize((size_t)n_tr);
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+      HIPCHK(p, hipMemcpy(c_host.data(), c0, sizeof(double) * (size_t)n_tr, hipMemcpyDeviceToHost));
+    }
+    if (!all_finite_host(c_host.data(), n_tr)) return fail(p, SIC_EINVAL, "non-finite segment charge");
+  }
   int32_t slot = -1;
   for (int32_t i = 0; i < p->slot_cap; ++i)
     if (!p->slots[i].live) {
@@ -753,12 +938,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   const int64_t cb = p->alloc.alloc(n_ch);
   if (cb < 0) return fail(p, SIC_EBUSY, "tracer arena full");
 
-  // chunk descriptors
-  double total_abs = 0.0;
-  for (int32_t s = 0; s < n_sheets; ++s) {
-    const int64_t nseg = sheets[s].closed ? sheets[s].n_tracers : sheets[s].n_tracers - 1;
-    total_abs += std::fabs(sheets[s].q_seg) * (double)nseg;
-  }
+  const double total_abs = total_abs_charge(sheets, n_sheets, c0 ? c_host.data() : nullptr);
   double q_unit = 1.0, q_scale = 1.0;
   if (p->prec != kFP64) {
     // fixed point: total |charge| just under 2^62 units
@@ -768,64 +948,21 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
     q_scale = std::ldexp(1.0, S);
     q_unit = std::ldexp(1.0, -S);
   }
-  std::vector<ChunkDesc> cd((size_t)n_ch);
   SlotHost &sh = p->slots[slot];
-  sh.chunk_in_off.assign((size_t)n_ch, 0);
-  {
-    int64_t c = 0, in = 0;
-    for (int32_t s = 0; s < n_sheets; ++s) {
-      const int32_t nt = sheets[s].n_tracers;
-      const int32_t nch = (nt + kChunk - 1) / kChunk;
-      const int64_t first = cb + c;
-      for (int32_t k = 0; k < nch; ++k) {
-        ChunkDesc &d = cd[(size_t)(c + k)];
-        d.q = sheets[s].q_seg;
-        d.q_fix = p->prec != kFP64 ? (int64_t)std::llrint(sheets[s].q_seg * q_scale) : 0;
-        d.n_valid = std::min(kChunk, nt - k * kChunk);
-        d.inst = slot;
-        d.pad = 0;
-        if (k + 1 < nch) d.partner = (int32_t)(first + k + 1);
-        else d.partner = sheets[s].closed ? (int32_t)first : -1;
-        sh.chunk_in_off[(size_t)(c + k)] = in + (int64_t)k * kChunk;
-      }
-      c += nch;
-      in += nt;
-    }
-  }
-  // Links to the tracer before each chunk and the one two past its end
-  // (piecewise-linear segments); a closed sheet of fewer than 3 tracers has
-  // no gradient, so it gets no links.
-  std::vector<int2> lk((size_t)n_ch, make_int2(-1, -1));
-  {
-    int64_t c = 0;
-    for (int32_t s = 0; s < n_sheets; ++s) {
-      const int32_t nt = sheets[s].n_tracers;
-      const int32_t nch = (nt + kChunk - 1) / kChunk;
-      const int32_t first = (int32_t)(cb + c);
-      const bool closed = sheets[s].closed != 0;
-      const bool grad = !closed || nt >= 3;
-      for (int32_t k = 0; k < nch && grad; ++k) {
-        int2 &L = lk[(size_t)(c + k)];
-        if (k > 0) L.x = ((first + k - 1) << 2) | kHaloLast;
-        else if (closed) L.x = ((first + nch - 1) << 2) | kHaloLast;
-        const int32_t P = cd[(size_t)(c + k)].partner;
-        if (P >= 0) {
-          const int32_t pk = P - first;
-          if (cd[(size_t)(c + pk)].n_valid >= 2) L.y = (P << 2) | kHaloSecond;
-          else {
-            const int32_t PP = cd[(size_t)(c + pk)].partner;
-            if (PP >= 0) L.y = (PP << 2) | kHaloFirst;
-          }
-        }
-      }
-      c += nch;
-    }
-  }
+  Layout L;
+  build_layout(slot, cb, nt, closed, q, q_scale, p->prec != kFP64, &L);
+  sh.chunk_in_off = L.in_off;
   sh.live = true;
   sh.n_cells = cfg->n_cells;
   sh.L = cfg->L;
   sh.dt = cfg->dt;
   sh.n_tracers = n_tr;
+  sh.n_tracers_s = nt;
+  sh.closed_s = closed;
+  sh.q_s = q;
+  sh.q_scale = q_scale;
+  sh.l_max = cfg->l_max;
+  sh.max_tracers = std::max<int64_t>(cfg->max_tracers, n_tr);
   sh.chunk_begin = (int32_t)cb;
   sh.n_chunks = (int32_t)n_ch;
   sh.state = kStale;
@@ -861,22 +998,11 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
     undo();
     return st;
   }
-  hipError_t e = hipSuccess;
-  if (!sh.d_in_off) {
-    e = hipMalloc((void **)&sh.d_in_off, sizeof(int64_t) * (size_t)std::max<int64_t>(n_ch, 1));
-  } else {
-    hipFree(sh.d_in_off);
-    e = hipMalloc((void **)&sh.d_in_off, sizeof(int64_t) * (size_t)std::max<int64_t>(n_ch, 1));
-  }
-  if (e != hipSuccess) {
-    sh.d_in_off = nullptr;
-    undo();
-    return fail(p, SIC_ENOMEM, "hipMalloc chunk offsets");
-  }
   double *stage = nullptr;
-  const double *dx0 = x0, *dv0 = v0;
+  const double *dx0 = x0, *dv0 = v0, *dc0 = c0;
+  hipError_t e = hipSuccess;
   if (mem_kind == SIC_MEM_HOST) {
-    e = hipMalloc((void **)&stage, sizeof(double) * 2 * (size_t)n_tr);
+    e = hipMalloc((void **)&stage, sizeof(double) * (c0 ? 3 : 2) * (size_t)std::max<int64_t>(n_tr, 1));
     if (e != hipSuccess) {
       undo();
       return fail(p, SIC_ENOMEM, "hipMalloc staging");
@@ -884,18 +1010,14 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
     e = hipMemcpyAsync(stage, x0, sizeof(double) * (size_t)n_tr, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(stage + n_tr, v0, sizeof(double) * (size_t)n_tr, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess && c0)
+      e = hipMemcpyAsync(stage + 2 * n_tr, c0, sizeof(double) * (size_t)n_tr, hipMemcpyHostToDevice, p->stream);
     dx0 = stage;
     dv0 = stage + n_tr;
+    dc0 = c0 ? stage + 2 * n_tr : nullptr;
   }
   const int32_t zero = 0;
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->chunks + cb, cd.data(), sizeof(ChunkDesc) * (size_t)n_ch, hipMemcpyHostToDevice,
-                       p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(sh.d_in_off, sh.chunk_in_off.data(), sizeof(int64_t) * (size_t)n_ch, hipMemcpyHostToDevice,
-                       p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->links + cb, lk.data(), sizeof(int2) * (size_t)n_ch, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = upload_layout(p, sh, cb, L);
   if (e == hipSuccess) e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(p->done + slot, &zero, sizeof(zero), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -907,19 +1029,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   p->used_tracers += n_tr;
   p->used_slots += 1;
   // ingest: place tracers, deposit, solve, half back-kick
-  IngestArgs ia;
-  ia.x_in = dx0;
-  ia.v_in = dv0;
-  ia.chunk_in_off = sh.d_in_off;
-  ia.chunk_begin = (int32_t)cb;
-  ia.n_chunks = (int32_t)n_ch;
-  ia.chunks = p->chunks;
-  ia.inst = p->inst;
-  ia.xs = p->xs;
-  ia.vs = p->vs;
-  ia.halo = p->halo[p->parity];
-  ia.halo3 = p->halo3[p->parity];
-  int le = launch_ingest(p->prec, ia, p->stream);
+  int le = ingest_slot(p, slot, dx0, nullptr, dv0, dc0, nullptr);
   if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
   if (le != 0) {
     if (stage) hipFree(stage);
@@ -934,6 +1044,154 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("ingest: ") + hipGetErrorString(e));
   sh.state = kField;
   *slot_out = slot;
+  return SIC_OK;
+}
+
+// Replaces a single simulation's tracers with a new layout (refinement,
+// sic_load_state): nt[s] tracers per sheet from flat device inputs (float64
+// positions or raw state words; velocities; float64 charges, raw charge words
+// or none).  step >= 0 sets the step.  With redeposit the new state is
+// deposited and solved at once (the newest diagnostics row is rewritten);
+// otherwise the field becomes stale.  Synchronous.
+sic_status pool_relayout(Pool *p, int32_t slot, const std::vector<int32_t> &nt, const double *x, const uint64_t *w,
+                         const double *v, const double *c, const uint64_t *cw, int64_t step, bool redeposit) {
+  SlotHost &sh = p->slots[slot];
+  int64_t n_tr = 0;
+  for (int32_t t : nt) n_tr += t;
+  const int64_t n_ch = chunks_for(nt);
+  if (n_ch > p->chunk_cap || n_tr > sh.max_tracers)
+    return fail(p, SIC_ENOMEM, "refined or loaded state exceeds the tracer capacity");
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  const int tile0 = p->tile, grid0 = p->grid;
+  // a single simulation owns the whole arena: after the release the new
+  // range always fits
+  sic_status st = clear_slot_items(p, slot);
+  if (st != SIC_OK) return st;
+  p->alloc.release(sh.chunk_begin, sh.n_chunks);
+  const int64_t cb = p->alloc.alloc(n_ch);
+  if (cb < 0) return fail(p, SIC_EDEVICE, "tracer arena fragmented");
+  Layout L;
+  build_layout(slot, cb, nt, sh.closed_s, sh.q_s, sh.q_scale, p->prec != kFP64, &L);
+  p->used_tracers += n_tr - sh.n_tracers;
+  sh.n_tracers = n_tr;
+  sh.n_tracers_s = nt;
+  sh.chunk_in_off = L.in_off;
+  sh.chunk_begin = (int32_t)cb;
+  sh.n_chunks = (int32_t)n_ch;
+  st = place_slot_items(p, slot);
+  if (st != SIC_OK) return st;
+  // captured graphs carry the tile (LDS size) and grid of their capture
+  if (p->tile != tile0 || p->grid != grid0) destroy_graphs(p);
+  hipError_t e = upload_layout(p, sh, cb, L);
+  if (e == hipSuccess && step >= 0) {
+    InstDesc I;
+    e = hipMemcpyAsync(&I, p->inst + slot, sizeof(I), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    I.step = step;
+    if (e == hipSuccess) e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
+  }
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("re-layout copies: ") + hipGetErrorString(e));
+  int le = ingest_slot(p, slot, x, w, v, c, cw);
+  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
+  if (le != 0) return fail(p, SIC_EDEVICE, std::string("re-layout ingest: ") + hipGetErrorString((hipError_t)le));
+  sh.pending_push = sh.pending_dep = false;
+  if (redeposit) {
+    st = launch_tracer_mode(p, kDeposit, slot, p->stream);
+    if (st == SIC_OK) st = launch_solve_mode(p, kHaveDeposit, slot, p->stream);
+    if (st != SIC_OK) return st;
+    sh.state = kField;
+  } else {
+    sh.state = kStale;
+  }
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return SIC_OK;
+}
+
+sic_status ensure_refine_scratch(Pool *p, int64_t stage_tracers) {
+  if (!p->ref_cnt) {
+    HIPCHK(p, dalloc(&p->ref_cnt, (size_t)p->chunk_cap));
+    HIPCHK(p, dalloc(&p->ref_mask, (size_t)p->chunk_cap));
+    HIPCHK(p, dalloc(&p->ref_off, (size_t)p->chunk_cap));
+  }
+  if (stage_tracers > p->ref_stage_cap) {
+    if (p->ref_w) hipFree(p->ref_w);
+    if (p->ref_v) hipFree(p->ref_v);
+    if (p->ref_c) hipFree(p->ref_c);
+    p->ref_w = nullptr;
+    p->ref_v = nullptr;
+    p->ref_c = nullptr;
+    p->ref_stage_cap = 0;
+    HIPCHK(p, dalloc(&p->ref_w, (size_t)stage_tracers));
+    HIPCHK(p, dalloc(&p->ref_v, (size_t)stage_tracers));
+    HIPCHK(p, dalloc(&p->ref_c, (size_t)stage_tracers));
+    p->ref_stage_cap = stage_tracers;
+  }
+  return SIC_OK;
+}
+
+// One refinement pass over a single simulation (section 2.6).
+sic_status pool_refine(Pool *p, int32_t slot, double l_max, int64_t *inserted) {
+  if (inserted) *inserted = 0;
+  if (!p->seg || p->batch) return fail(p, SIC_ENOTSUP, "refinement needs a simulation with per-segment charges");
+  if (!(l_max > 0.0) || !std::isfinite(l_max)) return fail(p, SIC_EINVAL, "l_max must be positive and finite");
+  SlotHost &sh = p->slots[slot];
+  if (sh.state != kField) return fail(p, SIC_ESTATE, "refinement needs the field of the current step");
+  sic_status st = ensure_refine_scratch(p, 0);
+  if (st != SIC_OK) return st;
+  RefineArgs ra;
+  ra.chunks = p->chunks;
+  ra.inst = p->inst;
+  ra.xs = p->xs;
+  ra.vs = p->vs;
+  ra.segq = p->segq;
+  ra.chunk_begin = sh.chunk_begin;
+  ra.n_chunks = sh.n_chunks;
+  ra.l_max = l_max;
+  ra.cnt = p->ref_cnt;
+  ra.mask = p->ref_mask;
+  ra.out_off = p->ref_off;
+  ra.w_out = nullptr;
+  ra.v_out = nullptr;
+  ra.c_out = nullptr;
+  LAUNCHCHK(p, launch_refine_mark(p->prec, ra, p->stream));
+  std::vector<int32_t> cnt((size_t)sh.n_chunks);
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  HIPCHK(p, hipMemcpy(cnt.data(), p->ref_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost));
+  // new sheet sizes and the output offset of every chunk
+  std::vector<int32_t> nt = sh.n_tracers_s;
+  std::vector<int64_t> off((size_t)sh.n_chunks);
+  int64_t add = 0, out = 0;
+  {
+    int64_t c = 0;
+    for (size_t s = 0; s < nt.size(); ++s) {
+      const int32_t nch = (sh.n_tracers_s[s] + kChunk - 1) / kChunk;
+      int64_t sheet_add = 0;
+      for (int32_t k = 0; k < nch; ++k) {
+        off[(size_t)(c + k)] = out;
+        const int32_t nv = std::min(kChunk, sh.n_tracers_s[s] - k * kChunk);
+        out += nv + cnt[(size_t)(c + k)];
+        sheet_add += cnt[(size_t)(c + k)];
+      }
+      if ((int64_t)nt[s] + sheet_add > (int64_t)INT32_MAX) return fail(p, SIC_ENOMEM, "sheet too long");
+      nt[s] += (int32_t)sheet_add;
+      add += sheet_add;
+      c += nch;
+    }
+  }
+  if (add == 0) return SIC_OK;
+  const int64_t n_new = sh.n_tracers + add;
+  if (n_new > sh.max_tracers || chunks_for(nt) > p->chunk_cap)
+    return fail(p, SIC_ENOMEM, "refinement exceeds the tracer capacity");
+  st = ensure_refine_scratch(p, n_new);
+  if (st != SIC_OK) return st;
+  HIPCHK(p, hipMemcpyAsync(p->ref_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, p->stream));
+  ra.w_out = p->ref_w;
+  ra.v_out = p->ref_v;
+  ra.c_out = p->ref_c;
+  LAUNCHCHK(p, launch_refine_scatter(p->prec, ra, p->stream));
+  st = pool_relayout(p, slot, nt, nullptr, p->ref_w, p->ref_v, nullptr, p->ref_c, -1, true);
+  if (st != SIC_OK) return st;
+  if (inserted) *inserted = add;
   return SIC_OK;
 }
 
@@ -1020,8 +1278,10 @@ sic_status pool_get_state(Pool *p, int32_t slot, double *x, double *v, int64_t *
   ea.inst = p->inst;
   ea.xs = p->xs;
   ea.vs = p->vs;
+  ea.segq = p->segq;
   ea.x_out = dx;
   ea.v_out = dv;
+  ea.c_out = nullptr;
   int le = launch_extract(p->prec, ea, p->stream);
   hipError_t e = hipStreamSynchronize(p->stream);
   if (le == 0 && e == hipSuccess && stage && x)
@@ -1038,6 +1298,90 @@ sic_status pool_get_state(Pool *p, int32_t slot, double *x, double *v, int64_t *
     *step = I.step;
   }
   return SIC_OK;
+}
+
+sic_status pool_get_charges(Pool *p, int32_t slot, double *c, int32_t mem_kind) {
+  if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return fail(p, SIC_EINVAL, "slot not live");
+  if (!c || (mem_kind != SIC_MEM_HOST && mem_kind != SIC_MEM_DEVICE)) return fail(p, SIC_EINVAL, "bad arguments");
+  SlotHost &sh = p->slots[slot];
+  const size_t n = (size_t)sh.n_tracers;
+  if (!p->seg) {
+    // every segment carries its sheet's charge
+    std::vector<double> h(n);
+    size_t b = 0;
+    for (size_t s = 0; s < sh.n_tracers_s.size(); ++s) {
+      const size_t nt = (size_t)sh.n_tracers_s[s];
+      for (size_t t = 0; t < nt; ++t) h[b + t] = sh.q_s[s];
+      if (!sh.closed_s[s]) h[b + nt - 1] = 0.0;
+      b += nt;
+    }
+    if (mem_kind == SIC_MEM_HOST) std::memcpy(c, h.data(), sizeof(double) * n);
+    else HIPCHK(p, hipMemcpy(c, h.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    return SIC_OK;
+  }
+  double *stage = nullptr;
+  HIPCHK(p, hipMalloc((void **)&stage, sizeof(double) * 3 * std::max<size_t>(n, 1)));
+  ExtractArgs ea;
+  ea.chunk_in_off = sh.d_in_off;
+  ea.chunk_begin = sh.chunk_begin;
+  ea.n_chunks = sh.n_chunks;
+  ea.chunks = p->chunks;
+  ea.inst = p->inst;
+  ea.xs = p->xs;
+  ea.vs = p->vs;
+  ea.segq = p->segq;
+  ea.x_out = stage;
+  ea.v_out = stage + n;
+  ea.c_out = stage + 2 * n;
+  int le = launch_extract(p->prec, ea, p->stream);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (le == 0 && e == hipSuccess)
+    e = hipMemcpy(c, stage + 2 * n, sizeof(double) * n,
+                  mem_kind == SIC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice);
+  hipFree(stage);
+  if (le != 0) return fail(p, SIC_EDEVICE, std::string("extract: ") + hipGetErrorString((hipError_t)le));
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("get_charges: ") + hipGetErrorString(e));
+  return SIC_OK;
+}
+
+// sic_load_state: a new layout for a single simulation.
+sic_status pool_load_state(Pool *p, int64_t step, const int32_t *n_tracers, const double *x, const double *v,
+                           const double *c, int32_t mem_kind) {
+  SlotHost &sh = p->slots[0];
+  if (!n_tracers || !x || !v || step < 0) return fail(p, SIC_EINVAL, "bad state arguments");
+  if (mem_kind != SIC_MEM_HOST && mem_kind != SIC_MEM_DEVICE) return fail(p, SIC_EINVAL, "bad mem_kind");
+  if (c && !p->seg)
+    return fail(p, SIC_ENOTSUP, "per-segment charges need a simulation created with them (or with refinement)");
+  std::vector<int32_t> nt(sh.n_tracers_s.size());
+  int64_t n = 0;
+  for (size_t s = 0; s < nt.size(); ++s) {
+    nt[s] = n_tracers[s];
+    if (nt[s] < 2) return fail(p, SIC_EINVAL, "every sheet needs at least 2 tracers");
+    n += nt[s];
+  }
+  if (n > sh.max_tracers || chunks_for(nt) > p->chunk_cap)
+    return fail(p, SIC_ENOMEM, "state exceeds the tracer capacity");
+  if (mem_kind == SIC_MEM_HOST &&
+      (!all_finite_host(x, n) || !all_finite_host(v, n) || (c && !all_finite_host(c, n))))
+    return fail(p, SIC_EINVAL, "non-finite state");
+  double *stage = nullptr;
+  const double *dx = x, *dv = v, *dc = c;
+  if (mem_kind == SIC_MEM_HOST) {
+    HIPCHK(p, hipMalloc((void **)&stage, sizeof(double) * 3 * (size_t)std::max<int64_t>(n, 1)));
+    hipError_t e = hipMemcpy(stage, x, sizeof(double) * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(stage + n, v, sizeof(double) * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && c) e = hipMemcpy(stage + 2 * n, c, sizeof(double) * (size_t)n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      hipFree(stage);
+      return fail(p, SIC_EDEVICE, std::string("load_state copies: ") + hipGetErrorString(e));
+    }
+    dx = stage;
+    dv = stage + n;
+    dc = c ? stage + 2 * n : nullptr;
+  }
+  sic_status st = pool_relayout(p, 0, nt, dx, nullptr, dv, dc, nullptr, step, false);
+  if (stage) hipFree(stage);
+  return st;
 }
 
 sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, const double *v,
@@ -1061,19 +1405,8 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
     dv = stage + sh.n_tracers;
   }
   hipError_t e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
-  IngestArgs ia;
-  ia.x_in = dx;
-  ia.v_in = dv;
-  ia.chunk_in_off = sh.d_in_off;
-  ia.chunk_begin = sh.chunk_begin;
-  ia.n_chunks = sh.n_chunks;
-  ia.chunks = p->chunks;
-  ia.inst = p->inst;
-  ia.xs = p->xs;
-  ia.vs = p->vs;
-  ia.halo = p->halo[p->parity];
-  ia.halo3 = p->halo3[p->parity];
-  int le = (e == hipSuccess) ? launch_ingest(p->prec, ia, p->stream) : 0;
+  // positions and velocities only: the layout and the charges stay
+  int le = (e == hipSuccess) ? ingest_slot(p, slot, dx, nullptr, dv, nullptr, nullptr, true) : 0;
   if (le == 0 && e == hipSuccess)
     le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
   hipError_t e2 = hipStreamSynchronize(p->stream);
@@ -1125,6 +1458,17 @@ sic_status sim_step(Pool *p, int64_t n) {
   if (sh.state == kStale) st = sim_deposit(p);
   if (st == SIC_OK && sh.state == kDeposited) st = sim_solve(p);
   if (st != SIC_OK) return st;
+  if (sh.l_max > 0.0) {
+    // refinement after every move: the fused step deposits the moved
+    // tracers; when a segment is split the refined state is deposited and
+    // solved again, so the step's field and row are those of the refined
+    // sheets
+    for (int64_t i = 0; i < n && st == SIC_OK; ++i) {
+      st = run_fused(p, 1);
+      if (st == SIC_OK) st = pool_refine(p, 0, sh.l_max, nullptr);
+    }
+    return st;
+  }
   return run_fused(p, n);
 }
 
@@ -1166,20 +1510,28 @@ int32_t sic_abi_version(void) { return SIC_ABI_VERSION; }
 const char *sic_status_str(sic_status s) { return status_str(s); }
 
 sic_status sic_init(const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets, const double *x0,
-                    const double *v0, int32_t mem_kind, void *hip_stream, sic_sim **out) {
+                    const double *v0, const double *seg_charges, int32_t mem_kind, void *hip_stream,
+                    sic_sim **out) {
   if (!out) return SIC_EINVAL;
   *out = nullptr;
   sic_status st = validate(nullptr, cfg, sheets, n_sheets, x0, v0);
   if (st != SIC_OK) return st;
-  int64_t n_ch = 0;
-  for (int32_t s = 0; s < n_sheets; ++s) n_ch += (sheets[s].n_tracers + kChunk - 1) / kChunk;
+  int64_t n_ch = 0, n_tr = 0;
+  for (int32_t s = 0; s < n_sheets; ++s) {
+    n_ch += (sheets[s].n_tracers + kChunk - 1) / kChunk;
+    n_tr += sheets[s].n_tracers;
+  }
+  // room to grow: every sheet may end in a partly filled chunk
+  if (cfg->max_tracers > n_tr) n_ch = std::max<int64_t>(n_ch, (cfg->max_tracers + kChunk - 1) / kChunk + n_sheets);
   const int64_t rows = cfg->history_rows > 0 ? std::max<int64_t>(2, cfg->history_rows) : 65536;
+  const bool seg = seg_charges != nullptr || cfg->l_max > 0.0;
   Pool *p = nullptr;
   std::string err;
-  st = pool_create(cfg->precision, cfg->deposit_order, false, 1, cfg->n_cells, n_ch, rows, 0, hip_stream, &p, &err);
+  st = pool_create(cfg->precision, cfg->deposit_order, seg, false, 1, cfg->n_cells, n_ch, rows, 0, hip_stream, &p,
+                   &err);
   if (st != SIC_OK) return st;
   int32_t slot = -1;
-  st = pool_admit(p, cfg, sheets, n_sheets, x0, v0, mem_kind, -1, &slot);
+  st = pool_admit(p, cfg, sheets, n_sheets, x0, v0, seg_charges, mem_kind, -1, &slot);
   if (st != SIC_OK) {
     pool_free(p);
     return st;
@@ -1226,6 +1578,30 @@ sic_status sic_set_state(sic_sim *sim, int64_t step, const double *x, const doub
   return pool_set_state(sim->pool, 0, step, x, v_half, mem_kind);
 }
 
+sic_status sic_refine(sic_sim *sim, double l_max, int64_t *inserted) {
+  if (!sim) return SIC_EINVAL;
+  return pool_refine(sim->pool, 0, l_max, inserted);
+}
+
+sic_status sic_get_layout(const sic_sim *sim, int32_t *n_tracers_out, int64_t *total) {
+  if (!sim) return SIC_EINVAL;
+  const SlotHost &sh = sim->pool->slots[0];
+  if (n_tracers_out) std::memcpy(n_tracers_out, sh.n_tracers_s.data(), sizeof(int32_t) * sh.n_tracers_s.size());
+  if (total) *total = sh.n_tracers;
+  return SIC_OK;
+}
+
+sic_status sic_get_charges(sic_sim *sim, double *seg_charges, int32_t mem_kind) {
+  if (!sim) return SIC_EINVAL;
+  return pool_get_charges(sim->pool, 0, seg_charges, mem_kind);
+}
+
+sic_status sic_load_state(sic_sim *sim, int64_t step, const int32_t *n_tracers, const double *x,
+                          const double *v_half, const double *seg_charges, int32_t mem_kind) {
+  if (!sim) return SIC_EINVAL;
+  return pool_load_state(sim->pool, step, n_tracers, x, v_half, seg_charges, mem_kind);
+}
+
 void sic_destroy(sic_sim *sim) {
   if (!sim) return;
   pool_free(sim->pool);
@@ -1263,10 +1639,12 @@ sic_status sic_last_timing(const sic_sim *sim, double *tracer_ms, double *solve_
 
 // ---- batch ----
 sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t max_cells, int32_t precision,
-                            int32_t deposit_order, int64_t history_rows, void *hip_stream, sic_batch **out) {
+                            int32_t deposit_order, int32_t flags, int64_t history_rows, void *hip_stream,
+                            sic_batch **out) {
   if (!out) return SIC_EINVAL;
   *out = nullptr;
   if (budget_tracers < 2 || max_slots < 1 || max_cells < 1 || max_cells > SIC_MAX_CELLS) return SIC_EINVAL;
+  if (flags & ~SIC_BATCH_SEGMENT_CHARGES) return SIC_EINVAL;
   if (precision < 0 || precision > 2 || history_rows < 0) return SIC_EINVAL;
   if (deposit_order < 0 || deposit_order > 2) return SIC_ENOTSUP;
   const int64_t rows = history_rows > 0 ? std::max<int64_t>(2, history_rows) : 4096;
@@ -1274,8 +1652,8 @@ sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t m
   const int64_t chunks = (budget_tracers + kChunk - 1) / kChunk + budget_tracers / 512 + 8 * (int64_t)max_slots;
   Pool *p = nullptr;
   std::string err;
-  sic_status st = pool_create(precision, deposit_order, true, max_slots, max_cells, chunks, rows, budget_tracers,
-                              hip_stream, &p, &err);
+  sic_status st = pool_create(precision, deposit_order, (flags & SIC_BATCH_SEGMENT_CHARGES) != 0, true, max_slots,
+                              max_cells, chunks, rows, budget_tracers, hip_stream, &p, &err);
   if (st != SIC_OK) return st;
   st = upload_item_count(p);
   if (st != SIC_OK) {
@@ -1289,10 +1667,15 @@ sic_status sic_batch_create(int64_t budget_tracers, int32_t max_slots, int32_t m
 }
 
 sic_status sic_batch_admit(sic_batch *b, const sic_config *cfg, const sic_sheet *sheets, int32_t n_sheets,
-                           const double *x0, const double *v0, int32_t mem_kind, int64_t n_steps,
-                           int32_t *slot) {
+                           const double *x0, const double *v0, const double *seg_charges, int32_t mem_kind,
+                           int64_t n_steps, int32_t *slot) {
   if (!b || !slot) return SIC_EINVAL;
-  return pool_admit(b->pool, cfg, sheets, n_sheets, x0, v0, mem_kind, n_steps, slot);
+  return pool_admit(b->pool, cfg, sheets, n_sheets, x0, v0, seg_charges, mem_kind, n_steps, slot);
+}
+
+sic_status sic_batch_get_charges(sic_batch *b, int32_t slot, double *seg_charges, int32_t mem_kind) {
+  if (!b) return SIC_EINVAL;
+  return pool_get_charges(b->pool, slot, seg_charges, mem_kind);
 }
 
 sic_status sic_batch_step(sic_batch *b, int64_t n_steps) {

@@ -15,6 +15,14 @@
 // the first tracer of the next chunk, which another workgroup may already
 // have overwritten; it recomputes that move from the halo copy written by the
 // previous step.  The halo is double-buffered (read one, write the other).
+//
+// Charges.  By default every segment of a sheet carries the sheet's charge,
+// kept in the chunk descriptor.  Pools created for per-segment charges (and
+// refinement, which halves segments) keep a third 8-byte word per tracer
+// slot: the charge of the segment that starts at that tracer (float64, or
+// int64 fixed point in the split forms), plus per chunk the charge of the
+// segment that ends at its first tracer and of the segment that starts at
+// its partner tracer ("charge edges").
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -63,7 +71,11 @@ struct alignas(16) ChunkDesc {
                           // valid tracer in the sheet; -1: open sheet end
   int32_t n_valid;        // valid tracer slots (1..64)
   int32_t inst;           // slot
-  int32_t pad;
+  int32_t flags;          // kChunkOpenStart
+};
+
+enum ChunkFlags : int {
+  kChunkOpenStart = 1,    // lane 0 is the first tracer of an open sheet (no segment before it)
 };
 
 struct alignas(16) Item {
@@ -108,6 +120,8 @@ struct TracerArgs {
   void *meshD;             // difference array for covered cell runs
   const double *meshE;
   Partial *partials;       // per item
+  const uint64_t *segq;    // per slot: charge of the segment starting there (per-segment pools)
+  const uint64_t *cedge;   // per chunk: charge ending at lane 0, charge starting at the partner
   int32_t mesh_cells;      // LDS capacity in cells (max n_cells of the pool)
   int32_t tile_cap;        // LDS capacity in chunks per work item
   int32_t respect_active;  // skip slots with active == 0
@@ -132,7 +146,12 @@ struct SolveArgs {
 
 struct IngestArgs {
   const double *x_in;
+  const uint64_t *w_in;       // raw state words instead of x_in (re-layout), or NULL
   const double *v_in;
+  const double *c_in;         // per-segment charges (float64), or NULL
+  const uint64_t *cw_in;      // raw per-segment charge words (re-layout), or NULL
+  uint64_t *segq;             // NULL: the pool keeps no per-segment charges
+  double q_scale;             // fixed-point units per unit charge (split forms)
   const int64_t *chunk_in_off;  // per chunk of the range: first input index
   int32_t chunk_begin;
   int32_t n_chunks;
@@ -152,20 +171,49 @@ struct ExtractArgs {
   const InstDesc *inst;
   const uint64_t *xs;
   const double *vs;
+  const uint64_t *segq;  // with c_out: per-segment charges
   double *x_out;
   double *v_out;
+  double *c_out;         // NULL: positions and velocities only
+};
+
+// Refinement (section 2.6) of one slot's chunk range: a marking pass counts
+// per chunk the segments longer than l_max (and keeps their lane mask); the
+// scatter pass writes every tracer, plus a centre tracer after each marked
+// one, to flat sheet-major output arrays (chunk cl starts at out_off[cl]).
+struct RefineArgs {
+  const ChunkDesc *chunks;
+  const InstDesc *inst;
+  const uint64_t *xs;
+  const double *vs;
+  const uint64_t *segq;
+  int32_t chunk_begin;
+  int32_t n_chunks;
+  double l_max;
+  int32_t *cnt;            // per chunk of the range
+  uint64_t *mask;          // per chunk of the range
+  const int64_t *out_off;  // per chunk of the range (scatter)
+  uint64_t *w_out;
+  double *v_out;
+  uint64_t *c_out;
 };
 
 // Launchers (sic_kernels.hip).  All return hipError_t as int.
-int launch_tracers(int prec, int mode, int order, const TracerArgs &a, int grid, int block, size_t lds_bytes,
-                   void *stream);
-int set_tracer_lds_limit(int prec, int order, size_t lds_bytes);
-size_t tracer_lds_size(int prec, int order, int mesh_cells, int tile_cap);
+int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a, int grid, int block,
+                   size_t lds_bytes, void *stream);
+int set_tracer_lds_limit(int prec, int order, bool seg, size_t lds_bytes);
+size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_cap);
 int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream);
 int launch_ingest(int prec, const IngestArgs &a, void *stream);
 int launch_extract(int prec, const ExtractArgs &a, void *stream);
 int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
                      const int32_t *slot_list, int n_blocks, void *stream);
 int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream);
+// Charge edges of chunks [chunk_begin, chunk_begin + n_chunks): prev_slot[c]
+// is the slot of the tracer before chunk c's first one (-1: none).
+int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const uint64_t *segq, uint64_t *cedge,
+                        int32_t chunk_begin, int32_t n_chunks, void *stream);
+int launch_refine_mark(int prec, const RefineArgs &a, void *stream);
+int launch_refine_scatter(int prec, const RefineArgs &a, void *stream);
 
 }  // namespace sic

@@ -31,6 +31,7 @@
 // order of the atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "sic_internal.h"
@@ -118,6 +119,21 @@ __device__ __forceinline__ double gather_field(const double *E, double u, int nc
   return (1.0 - s) * E[j0] + s * E[j1];
 }
 
+// Split-form word moved by du cells: t = fraction + du, the cell advances by
+// floor(t) (periodically) and the rest is re-quantised.
+template <int PREC>
+__device__ __forceinline__ uint64_t advance_split(uint64_t w, double du, int nc) {
+  const double t = split_frac<PREC>(split_bits(w)) + du;
+  const double k = floor(t);
+  const double r = t - k;
+  int carry;
+  const uint32_t bits = split_quantise<PREC>(r, carry);
+  long long cell = (long long)split_cell(w) + (long long)k + carry;
+  cell %= nc;
+  if (cell < 0) cell += nc;
+  return pack_split((int)cell, bits);
+}
+
 // Drift of a state word by dt * v.
 template <int PREC>
 __device__ __forceinline__ uint64_t drift(uint64_t w, double v, double dt, double L, double inv_dx, int nc) {
@@ -125,15 +141,7 @@ __device__ __forceinline__ uint64_t drift(uint64_t w, double v, double dt, doubl
     const double x = __longlong_as_double((long long)w);
     return (uint64_t)__double_as_longlong(wrap_into_box(x + dt * v, L));
   } else {
-    const double t = split_frac<PREC>(split_bits(w)) + (dt * v) * inv_dx;
-    const double k = floor(t);
-    const double r = t - k;
-    int carry;
-    const uint32_t bits = split_quantise<PREC>(r, carry);
-    long long cell = (long long)split_cell(w) + (long long)k + carry;
-    cell %= nc;
-    if (cell < 0) cell += nc;
-    return pack_split((int)cell, bits);
+    return advance_split<PREC>(w, (dt * v) * inv_dx, nc);
   }
 }
 
@@ -299,15 +307,15 @@ __device__ __forceinline__ SegGeo seg_geo_mesh(double ua, double ub, double half
   return s;
 }
 
-// Gradient of segment i from its neighbours (qd: segment charge in the
-// accumulator's units).
+// Gradient of segment i from its neighbours (qm, qp: charges of segments
+// i-1 and i+1 in the accumulator's units).
 __device__ __forceinline__ double linear_gradient(const SegGeo &m, const SegGeo &i, const SegGeo &p, bool have_m,
-                                                  bool have_p, double qd, double half_nc, double nc) {
+                                                  bool have_p, double qm, double qp, double half_nc, double nc) {
   if (!(have_m && have_p) || m.d == 0.0 || p.d == 0.0) return 0.0;
   const double dm = min_image_cells(m.c - i.c, half_nc, nc);
   const double dp = min_image_cells(p.c - i.c, half_nc, nc);
   if (!((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))) return 0.0;
-  return (qd / fabs(p.d) - qd / fabs(m.d)) / (dp - dm);
+  return (qp / fabs(p.d) - qm / fabs(m.d)) / (dp - dm);
 }
 
 // FP64: deposit segment i given its geometry and gradient (mesh units).
@@ -504,21 +512,41 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------
 // Per-item LDS layout (bytes): P, D (and for linear segments R) accumulators
 // and the field E for mesh_cells cells; for tile_cap chunks the item's chunk
-// descriptors and the halo copies of the tracers next to each chunk (one for
-// constant segments; three, plus the links, for linear ones); 48 doubles for
-// the block reduction.
+// descriptors, the halo copies of the tracers next to each chunk (one for
+// constant segments; three, plus the links, for linear ones) and, with
+// per-segment charges, the two charge edges; 48 doubles for the block
+// reduction.
 // ORDER: 0 piecewise-constant segments, 1 piecewise-linear segments (ramp
 // array R and three halo copies per chunk), 2 first-order weighting of
-// constant segments.
-template <class Acc, int ORDER>
+// constant segments.  SEG: per-segment charges (a charge word per tracer).
+template <class Acc, int ORDER, bool SEG>
 __host__ __device__ constexpr size_t tracer_lds_bytes(int mesh_cells, int tile_cap) {
   return (size_t)(2 + (ORDER == 1)) * mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
          (size_t)tile_cap *
-             (sizeof(ChunkDesc) + (ORDER == 1 ? 3 : 1) * sizeof(double2) + (ORDER == 1 ? sizeof(int2) : 0)) +
+             (sizeof(ChunkDesc) + (ORDER == 1 ? 3 : 1) * sizeof(double2) + (ORDER == 1 ? sizeof(int2) : 0) +
+              (SEG ? 2 * sizeof(uint64_t) : 0)) +
          48 * sizeof(double);
 }
 
-template <int PREC, int MODE, int ORDER>
+// Charge word -> charge as float64 (split forms: fixed-point units times q_unit).
+template <int PREC>
+__device__ __forceinline__ double charge_value(uint64_t w, double q_unit) {
+  if constexpr (PREC == kFP64) return __longlong_as_double((long long)w);
+  else return (double)(long long)w * q_unit;
+}
+
+// Mass of a tracer bounded by segments of charge words `left` and `right`:
+// half of each.
+template <int PREC>
+__device__ __forceinline__ double tracer_mass(uint64_t left, uint64_t right, double q_unit) {
+  if constexpr (PREC == kFP64) {
+    return 0.5 * (__longlong_as_double((long long)left) + __longlong_as_double((long long)right));
+  } else {
+    return 0.5 * ((double)((long long)left + (long long)right) * q_unit);
+  }
+}
+
+template <int PREC, int MODE, int ORDER, bool SEG>
 __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -532,7 +560,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   double2 *sHalo2 = sHalo + a.tile_cap;                               // order 1: next but one
   double2 *sHaloP = sHalo2 + a.tile_cap;                              // order 1: previous
   int2 *sLinks = reinterpret_cast<int2 *>(sHalo + (kLin ? 3 : 1) * a.tile_cap);
-  double *sRed = reinterpret_cast<double *>(sLinks + (kLin ? a.tile_cap : 0));  // 3 x 16 waves
+  uint64_t *sEdge = reinterpret_cast<uint64_t *>(sLinks + (kLin ? a.tile_cap : 0));  // per-segment charges
+  double *sRed = reinterpret_cast<double *>(sEdge + (SEG ? 2 * a.tile_cap : 0));      // 3 x 16 waves
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -543,6 +572,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   constexpr bool kMove = (MODE & kPush) != 0;
   constexpr bool kKick = (MODE & kKickHalf) != 0;
   constexpr bool kField = kMove || kKick;
+  constexpr bool kNeedQ = SEG && (kDep || kMove);  // per-segment charges are read
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item item = a.items[it];
@@ -572,6 +602,10 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     for (int i = tid; i < nch; i += blockDim.x) {
       sDesc[i] = a.chunks[cb + i];
       if constexpr (kLin && kDep) sLinks[i] = a.links[cb + i];
+      if constexpr (kNeedQ) {
+        sEdge[2 * i] = a.cedge[2 * (size_t)(cb + i)];
+        sEdge[2 * i + 1] = a.cedge[2 * (size_t)(cb + i) + 1];
+      }
     }
     __syncthreads();
     if constexpr (kDep) {
@@ -597,17 +631,27 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     // Loads and stores are unconditional (a chunk always has 64 slots; the
     // padding slots of a sheet's last chunk are read and written back
     // unchanged), so the only branches around memory operations are uniform.
-    auto load_state = [&](int kk, uint64_t &xw, double &v) {
+    auto load_state = [&](int kk, uint64_t &xw, double &v, uint64_t &cw) {
       const int kc = kk < nch ? kk : nch - 1;
       const size_t s = (size_t)(cb + kc) * kChunk + lane;
       xw = a.xs[s];
       v = a.vs[s];
+      if constexpr (kNeedQ) cw = a.segq[s];
     };
-    auto process = [&](int kk, uint64_t xw, double v) {
+    auto process = [&](int kk, uint64_t xw, double v, uint64_t cw) {
       const ChunkDesc ch = sDesc[kk];
       const int n_valid = __builtin_amdgcn_readfirstlane(ch.n_valid);
       const bool valid = lane < n_valid;
       const size_t s = (size_t)(cb + kk) * kChunk + lane;
+      // Per-segment charges: this lane's segment (cw), the one ending at this
+      // tracer (cl) and, for linear segments, the next one (cn).
+      uint64_t cl = 0, cn = 0;
+      if constexpr (kNeedQ) {
+        const uint64_t up = (uint64_t)__shfl_up((long long)cw, 1, 64);
+        const uint64_t dn = (uint64_t)__shfl_down((long long)cw, 1, 64);
+        cl = lane == 0 ? sEdge[2 * kk] : up;
+        cn = lane == n_valid - 1 ? sEdge[2 * kk + 1] : dn;
+      }
       if constexpr (kField) {
         const double e = gather_field(sE, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
         if constexpr (kKick) {
@@ -616,7 +660,16 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           a.vs[s] = v;
         } else {
           const double vn = v + g.dt * e;
-          const double qv = valid ? ch.q : 0.0;
+          double m;
+          if constexpr (SEG) {
+            m = tracer_mass<PREC>(cl, cw, I.q_unit);
+          } else {
+            // half of each segment the tracer bounds: the ends of an open
+            // sheet bound one
+            const bool end = (lane == 0 && (ch.flags & kChunkOpenStart)) || (lane == n_valid - 1 && ch.partner < 0);
+            m = end ? 0.5 * ch.q : ch.q;
+          }
+          const double qv = valid ? m : 0.0;
           ke += 0.5 * qv * v * vn;
           mom += qv * (0.5 * (v + vn));
           const uint64_t xn = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
@@ -680,14 +733,28 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           }
           const SegGeo sm = seg_geo_mesh(um1, u0, half_nc, ncd);
           const SegGeo sp = seg_geo_mesh(up1d, up2, half_nc, ncd);
-          const double qd = PREC == kFP64 ? ch.q : (double)ch.q_fix;
-          const double grad = linear_gradient(sm, sg, sp, has_m1, has_p2, qd, half_nc, ncd);
+          double qm, qp, q0 = ch.q;
+          long long q0_fix = ch.q_fix;
+          if constexpr (SEG) {
+            if constexpr (PREC == kFP64) {
+              qm = __longlong_as_double((long long)cl);
+              qp = __longlong_as_double((long long)cn);
+              q0 = __longlong_as_double((long long)cw);
+            } else {
+              qm = (double)(long long)cl;
+              qp = (double)(long long)cn;
+              q0_fix = (long long)cw;
+            }
+          } else {
+            qm = qp = PREC == kFP64 ? ch.q : (double)ch.q_fix;
+          }
+          const double grad = linear_gradient(sm, sg, sp, has_m1, has_p2, qm, qp, half_nc, ncd);
           const double len = fabs(sg.d) * g.dx;
           if (len <= g.half_L) {
             if constexpr (PREC == kFP64) {
-              deposit_linear_fp64(__longlong_as_double((long long)xw), sg, grad, ch.q, g, sP, sD, sR);
+              deposit_linear_fp64(__longlong_as_double((long long)xw), sg, grad, q0, g, sP, sD, sR);
             } else {
-              deposit_linear_split(split_cell(xw), split_frac<PREC>(split_bits(xw)), sg, grad, ch.q_fix, g, sP,
+              deposit_linear_split(split_cell(xw), split_frac<PREC>(split_bits(xw)), sg, grad, q0_fix, g, sP,
                                    sD, sR);
             }
           }
@@ -714,6 +781,12 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         }
         if (has_seg) {
           double len;
+          double q0 = ch.q;
+          long long q0_fix = ch.q_fix;
+          if constexpr (SEG) {
+            if constexpr (PREC == kFP64) q0 = __longlong_as_double((long long)cw);
+            else q0_fix = (long long)cw;
+          }
           if constexpr (ORDER == 2) {
             // first-order weighting: geometry in mesh units, minimum image as
             // for the constant scheme
@@ -731,33 +804,33 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
             }
             len = fabs(dm) * g.dx;
             if (len <= g.half_L) {
-              if constexpr (PREC == kFP64) deposit_cic_fp64(ua, dm, ch.q, g, sP, sD);
-              else deposit_cic_split(ua, dm, ch.q_fix, g, sP, sD);
+              if constexpr (PREC == kFP64) deposit_cic_fp64(ua, dm, q0, g, sP, sD);
+              else deposit_cic_split(ua, dm, q0_fix, g, sP, sD);
             }
           } else if constexpr (PREC == kFP64) {
-            len = deposit_fp64(__longlong_as_double((long long)xw), __longlong_as_double((long long)pw), ch.q, g,
+            len = deposit_fp64(__longlong_as_double((long long)xw), __longlong_as_double((long long)pw), q0, g,
                                sP, sD);
           } else {
-            len = deposit_split<PREC>(xw, pw, ch.q_fix, g, sP, sD);
+            len = deposit_split<PREC>(xw, pw, q0_fix, g, sP, sD);
           }
           ms = nan_max(ms, len);
         }
       }
     };
-    uint64_t xa = 0, xb = 0, xc = 0;
+    uint64_t xa = 0, xb = 0, xc = 0, ca = 0, cb_ = 0, cc = 0;
     double va = 0.0, vb = 0.0, vc = 0.0;
-    load_state(wave, xa, va);
-    load_state(wave + nwaves, xb, vb);
-    load_state(wave + 2 * nwaves, xc, vc);
+    load_state(wave, xa, va, ca);
+    load_state(wave + nwaves, xb, vb, cb_);
+    load_state(wave + 2 * nwaves, xc, vc, cc);
     for (int k = wave; k < nch; k += 3 * nwaves) {
-      process(k, xa, va);
-      load_state(k + 3 * nwaves, xa, va);
+      process(k, xa, va, ca);
+      load_state(k + 3 * nwaves, xa, va, ca);
       if (k + nwaves >= nch) break;
-      process(k + nwaves, xb, vb);
-      load_state(k + 4 * nwaves, xb, vb);
+      process(k + nwaves, xb, vb, cb_);
+      load_state(k + 4 * nwaves, xb, vb, cb_);
       if (k + 2 * nwaves >= nch) break;
-      process(k + 2 * nwaves, xc, vc);
-      load_state(k + 5 * nwaves, xc, vc);
+      process(k + 2 * nwaves, xc, vc, cc);
+      load_state(k + 5 * nwaves, xc, vc, cc);
     }
 
     // Work-item partial sums in a fixed order (deterministic for a fixed
@@ -814,12 +887,13 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   }
 }
 
-size_t tracer_lds_size(int prec, int order, int mesh_cells, int tile_cap) {
+size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_cap) {
+  // the accumulators are 8 bytes in every precision
   if (order == 1)
-    return prec == kFP64 ? tracer_lds_bytes<double, 1>(mesh_cells, tile_cap)
-                         : tracer_lds_bytes<unsigned long long, 1>(mesh_cells, tile_cap);
-  return prec == kFP64 ? tracer_lds_bytes<double, 0>(mesh_cells, tile_cap)
-                       : tracer_lds_bytes<unsigned long long, 0>(mesh_cells, tile_cap);
+    return seg ? tracer_lds_bytes<double, 1, true>(mesh_cells, tile_cap)
+               : tracer_lds_bytes<double, 1, false>(mesh_cells, tile_cap);
+  return seg ? tracer_lds_bytes<double, 0, true>(mesh_cells, tile_cap)
+             : tracer_lds_bytes<double, 0, false>(mesh_cells, tile_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -1086,25 +1160,42 @@ __global__ void __launch_bounds__(256) k_ingest(IngestArgs a) {
   const ChunkDesc ch = a.chunks[c];
   const InstDesc &I = a.inst[ch.inst];
   const size_t s = (size_t)c * kChunk + lane;
-  uint64_t w = 0;
+  uint64_t w = 0, cw = 0;
   double v = 0.0;
   if (lane < ch.n_valid) {
     const int64_t src = a.chunk_in_off[cl] + lane;
-    const double x = wrap_into_box(a.x_in[src], I.L);
     v = a.v_in[src];
-    if constexpr (PREC == kFP64) {
-      w = (uint64_t)__double_as_longlong(x);
+    if (a.w_in) {
+      w = a.w_in[src];  // a state word of this pool (re-layout)
     } else {
-      const double u = x * I.inv_dx;
-      const double f = floor(u);
-      int carry;
-      const uint32_t bits = split_quantise<PREC>(u - f, carry);
-      const int cell = wrap_cell((int)f + carry, I.n_cells);
-      w = pack_split(cell, bits);
+      const double x = wrap_into_box(a.x_in[src], I.L);
+      if constexpr (PREC == kFP64) {
+        w = (uint64_t)__double_as_longlong(x);
+      } else {
+        const double u = x * I.inv_dx;
+        const double f = floor(u);
+        int carry;
+        const uint32_t bits = split_quantise<PREC>(u - f, carry);
+        const int cell = wrap_cell((int)f + carry, I.n_cells);
+        w = pack_split(cell, bits);
+      }
+    }
+    if (a.segq) {
+      if (a.cw_in) {
+        cw = a.cw_in[src];
+      } else if (a.c_in) {
+        if constexpr (PREC == kFP64) cw = (uint64_t)__double_as_longlong(a.c_in[src]);
+        else cw = (uint64_t)llrint(a.c_in[src] * a.q_scale);
+      } else {
+        if constexpr (PREC == kFP64) cw = (uint64_t)__double_as_longlong(ch.q);
+        else cw = (uint64_t)ch.q_fix;
+      }
+      if (lane == ch.n_valid - 1 && ch.partner < 0) cw = 0;  // an open sheet's last tracer starts no segment
     }
   }
   a.xs[s] = w;
   a.vs[s] = v;
+  if (a.segq) a.segq[s] = cw;
   const double2 hv = make_double2(__longlong_as_double((long long)w), v);
   if (lane == 0) a.halo[c] = hv;
   if (a.halo3) {
@@ -1134,6 +1225,124 @@ __global__ void __launch_bounds__(256) k_extract(ExtractArgs a) {
   }
   a.x_out[dst] = x;
   a.v_out[dst] = a.vs[s];
+  if (a.c_out) a.c_out[dst] = charge_value<PREC>(a.segq[s], I.q_unit);
+}
+
+// Charge edges of a chunk range (one thread per chunk): the charge of the
+// segment ending at the chunk's first tracer and of the segment starting at
+// its partner tracer.
+__global__ void __launch_bounds__(256) k_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot,
+                                                      const uint64_t *segq, uint64_t *cedge, int32_t chunk_begin,
+                                                      int32_t n_chunks) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_chunks) return;
+  const int c = chunk_begin + i;
+  const int64_t pv = prev_slot[c];
+  const int32_t pc = chunks[c].partner;
+  cedge[2 * (size_t)c] = pv >= 0 ? segq[pv] : 0ull;
+  cedge[2 * (size_t)c + 1] = pc >= 0 ? segq[(size_t)pc * kChunk] : 0ull;
+}
+
+// Refinement, one wavefront per chunk.  Each valid lane looks at its segment
+// (to the next tracer, or for the last lane to the partner tracer; none at
+// an open sheet's end) and marks it when its minimum-image length exceeds
+// l_max.
+template <int PREC>
+__device__ __forceinline__ bool refine_segment(const RefineArgs &a, const ChunkDesc &ch, const InstDesc &I,
+                                               int lane, uint64_t w, uint64_t &wn, double &vn, double &du) {
+  bool has = lane < ch.n_valid;
+  if (lane == ch.n_valid - 1) {
+    if (ch.partner >= 0) {
+      wn = a.xs[(size_t)ch.partner * kChunk];
+      vn = a.vs[(size_t)ch.partner * kChunk];
+    } else {
+      has = false;
+    }
+  }
+  if (!has) return false;
+  double len;
+  if constexpr (PREC == kFP64) {
+    const double xa = __longlong_as_double((long long)w);
+    double d = __longlong_as_double((long long)wn) - xa;
+    if (d >= I.half_L) d -= I.L;
+    else if (d < -I.half_L) d += I.L;
+    du = d;
+    len = fabs(d);
+  } else {
+    const double ua = mesh_pos<PREC>(w, I.inv_dx);
+    const double dm = min_image_cells(mesh_pos<PREC>(wn, I.inv_dx) - ua, 0.5 * (double)I.n_cells, (double)I.n_cells);
+    du = dm;
+    len = fabs(dm) * I.dx;
+  }
+  return len > a.l_max;
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_refine_mark(RefineArgs a) {
+  const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (cl >= a.n_chunks) return;  // uniform per wavefront
+  const int lane = threadIdx.x & 63;
+  const int c = a.chunk_begin + cl;
+  const ChunkDesc ch = a.chunks[c];
+  const InstDesc &I = a.inst[ch.inst];
+  const size_t s = (size_t)c * kChunk + lane;
+  const uint64_t w = a.xs[s];
+  uint64_t wn = (uint64_t)__shfl_down((long long)w, 1, 64);
+  double vn = 0.0, du = 0.0;
+  const bool flag = refine_segment<PREC>(a, ch, I, lane, w, wn, vn, du);
+  const uint64_t mask = __ballot(flag);
+  if (lane == 0) {
+    a.cnt[cl] = __popcll(mask);
+    a.mask[cl] = mask;
+  }
+}
+
+// Writes the chunk's tracers to the flat output, each marked one followed by
+// the centre of its segment: mean velocity, and the charge split in halves
+// (fixed point: the halves differ by at most one unit and sum exactly).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_refine_scatter(RefineArgs a) {
+  const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (cl >= a.n_chunks) return;  // uniform per wavefront
+  const int lane = threadIdx.x & 63;
+  const int c = a.chunk_begin + cl;
+  const ChunkDesc ch = a.chunks[c];
+  const InstDesc &I = a.inst[ch.inst];
+  const size_t s = (size_t)c * kChunk + lane;
+  const uint64_t w = a.xs[s];
+  const double v = a.vs[s];
+  const uint64_t cq = a.segq[s];
+  uint64_t wn = (uint64_t)__shfl_down((long long)w, 1, 64);
+  double vn = __shfl_down(v, 1, 64);
+  double du = 0.0;
+  refine_segment<PREC>(a, ch, I, lane, w, wn, vn, du);
+  // the marking pass decided (the host sized the output from its counts)
+  const uint64_t mask = a.mask[cl];
+  const bool flag = ((mask >> lane) & 1ull) != 0;
+  if (lane >= ch.n_valid) return;
+  const int64_t out = a.out_off[cl] + lane + __popcll(mask & ((1ull << lane) - 1ull));
+  uint64_t c0 = cq;
+  if (flag) {
+    uint64_t c1, wm;
+    if constexpr (PREC == kFP64) {
+      const double h = 0.5 * __longlong_as_double((long long)cq);
+      c0 = c1 = (uint64_t)__double_as_longlong(h);
+      const double xa = __longlong_as_double((long long)w);
+      wm = (uint64_t)__double_as_longlong(wrap_into_box(xa + 0.5 * du, I.L));
+    } else {
+      const long long q = (long long)cq;
+      const long long q1 = q >> 1;
+      c0 = (uint64_t)(q - q1);
+      c1 = (uint64_t)q1;
+      wm = advance_split<PREC>(w, 0.5 * du, I.n_cells);
+    }
+    a.w_out[out + 1] = wm;
+    a.v_out[out + 1] = 0.5 * (v + vn);
+    a.c_out[out + 1] = c1;
+  }
+  a.w_out[out] = w;
+  a.v_out[out] = v;
+  a.c_out[out] = c0;
 }
 
 template <int PREC>
@@ -1160,20 +1369,20 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, d
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int PREC, int ORDER>
+template <int PREC, int ORDER, bool SEG>
 static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
   switch (mode) {
     case kDeposit:
-      hipLaunchKernelGGL((k_tracers<PREC, kDeposit, ORDER>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kDeposit, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
       break;
     case kPush:
-      hipLaunchKernelGGL((k_tracers<PREC, kPush, ORDER>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kPush, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
       break;
     case kPush | kDeposit:
-      hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit, ORDER>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
       break;
     case kKickHalf:
-      hipLaunchKernelGGL((k_tracers<PREC, kKickHalf, ORDER>), dim3(grid), dim3(block), lds, st, a);
+      hipLaunchKernelGGL((k_tracers<PREC, kKickHalf, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1181,12 +1390,13 @@ static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int bloc
   return hipGetLastError();
 }
 
-template <int PREC, int ORDER>
+template <int PREC, int ORDER, bool SEG>
 static hipError_t set_lds_limit(size_t bytes) {
   const int b = (int)bytes;
-  const void *fns[] = {(const void *)k_tracers<PREC, kDeposit, ORDER>, (const void *)k_tracers<PREC, kPush, ORDER>,
-                       (const void *)k_tracers<PREC, kPush | kDeposit, ORDER>,
-                       (const void *)k_tracers<PREC, kKickHalf, ORDER>};
+  const void *fns[] = {(const void *)k_tracers<PREC, kDeposit, ORDER, SEG>,
+                       (const void *)k_tracers<PREC, kPush, ORDER, SEG>,
+                       (const void *)k_tracers<PREC, kPush | kDeposit, ORDER, SEG>,
+                       (const void *)k_tracers<PREC, kKickHalf, ORDER, SEG>};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
@@ -1194,50 +1404,48 @@ static hipError_t set_lds_limit(size_t bytes) {
   return hipSuccess;
 }
 
+// Dispatch of a runtime (precision, order, per-segment charges) triple to a
+// template instance.
+template <template <int, int, bool> class F, class... Args>
+static hipError_t dispatch(int prec, int order, bool seg, Args &&...args) {
+#define SIC_CASE(P, O)                                                                    \
+  if (prec == P && order == O)                                                            \
+    return seg ? F<P, O, true>::run(args...) : F<P, O, false>::run(args...);
+  SIC_CASE(kFP64, 0) SIC_CASE(kFP64, 1) SIC_CASE(kFP64, 2)
+  SIC_CASE(kSplitF32, 0) SIC_CASE(kSplitF32, 1) SIC_CASE(kSplitF32, 2)
+  SIC_CASE(kSplitU32, 0) SIC_CASE(kSplitU32, 1) SIC_CASE(kSplitU32, 2)
+#undef SIC_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int PREC, int ORDER, bool SEG>
+struct LaunchTracers {
+  static hipError_t run(int mode, const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
+    return tracers_prec<PREC, ORDER, SEG>(mode, a, grid, block, lds, st);
+  }
+};
+
+template <int PREC, int ORDER, bool SEG>
+struct SetLdsLimit {
+  static hipError_t run(size_t bytes) { return set_lds_limit<PREC, ORDER, SEG>(bytes); }
+};
+
 // The limit is a property of the kernel function, shared by every pool in
 // the process, so it only ever grows.
-int set_tracer_lds_limit(int prec, int order, size_t lds) {
-  static size_t granted[3][3] = {{65536, 65536, 65536}, {65536, 65536, 65536}, {65536, 65536, 65536}};
+int set_tracer_lds_limit(int prec, int order, bool seg, size_t lds) {
+  static size_t granted[3][3][2] = {};
   if (prec < 0 || prec > 2 || order < 0 || order > 2) return (int)hipErrorInvalidValue;
-  if (lds <= granted[prec][order]) return 0;
-  hipError_t e;
-  if (order == 0)
-    e = prec == kFP64 ? set_lds_limit<kFP64, 0>(lds)
-                      : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 0>(lds) : set_lds_limit<kSplitU32, 0>(lds));
-  else if (order == 1)
-    e = prec == kFP64 ? set_lds_limit<kFP64, 1>(lds)
-                      : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 1>(lds) : set_lds_limit<kSplitU32, 1>(lds));
-  else
-    e = prec == kFP64 ? set_lds_limit<kFP64, 2>(lds)
-                      : (prec == kSplitF32 ? set_lds_limit<kSplitF32, 2>(lds) : set_lds_limit<kSplitU32, 2>(lds));
-  if (e == hipSuccess) granted[prec][order] = lds;
+  size_t &g = granted[prec][order][seg ? 1 : 0];
+  if (lds <= std::max<size_t>(g, 65536)) return 0;
+  const hipError_t e = dispatch<SetLdsLimit>(prec, order, seg, lds);
+  if (e == hipSuccess) g = lds;
   return (int)e;
 }
 
-int launch_tracers(int prec, int mode, int order, const TracerArgs &a, int grid, int block, size_t lds,
+int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a, int grid, int block, size_t lds,
                    void *stream) {
-  hipStream_t st = (hipStream_t)stream;
   if (grid <= 0) return 0;
-  if (order == 0) {
-    switch (prec) {
-      case kFP64: return (int)tracers_prec<kFP64, 0>(mode, a, grid, block, lds, st);
-      case kSplitF32: return (int)tracers_prec<kSplitF32, 0>(mode, a, grid, block, lds, st);
-      case kSplitU32: return (int)tracers_prec<kSplitU32, 0>(mode, a, grid, block, lds, st);
-    }
-  } else if (order == 1) {
-    switch (prec) {
-      case kFP64: return (int)tracers_prec<kFP64, 1>(mode, a, grid, block, lds, st);
-      case kSplitF32: return (int)tracers_prec<kSplitF32, 1>(mode, a, grid, block, lds, st);
-      case kSplitU32: return (int)tracers_prec<kSplitU32, 1>(mode, a, grid, block, lds, st);
-    }
-  } else if (order == 2) {
-    switch (prec) {
-      case kFP64: return (int)tracers_prec<kFP64, 2>(mode, a, grid, block, lds, st);
-      case kSplitF32: return (int)tracers_prec<kSplitF32, 2>(mode, a, grid, block, lds, st);
-      case kSplitU32: return (int)tracers_prec<kSplitU32, 2>(mode, a, grid, block, lds, st);
-    }
-  }
-  return (int)hipErrorInvalidValue;
+  return (int)dispatch<LaunchTracers>(prec, order, seg, mode, a, grid, block, lds, (hipStream_t)stream);
 }
 
 int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream) {
@@ -1287,6 +1495,40 @@ int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const Inst
   else
     hipLaunchKernelGGL(k_zero_mesh<kSplitF32>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, meshR, inst,
                        slot_list);
+  return (int)hipGetLastError();
+}
+
+int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const uint64_t *segq, uint64_t *cedge,
+                        int32_t chunk_begin, int32_t n_chunks, void *stream) {
+  if (n_chunks <= 0) return 0;
+  hipLaunchKernelGGL(k_charge_edges, dim3((n_chunks + 255) / 256), dim3(256), 0, (hipStream_t)stream, chunks,
+                     prev_slot, segq, cedge, chunk_begin, n_chunks);
+  return (int)hipGetLastError();
+}
+
+int launch_refine_mark(int prec, const RefineArgs &a, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int grid = (a.n_chunks + 3) / 4;
+  if (grid <= 0) return 0;
+  switch (prec) {
+    case kFP64: hipLaunchKernelGGL(k_refine_mark<kFP64>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitF32: hipLaunchKernelGGL(k_refine_mark<kSplitF32>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitU32: hipLaunchKernelGGL(k_refine_mark<kSplitU32>, dim3(grid), dim3(256), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_refine_scatter(int prec, const RefineArgs &a, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int grid = (a.n_chunks + 3) / 4;
+  if (grid <= 0) return 0;
+  switch (prec) {
+    case kFP64: hipLaunchKernelGGL(k_refine_scatter<kFP64>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitF32: hipLaunchKernelGGL(k_refine_scatter<kSplitF32>, dim3(grid), dim3(256), 0, st, a); break;
+    case kSplitU32: hipLaunchKernelGGL(k_refine_scatter<kSplitU32>, dim3(grid), dim3(256), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 

@@ -61,11 +61,21 @@ def test_invalid_arguments_are_rejected_before_any_device_work(lib):
     assert _init_status(q=[float("nan")]) == 1
     assert _init_status(precision=7) == 1
     assert _init_status(deposit_order=3) == 6
+    assert _init_status(l_max=-1.0) == 1
+    assert _init_status(l_max=float("nan")) == 1
+    assert _init_status(max_tracers=-5) == 1
     h = ctypes.c_void_p()
-    assert lib.sic_init(None, None, 0, None, None, 0, None, ctypes.byref(h)) == 1
-    assert lib.sic_batch_create(0, 1, 8, 0, 0, 0, None, ctypes.byref(h)) == 1
-    assert lib.sic_batch_create(100, 1, B.SIC_MAX_CELLS + 1, 0, 0, 0, None, ctypes.byref(h)) == 1
-    assert lib.sic_batch_create(100, 1, 8, 0, 3, 0, None, ctypes.byref(h)) == 6
+    assert lib.sic_init(None, None, 0, None, None, None, 0, None, ctypes.byref(h)) == 1
+    assert lib.sic_batch_create(0, 1, 8, 0, 0, 0, 0, None, ctypes.byref(h)) == 1
+    assert lib.sic_batch_create(100, 1, B.SIC_MAX_CELLS + 1, 0, 0, 0, 0, None, ctypes.byref(h)) == 1
+    assert lib.sic_batch_create(100, 1, 8, 0, 3, 0, 0, None, ctypes.byref(h)) == 6
+    assert lib.sic_batch_create(100, 1, 8, 0, 0, 4, 0, None, ctypes.byref(h)) == 1  # unknown flag
+    n = ctypes.c_int64(0)
+    assert lib.sic_refine(None, 1.0, ctypes.byref(n)) == 1
+    assert lib.sic_get_layout(None, None, ctypes.byref(n)) == 1
+    assert lib.sic_get_charges(None, None, 0) == 1
+    assert lib.sic_load_state(None, 0, None, None, None, None, 0) == 1
+    assert lib.sic_batch_get_charges(None, 0, None, 0) == 1
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

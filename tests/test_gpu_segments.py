@@ -1,0 +1,271 @@
+"""Per-segment charges, vertically connected sheets (paper section 3.3.2)
+and refinement (section 2.6) on the GPU against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1506_07207_amd import binding as B
+from paper_1506_07207_amd import inputs as I
+from tests.parity import envelope_rel, periodic_diff, rel_inf
+
+pytestmark = pytest.mark.gpu
+RAGGED = [2, 3, 4, 63, 64, 65, 127, 128, 129, 300]
+CLOSED = [1, 0, 0, 1, 0, 1, 0, 1, 1, 0]
+
+
+def _random_charges(p, seed):
+    """Charges that differ from segment to segment (0 for the last tracer of
+    an open sheet)."""
+    rng = np.random.default_rng(seed)
+    c = p.seg_charges * rng.uniform(0.3, 3.0, p.total_tracers)
+    ends = np.cumsum(p.n_tracers) - 1
+    c[ends[p.closed == 0]] = 0.0
+    return c
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("nc", [1, 16, 100, 1024])
+def test_segment_charge_deposit_matches_oracle(order, nc):
+    p = I.random_sheets(300 + nc, len(RAGGED), RAGGED, nc, L=1.9, jitter=0.5, closed=CLOSED)
+    c = _random_charges(p, nc)
+    print(f"case segment charges order={order} nc={nc}", flush=True)
+    with B.Simulation(p, deposit_order=order, seg_charges=c) as s:
+        d = s.diagnostics()
+        back = s.charges()
+    assert np.array_equal(back, c)
+    Q, ms = O.deposit(p.L, nc, p.n_tracers, p.q, p.closed, p.x0, order=order, c=c)
+    dx = p.L / nc
+    rho_o = Q / dx - Q.sum() / p.L
+    err_rho = np.max(np.abs(d["rho"] - rho_o))
+    tol = 1e-10 * max(1.0, np.max(np.abs(Q / dx)))
+    if order == 1:
+        # piecewise-linear gradients divide by segment lengths: next to a
+        # nearly degenerate segment two correct FP64 deposits differ by as
+        # much as the oracle moves under one-ulp position changes
+        rng = np.random.default_rng(0)
+        for _ in range(4):
+            x2 = np.mod(p.x0 + rng.choice([-1.0, 0.0, 1.0], len(p.x0)) * np.spacing(p.x0), p.L)
+            Q2, _ = O.deposit(p.L, nc, p.n_tracers, p.q, p.closed, x2, order=1, c=c)
+            tol = max(tol, 4.0 * float(np.max(np.abs(Q2 - Q))) / dx)
+    print(f"  |drho| {err_rho:.3e} tolerance {tol:.3e}", flush=True)
+    assert err_rho < tol
+    E_g, _, _ = O.solve(p.L, nc, d["rho"] * dx)
+    assert rel_inf(d["E"], E_g) < 1e-10 or np.max(np.abs(E_g)) < 1e-14
+    total = math.fsum(c)
+    assert abs(d["last"]["total_charge"] - total) < 1e-11 * total
+    assert abs(d["last"]["max_segment"] - ms) < 1e-13 * p.L
+
+
+@pytest.mark.parametrize("use_c", [False, True])
+def test_open_sheet_masses_and_steps_match_oracle(use_c):
+    """Kinetic energy and momentum use tracer masses of half of each
+    bounding segment, so an open sheet's end tracers weigh half; the same
+    holds with per-segment charges."""
+    p = I.random_sheets(41, 6, [2, 70, 3, 130, 64, 65], 40, L=2.0, jitter=0.3, vscale=0.4, dt=0.05,
+                        closed=[0, 0, 1, 0, 1, 0])
+    c = _random_charges(p, 5) if use_c else p.seg_charges
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, c, p.x0, p.v0, 6)
+    with B.Simulation(p, seg_charges=c if use_c else None) as s:
+        s.step(6)
+        x, v, _ = s.state()
+        h = s.diagnostics()["history"]
+    assert np.max(periodic_diff(x, ref["x"], p.L)) < 1e-12 * p.L
+    for n in range(6):
+        for col, k in (("W_E", 2), ("KE", 3), ("momentum", 4)):
+            r = ref["hist"][n, k]
+            assert abs(h[col][n] - r) <= 1e-10 * max(abs(r), 1e-12), (col, n, h[col][n], r)
+
+
+@pytest.mark.parametrize("order", [0, 2])
+def test_vertical_landau_fp64_matches_oracle(order):
+    p = I.landau_vertical(n_streams=26, n_positions=160, n_cells=40, n_steps=200)
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, order=order)
+    with B.Simulation(p, deposit_order=order) as s:
+        s.step(p.n_steps)
+        h = s.diagnostics()["history"]
+        x, _, _ = s.state()
+    err = envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt)
+    print(f"vertical landau order={order} fp64 envelope error {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert np.max(periodic_diff(x, ref["x"], p.L)) < 1e-10 * p.L
+
+
+@pytest.mark.parametrize("prec", [B.SIC_SPLIT_U32, B.SIC_SPLIT_F32])
+def test_vertical_landau_split(prec):
+    p = I.landau_vertical(n_streams=26, n_positions=160, n_cells=40, n_steps=200)
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps)
+    with B.Simulation(p, precision=prec) as s:
+        s.step(p.n_steps)
+        h = s.diagnostics()["history"]
+    err = envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt)
+    print(f"vertical landau prec={prec} envelope error {err:.3e}", flush=True)
+    assert err < 1e-6
+    assert np.all(h["total_charge"] == h["total_charge"][0])
+
+
+def test_refine_pass_matches_oracle_exactly():
+    """One refinement pass on the GPU inserts the same tracers, at the same
+    positions, with the same velocities and charges as the oracle's."""
+    p = I.random_sheets(77, 5, [40, 3, 64, 129, 9], 50, L=2.5, jitter=1.5, closed=[1, 0, 1, 1, 0])
+    dx = p.L / p.n_cells
+    c = p.seg_charges
+    with B.Simulation(p, l_max=0.0, seg_charges=c, max_tracers=4 * p.total_tracers) as s:
+        x0, v0, _ = s.state()
+        added = s.refine(0.8 * dx)
+        nt, tot = s.layout()
+        x, v, _ = s.state()
+        cc = s.charges()
+        d = s.diagnostics()
+    nt_o, x_o, v_o, c_o, add_o = O.refine(p.L, 0.8 * dx, p.n_tracers, p.closed, x0, v0, c)
+    assert added == add_o > 20
+    assert np.array_equal(nt, nt_o) and tot == len(x_o)
+    assert np.array_equal(x, x_o) and np.array_equal(v, v_o) and np.array_equal(cc, c_o)
+    Q, ms = O.deposit(p.L, p.n_cells, nt_o, p.q, p.closed, x_o, c=c_o)
+    rho_o = Q / dx - Q.sum() / p.L
+    assert np.max(np.abs(d["rho"] - rho_o)) < 1e-10 * np.max(np.abs(Q / dx))
+    assert abs(d["last"]["max_segment"] - ms) < 1e-13 * p.L
+
+
+def test_refinement_run_matches_oracle():
+    """The section 2.6 two-stream run with refinement at one cell, through
+    the onset of refinement: the GPU inserts the same tracers at every step
+    (same count history) and its field energy follows the oracle's."""
+    p = I.refinement_two_stream(n_steps=340)
+    dx = p.L / p.n_cells
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, l_max=dx,
+                    capacity=200_000)
+    counts = [p.total_tracers]
+    print(f"case refinement run, oracle final count {ref['count'][-1]}", flush=True)
+    with B.Simulation(p, l_max=dx, max_tracers=200_000) as s:
+        for _ in range(p.n_steps):
+            s.step(1)
+            counts.append(s.n)
+        h = s.diagnostics()["history"]
+        nt, _ = s.layout()
+    assert ref["count"][-1] > 1.05 * ref["count"][0]  # refinement has started
+    assert np.array_equal(np.array(counts), ref["count"])
+    assert np.array_equal(nt, ref["n_tracers"])
+    err = envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt)
+    print(f"refinement run envelope error {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert np.max(np.abs(h["total_charge"] - ref["hist"][:, 5])) < 1e-12 * ref["hist"][0, 5]
+
+
+def test_refinement_resynchronised_steps_deep_in_the_nonlinear_phase():
+    """At steps 300, 400 and 500 of the refined two-stream run the GPU is
+    loaded with the oracle's refined state (sic_load_state) and takes one
+    step with refinement: same insertions, same positions, same field
+    energy."""
+    p = I.refinement_two_stream(n_steps=500)
+    dx = p.L / p.n_cells
+    cap = 2_000_000
+    with B.Simulation(p, l_max=dx, max_tracers=cap) as s:
+        for target in (300, 400, 500):
+            st = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, target,
+                           l_max=dx, capacity=cap)
+            one = O.run_seg(p.L, p.n_cells, p.dt, st["n_tracers"], p.closed, st["c"], st["x"], st["v"], 1,
+                            step0=target, init_kick=False, l_max=dx, capacity=cap)
+            s.load_state(target, st["n_tracers"], st["x"], st["v"], st["c"])
+            s.step(1)
+            nt, tot = s.layout()
+            x, v, step = s.state()
+            W = s.diagnostics(history=False)["last"]["W_E"]
+            assert step == target + 1
+            assert np.array_equal(nt, one["n_tracers"]), target
+            assert np.max(periodic_diff(x, one["x"], p.L)) < 1e-12 * p.L
+            assert abs(W - one["hist"][-1, 2]) <= 1e-10 * one["hist"][-1, 2]
+            print(f"resync at {target}: {tot} tracers", flush=True)
+
+
+def test_refinement_split_conserves_charge_exactly():
+    p = I.refinement_two_stream(n_steps=360)
+    dx = p.L / p.n_cells
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, l_max=dx,
+                    capacity=200_000)
+    with B.Simulation(p, precision=B.SIC_SPLIT_U32, l_max=dx, max_tracers=200_000) as s:
+        s.step(p.n_steps)
+        h = s.diagnostics()["history"]
+        n = s.n
+    assert np.all(h["total_charge"] == h["total_charge"][0])
+    err = envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt)
+    print(f"refinement split U32 envelope error {err:.3e}, count {n} vs oracle {ref['count'][-1]}", flush=True)
+    assert err < 1e-6
+    assert abs(n - ref["count"][-1]) <= 0.01 * ref["count"][-1]
+
+
+def test_refinement_beyond_capacity_is_refused_and_state_kept():
+    p = I.refinement_two_stream(n_steps=10)
+    dx = p.L / p.n_cells
+    with B.Simulation(p, l_max=0.0, seg_charges=p.seg_charges, max_tracers=p.total_tracers + 10) as s:
+        x0, v0, _ = s.state()
+        with pytest.raises(B.SicError) as e:
+            s.refine(0.01 * dx)  # would split every segment
+        assert e.value.status == 2
+        x1, v1, _ = s.state()
+        assert np.array_equal(x0, x1) and np.array_equal(v0, v1)
+        assert s.refine(10 * dx) == 0
+        s.step(3)
+
+
+def test_load_state_round_trip_and_uniform_simulation_rejects_charges():
+    p = I.landau_vertical(n_streams=10, n_positions=64, n_cells=32, n_steps=5)
+    with B.Simulation(p) as s:
+        s.step(5)
+        x, v, step = s.state()
+        c = s.charges()
+        nt, _ = s.layout()
+        W = s.diagnostics(history=False)["last"]["W_E"]
+        s.load_state(step, nt, x, v, c)
+        x2, v2, step2 = s.state()
+        assert step2 == step and np.array_equal(x2, x) and np.array_equal(v2, v)
+        s.step(0)  # brings the stale field up to date
+        assert abs(s.diagnostics(history=False)["last"]["W_E"] - W) <= 1e-13 * W
+    u = I.landau(n_sheets=4, n_tracers=64, n_cells=32, n_steps=3)
+    with B.Simulation(u) as s:
+        x, v, step = s.state()
+        with pytest.raises(B.SicError) as e:
+            s.load_state(step, u.n_tracers, x, v, u.seg_charges)
+        assert e.value.status == 6
+        with pytest.raises(B.SicError) as e:
+            s.refine(0.1)
+        assert e.value.status == 6
+
+
+def test_batch_with_segment_charges_matches_alone():
+    prec = B.SIC_SPLIT_U32
+    probs = [I.landau_vertical(n_streams=26, n_positions=160, n_cells=40, n_steps=17),
+             I.landau_vertical(n_streams=12, n_positions=100, n_cells=64, n_steps=23, alpha=0.2),
+             I.landau(n_sheets=8, n_tracers=130, n_cells=64, n_steps=19, alpha=0.1)]
+    # short vertical sheets leave most of each 64-tracer chunk empty: budget
+    # the padded slots
+    slots_needed = sum(int(np.sum((p.n_tracers + 63) // 64)) * 64 for p in probs)
+    b = B.sic_batch_create(slots_needed, 4, 64, precision=prec, flags=B.SIC_BATCH_SEGMENT_CHARGES)
+    try:
+        slots = [B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, p.n_steps,
+                                   precision=prec, seg_charges=p.c_full) for p in probs]
+        B.sic_batch_step(b, 30)
+        assert sorted(B.sic_batch_poll(b)) == sorted(slots)
+        for p, sl in zip(probs, slots):
+            with B.Simulation(p, precision=prec, seg_charges=p.seg_charges) as s:
+                s.step(p.n_steps)
+                x, v, _ = s.state()
+                W = s.diagnostics()["history"]["W_E"]
+            xb, vb, st = B.sic_batch_get_state(b, sl, p.total_tracers)
+            assert st == p.n_steps
+            assert np.array_equal(x, xb) and np.array_equal(v, vb)
+            assert np.array_equal(W, B.sic_batch_result(b, sl)["history"]["W_E"])
+            cb = B.sic_batch_get_charges(b, sl, p.total_tracers)
+            assert np.max(np.abs(cb - p.seg_charges)) <= 1e-15 * np.max(p.seg_charges)  # fixed-point rounding
+    finally:
+        B.sic_batch_destroy(b)
+    plain = B.sic_batch_create(1000, 1, 64)
+    try:
+        p = probs[0]
+        with pytest.raises(B.SicError) as e:
+            B.sic_batch_admit(plain, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, 3,
+                              seg_charges=p.c_full)
+        assert e.value.status == 6
+    finally:
+        B.sic_batch_destroy(plain)
