@@ -31,9 +31,12 @@ using namespace sic;
 namespace {
 
 constexpr int kGraphSteps = 32;         // steps per captured graph
-constexpr int kDefaultGrid = 2048;      // persistent tracer workgroups (8 per CU)
+constexpr int kDefaultGrid = 2048;       // persistent tracer workgroups, single simulations (8 per CU)
+constexpr int kDefaultBatchGrid = 4096;  // batches
 constexpr int kDefaultBlock = 256;       // single simulations
-constexpr int kDefaultBatchBlock = 512;  // batches (measured best of 256/512/1024)
+constexpr int kDefaultBatchBlock = 512;  // batches
+constexpr int kDefaultBatchTile = 256;   // chunks per batch work item (16k tracers per LDS mesh merge)
+// (batch defaults: the autotuner's choice on the 4096-instance mixed batch)
 constexpr int kMinTile = 4;             // chunks per work item, lower bound
 constexpr int kMaxTile = 256;
 
@@ -347,17 +350,29 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
 int slot_tile(const Pool *p, int64_t n_chunks) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
   const int wave_min = p->block / kChunk;
-  if (p->batch) return std::max(128, wave_min);  // ~8k tracers: one mesh merge per 8k tracers
+  if (p->batch) return std::max(kDefaultBatchTile, wave_min);
   const int64_t per = (n_chunks + 2047) / 2048;
   int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(64, per));
   t = (t + 3) / 4 * 4;
   return std::max(t, wave_min);
 }
 
+constexpr size_t kLdsPerCU = 160 * 1024;
+
 void apply_launch_shape(Pool *p) {
-  p->block = p->tune.block_threads > 0 ? p->tune.block_threads : (p->batch ? kDefaultBatchBlock : kDefaultBlock);
+  if (p->tune.block_threads > 0) {
+    p->block = p->tune.block_threads;
+  } else {
+    // Large meshes leave room for one or two workgroups per CU in LDS; give
+    // those workgroups more waves so the CU still has enough loads in flight.
+    const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
+    const size_t per_cu = lds > 0 ? kLdsPerCU / lds : 8;
+    p->block = p->batch ? kDefaultBatchBlock : kDefaultBlock;
+    if (per_cu <= 1) p->block = 1024;
+    else if (per_cu == 2) p->block = std::max(p->block, 512);
+  }
   if (p->tune.grid_blocks > 0) p->grid = p->tune.grid_blocks;
-  else if (p->batch) p->grid = kDefaultGrid;
+  else if (p->batch) p->grid = kDefaultBatchGrid;
   else p->grid = std::max(1, std::min<int>(kDefaultGrid, p->n_items_h));
 }
 

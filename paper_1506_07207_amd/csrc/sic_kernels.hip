@@ -631,11 +631,13 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     // Loads and stores are unconditional (a chunk always has 64 slots; the
     // padding slots of a sheet's last chunk are read and written back
     // unchanged), so the only branches around memory operations are uniform.
+    // The state is streamed once per step: non-temporal loads and stores
+    // keep it from displacing the meshes and tables in the caches.
     auto load_state = [&](int kk, uint64_t &xw, double &v, uint64_t &cw) {
       const int kc = kk < nch ? kk : nch - 1;
       const size_t s = (size_t)(cb + kc) * kChunk + lane;
-      xw = a.xs[s];
-      v = a.vs[s];
+      xw = __builtin_nontemporal_load(a.xs + s);
+      v = __builtin_nontemporal_load(a.vs + s);
       if constexpr (kNeedQ) cw = a.segq[s];
     };
     auto process = [&](int kk, uint64_t xw, double v, uint64_t cw) {
@@ -675,8 +677,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           const uint64_t xn = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
           xw = valid ? xn : xw;
           v = valid ? vn : v;
-          a.xs[s] = xw;
-          a.vs[s] = v;
+          __builtin_nontemporal_store(xw, a.xs + s);
+          __builtin_nontemporal_store(v, a.vs + s);
         }
         const double2 hv2 = make_double2(__longlong_as_double((long long)xw), v);
         if constexpr (kLin) {

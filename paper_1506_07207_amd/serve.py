@@ -203,10 +203,18 @@ class GpuExecutor(Executor):
         self.torch = torch
         self.classes = list(classes)
         self.precision = precision
+        # one stream per size class (default priority): the classes' steps
+        # overlap on the device, so the large-mesh class, whose LDS mesh
+        # leaves room for few workgroups per CU, shares the GPU with the rest
+        self.streams = [torch.cuda.Stream() for _ in self.classes]
         self.batches = [B.sic_batch_create(c.budget_tracers, c.max_slots, c.max_cells, precision=precision,
-                                           history_rows=history_rows) for c in self.classes]
+                                           history_rows=history_rows, stream=st)
+                        for c, st in zip(self.classes, self.streams)]
         self.live = [set() for _ in self.classes]
         self.cache: Dict[int, tuple] = {}
+        # request arrays are built on a stream of their own (default
+        # priority), so building them never waits for the batch's steps
+        self.side = torch.cuda.Stream()
 
     def close(self):
         for b in self.batches:
@@ -220,19 +228,26 @@ class GpuExecutor(Executor):
         raise ValueError("request larger than every size class")
 
     def prepare(self, req):
-        """Host and device arrays of a request (done ahead of admission)."""
+        """Host and device arrays of a request (done ahead of admission, on
+        the side stream; the event marks them ready)."""
         if req.rid in self.cache:
             return self.cache[req.rid]
         p = req.spec.build()
         torch = self.torch
-        x0 = torch.from_numpy(p.line).cuda().repeat(p.n_sheets)
-        v0 = torch.from_numpy(p.sheet_v).cuda().repeat_interleave(int(p.n_tracers[0]))
-        self.cache[req.rid] = (p, x0, v0)
+        with torch.cuda.stream(self.side):
+            line = torch.from_numpy(p.line).to("cuda", non_blocking=True)
+            sv = torch.from_numpy(p.sheet_v).to("cuda", non_blocking=True)
+            x0 = line.repeat(p.n_sheets)
+            v0 = sv.repeat_interleave(int(p.n_tracers[0]))
+            ready = torch.cuda.Event()
+            ready.record(self.side)
+        self.cache[req.rid] = (p, x0, v0, ready)
         return self.cache[req.rid]
 
     def admit(self, req):
         ci = self._class_of(req.spec)
-        p, x0, v0 = self.prepare(req)
+        p, x0, v0, ready = self.prepare(req)
+        ready.synchronize()
         slot = self.B.sic_batch_admit(self.batches[ci], p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x0, v0,
                                       p.n_steps, precision=self.precision, raise_busy=False)
         if slot is None:
