@@ -143,6 +143,41 @@ def time_plain(B, specs, precision, steps, torch):
     return n_tr * steps / dt, n_tr, dt
 
 
+DEPOSIT_BYTES_PER_TRACER = 8   # the position word, read once
+DEPOSIT_BYTES_PER_CELL = 16    # P and D accumulators written
+
+
+def time_deposit(B, I, precision, torch, sheets=8192, tracers=16384, cells=1024, reps=10):
+    """The standalone deposit (sic_deposit) of one large simulation: 8192
+    Landau sheets x 16384 tracers (134M tracers, 1.07 GB of positions, far
+    beyond the caches) on 1024 cells, timed with events on the stream the
+    kernel runs on (the current torch stream)."""
+    p = I.landau(n_sheets=sheets, n_tracers=tracers, n_cells=cells, n_steps=1)
+    x0, v0 = device_inputs(p, torch)
+    sim = B.Simulation(p, precision=precision, history_rows=8, x0=x0, v0=v0)
+    del x0, v0
+    try:
+        for _ in range(2):
+            sim.deposit()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sim.deposit()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+    finally:
+        sim.close()
+        torch.cuda.empty_cache()
+    n = p.total_tracers
+    algo = DEPOSIT_BYTES_PER_TRACER * n + DEPOSIT_BYTES_PER_CELL * cells
+    gbps = algo / (ms * 1e-3) / 1e9
+    return {"tracers": n, "cells": cells, "ms": ms, "segments_per_s": n / (ms * 1e-3), "achieved": gbps,
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS, "algorithmic_bytes": algo,
+            "workload": f"one Landau simulation, {sheets} sheets x {tracers} tracers, {cells} cells, "
+                        "sic_deposit (zeroing of the mesh included)"}
+
+
 def cpu_baseline(specs, seconds):
     """The FP64 oracle (single thread) on whole instances of the same mix, a
     few steps each, until about ``seconds`` of CPU work."""
@@ -248,6 +283,10 @@ def main():
     B.sic_batch_destroy(b)
     torch.cuda.empty_cache()
 
+    deposit = time_deposit(B, I, precision, torch)
+    log(f"standalone deposit: {deposit['ms']:.3f} ms for {deposit['tracers']:.3e} tracers "
+        f"({deposit['achieved']:.0f} GB/s, {deposit['segments_per_s']:.3e} segments/s)")
+
     plain = None
     if not args.no_plain:
         rng = np.random.default_rng(7)
@@ -292,6 +331,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": profiled_traffic(args.precision, args.instances),
                      "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
+        "deposit": deposit,
         "plain": plain,
         "serving": serve,
         "cpu_baseline": cpu,
