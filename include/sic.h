@@ -91,11 +91,12 @@ typedef struct sic_config {
     double l_max;          /* refinement length (section 2.6): after every move, each segment
                               longer than l_max gets a new tracer at its centre with the mean
                               velocity of its two tracers, and each half carries half of its
-                              charge; 0: no refinement.  Single simulations only (a batch
-                              admission with l_max > 0 returns SIC_ENOTSUP). */
-    int64_t max_tracers;   /* tracer capacity for refinement growth; 0: the initial count.  A
-                              refinement that would exceed it fails with SIC_ENOMEM and leaves
-                              the state unchanged. */
+                              charge; 0: no refinement.  In a batch it needs
+                              SIC_BATCH_SEGMENT_CHARGES (else SIC_ENOTSUP). */
+    int64_t max_tracers;   /* tracer capacity for refinement growth; 0: the initial count.  The
+                              simulation reserves room for this many tracers (in a batch the
+                              reservation counts against the budget).  A refinement that would
+                              exceed it fails with SIC_ENOMEM and leaves the state unchanged. */
 } sic_config;
 
 typedef struct sic_sheet {
@@ -274,8 +275,13 @@ sic_status sic_batch_admit(sic_batch *b, const sic_config *cfg, const sic_sheet 
 
 /* Advances every unfinished resident simulation by up to n_steps steps in
  * shared launches (captured HIP graphs); a simulation stops when its own step
- * count is reached.  Async. */
+ * count is reached.  Async.  While a resident simulation refines (l_max > 0),
+ * steps run one at a time and each is followed by a refinement pass of every
+ * refining simulation that took it, as sic_step does (synchronous). */
 sic_status sic_batch_step(sic_batch *b, int64_t n_steps);
+
+/* Tracers per sheet of one slot now, and their total, as sic_get_layout. */
+sic_status sic_batch_get_layout(const sic_batch *b, int32_t slot, int32_t *n_tracers_out, int64_t *total);
 
 /* Synchronises the stream and lists slots whose simulation has finished and
  * has not been reported before (at most cap entries). */

@@ -89,6 +89,7 @@ _SIGS = {
     "sic_batch_create": (_I32, [_I64, _I32, _I32, _I32, _I32, _I32, _I64, _P, _P]),
     "sic_batch_admit": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _I32, _I64, _P]),
     "sic_batch_get_charges": (_I32, [_P, _I32, _P, _I32]),
+    "sic_batch_get_layout": (_I32, [_P, _I32, _P, _P]),
     "sic_batch_step": (_I32, [_P, _I64]),
     "sic_batch_poll": (_I32, [_P, _P, _I32, _P]),
     "sic_batch_result": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
@@ -375,10 +376,11 @@ def sic_batch_create(budget_tracers, max_slots, max_cells, precision=SIC_FP64, h
 
 
 def sic_batch_admit(b, L, n_cells, dt, n_tracers, q, closed, x0, v0, n_steps, precision=SIC_FP64,
-                    raise_busy=True, deposit_order=0, seg_charges=None):
+                    raise_busy=True, deposit_order=0, seg_charges=None, l_max=0.0, max_tracers=0):
     """Returns the slot, or None when the batch is full (SIC_EBUSY) and raise_busy is False."""
     lib = load()
-    cfg = make_config(L, n_cells, dt, precision, deposit_order=deposit_order)
+    cfg = make_config(L, n_cells, dt, precision, deposit_order=deposit_order, l_max=l_max,
+                      max_tracers=max_tracers)
     sheets = make_sheets(n_tracers, q, closed)
     px, kx, kx_ = _as_f64(x0)
     pv, kv, kv_ = _as_f64(v0)
@@ -449,6 +451,14 @@ def sic_batch_get_charges(b, slot: int, n_tracers_total: int, out=None):
     pc, kc, _ = _as_f64(out)
     _check(load().sic_batch_get_charges(b, int(slot), pc, kc), "sic_batch_get_charges", b, batch=True)
     return out
+
+
+def sic_batch_get_layout(b, slot: int, n_sheets: int):
+    nt = np.zeros(int(n_sheets), dtype=np.int32)
+    tot = ctypes.c_int64(0)
+    _check(load().sic_batch_get_layout(b, int(slot), nt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tot)),
+           "sic_batch_get_layout", b, batch=True)
+    return nt, tot.value
 
 
 def sic_batch_release(b, slot: int):

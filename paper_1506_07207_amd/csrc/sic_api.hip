@@ -102,6 +102,7 @@ struct SlotHost {
   double l_max = 0.0;     // refinement length; 0: off
   int64_t max_tracers = 0;
   int32_t chunk_begin = 0, n_chunks = 0;
+  int32_t n_chunks_res = 0;  // chunks reserved from chunk_begin (room to grow by refinement)
   int32_t item_begin = 0, n_items = 0;
   std::vector<int64_t> chunk_in_off;
   int64_t *d_in_off = nullptr;
@@ -916,7 +917,8 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   if (cfg->n_cells > p->max_cells) return fail(p, SIC_EINVAL, "n_cells above the batch max_cells");
   if (mem_kind != SIC_MEM_HOST && mem_kind != SIC_MEM_DEVICE) return fail(p, SIC_EINVAL, "bad mem_kind");
   if (c0 && !p->seg) return fail(p, SIC_ENOTSUP, "per-segment charges need a batch created for them");
-  if (p->batch && cfg->l_max != 0.0) return fail(p, SIC_ENOTSUP, "refinement is for single simulations");
+  if (cfg->l_max != 0.0 && !p->seg)
+    return fail(p, SIC_ENOTSUP, "refinement in a batch needs SIC_BATCH_SEGMENT_CHARGES");
 
   int64_t n_tr = 0;
   std::vector<int32_t> nt((size_t)n_sheets), closed((size_t)n_sheets);
@@ -949,8 +951,14 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
       break;
     }
   if (slot < 0) return fail(p, SIC_EBUSY, "no free slot");
-  if (p->budget > 0 && p->used_tracers + n_tr > p->budget) return fail(p, SIC_EBUSY, "over the tracer budget");
-  const int64_t cb = p->alloc.alloc(n_ch);
+  // A slot reserves room for max_tracers (refinement grows it in place): the
+  // reservation counts against the budget and its chunks are allocated now.
+  const int64_t reserve_tr = std::max<int64_t>(cfg->max_tracers, n_tr);
+  const int64_t n_res = reserve_tr > n_tr ? std::max<int64_t>(n_ch, (reserve_tr + kChunk - 1) / kChunk + n_sheets)
+                                          : n_ch;
+  if (p->budget > 0 && p->used_tracers + reserve_tr > p->budget)
+    return fail(p, SIC_EBUSY, "over the tracer budget");
+  const int64_t cb = p->alloc.alloc(n_res);
   if (cb < 0) return fail(p, SIC_EBUSY, "tracer arena full");
 
   const double total_abs = total_abs_charge(sheets, n_sheets, c0 ? c_host.data() : nullptr);
@@ -977,9 +985,10 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   sh.q_s = q;
   sh.q_scale = q_scale;
   sh.l_max = cfg->l_max;
-  sh.max_tracers = std::max<int64_t>(cfg->max_tracers, n_tr);
+  sh.max_tracers = reserve_tr;
   sh.chunk_begin = (int32_t)cb;
   sh.n_chunks = (int32_t)n_ch;
+  sh.n_chunks_res = (int32_t)n_res;
   sh.state = kStale;
   sh.pending_push = sh.pending_dep = false;
   sh.reported = false;
@@ -1004,7 +1013,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
 
   auto undo = [&]() {
     if (sh.n_items > 0) clear_slot_items(p, slot);
-    p->alloc.release(cb, n_ch);
+    p->alloc.release(cb, n_res);
     sh.live = false;
     sh.chunk_in_off.clear();
   };
@@ -1041,7 +1050,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
     undo();
     return fail(p, SIC_EDEVICE, std::string("admission copies: ") + hipGetErrorString(e));
   }
-  p->used_tracers += n_tr;
+  p->used_tracers += reserve_tr;
   p->used_slots += 1;
   // ingest: place tracers, deposit, solve, half back-kick
   int le = ingest_slot(p, slot, dx0, nullptr, dv0, dc0, nullptr);
@@ -1062,8 +1071,8 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   return SIC_OK;
 }
 
-// Replaces a single simulation's tracers with a new layout (refinement,
-// sic_load_state): nt[s] tracers per sheet from flat device inputs (float64
+// Replaces a slot's tracers with a new layout inside its reserved chunk range
+// (refinement, sic_load_state): nt[s] tracers per sheet from flat device inputs (float64
 // positions or raw state words; velocities; float64 charges, raw charge words
 // or none).  step >= 0 sets the step.  With redeposit the new state is
 // deposited and solved at once (the newest diagnostics row is rewritten);
@@ -1074,24 +1083,18 @@ sic_status pool_relayout(Pool *p, int32_t slot, const std::vector<int32_t> &nt, 
   int64_t n_tr = 0;
   for (int32_t t : nt) n_tr += t;
   const int64_t n_ch = chunks_for(nt);
-  if (n_ch > p->chunk_cap || n_tr > sh.max_tracers)
+  if (n_ch > sh.n_chunks_res || n_tr > sh.max_tracers)
     return fail(p, SIC_ENOMEM, "refined or loaded state exceeds the tracer capacity");
   HIPCHK(p, hipStreamSynchronize(p->stream));
   const int tile0 = p->tile, grid0 = p->grid;
-  // a single simulation owns the whole arena: after the release the new
-  // range always fits
   sic_status st = clear_slot_items(p, slot);
   if (st != SIC_OK) return st;
-  p->alloc.release(sh.chunk_begin, sh.n_chunks);
-  const int64_t cb = p->alloc.alloc(n_ch);
-  if (cb < 0) return fail(p, SIC_EDEVICE, "tracer arena fragmented");
+  const int64_t cb = sh.chunk_begin;  // the new layout stays inside the reservation
   Layout L;
   build_layout(slot, cb, nt, sh.closed_s, sh.q_s, sh.q_scale, p->prec != kFP64, &L);
-  p->used_tracers += n_tr - sh.n_tracers;
   sh.n_tracers = n_tr;
   sh.n_tracers_s = nt;
   sh.chunk_in_off = L.in_off;
-  sh.chunk_begin = (int32_t)cb;
   sh.n_chunks = (int32_t)n_ch;
   st = place_slot_items(p, slot);
   if (st != SIC_OK) return st;
@@ -1147,7 +1150,7 @@ sic_status ensure_refine_scratch(Pool *p, int64_t stage_tracers) {
 // One refinement pass over a single simulation (section 2.6).
 sic_status pool_refine(Pool *p, int32_t slot, double l_max, int64_t *inserted) {
   if (inserted) *inserted = 0;
-  if (!p->seg || p->batch) return fail(p, SIC_ENOTSUP, "refinement needs a simulation with per-segment charges");
+  if (!p->seg) return fail(p, SIC_ENOTSUP, "refinement needs per-segment charges (or l_max at creation)");
   if (!(l_max > 0.0) || !std::isfinite(l_max)) return fail(p, SIC_EINVAL, "l_max must be positive and finite");
   SlotHost &sh = p->slots[slot];
   if (sh.state != kField) return fail(p, SIC_ESTATE, "refinement needs the field of the current step");
@@ -1195,7 +1198,7 @@ sic_status pool_refine(Pool *p, int32_t slot, double l_max, int64_t *inserted) {
   }
   if (add == 0) return SIC_OK;
   const int64_t n_new = sh.n_tracers + add;
-  if (n_new > sh.max_tracers || chunks_for(nt) > p->chunk_cap)
+  if (n_new > sh.max_tracers || chunks_for(nt) > sh.n_chunks_res)
     return fail(p, SIC_ENOMEM, "refinement exceeds the tracer capacity");
   st = ensure_refine_scratch(p, n_new);
   if (st != SIC_OK) return st;
@@ -1219,8 +1222,8 @@ sic_status pool_release(Pool *p, int32_t slot) {
   HIPCHK(p, hipStreamSynchronize(p->stream));
   sic_status st = clear_slot_items(p, slot);
   if (st != SIC_OK) return st;
-  p->alloc.release(sh.chunk_begin, sh.n_chunks);
-  p->used_tracers -= sh.n_tracers;
+  p->alloc.release(sh.chunk_begin, sh.n_chunks_res);
+  p->used_tracers -= sh.max_tracers;
   p->used_slots -= 1;
   sh.live = false;
   sh.chunk_in_off.clear();
@@ -1374,7 +1377,7 @@ sic_status pool_load_state(Pool *p, int64_t step, const int32_t *n_tracers, cons
     if (nt[s] < 2) return fail(p, SIC_EINVAL, "every sheet needs at least 2 tracers");
     n += nt[s];
   }
-  if (n > sh.max_tracers || chunks_for(nt) > p->chunk_cap)
+  if (n > sh.max_tracers || chunks_for(nt) > sh.n_chunks_res)
     return fail(p, SIC_ENOMEM, "state exceeds the tracer capacity");
   if (mem_kind == SIC_MEM_HOST &&
       (!all_finite_host(x, n) || !all_finite_host(v, n) || (c && !all_finite_host(c, n))))
@@ -1498,6 +1501,33 @@ const char *status_str(sic_status s) {
     case SIC_ENOTSUP: return "not supported";
   }
   return "unknown status";
+}
+
+// Batch steps.  Without refining slots: captured graphs of up to 32 steps.
+// With refining slots (l_max > 0): one step at a time, each followed by a
+// refinement pass of every refining slot that took the step.
+sic_status batch_step(Pool *p, int64_t n) {
+  std::vector<int32_t> refining;
+  for (int32_t i = 0; i < p->slot_cap; ++i)
+    if (p->slots[i].live && p->slots[i].l_max > 0.0) refining.push_back(i);
+  if (refining.empty()) return run_fused(p, n);
+  for (int64_t k = 0; k < n; ++k) {
+    std::vector<int32_t> stepping;
+    for (int32_t slot : refining) {
+      InstDesc I;
+      sic_status st = read_inst(p, slot, &I);
+      if (st != SIC_OK) return st;
+      if (I.active) stepping.push_back(slot);
+    }
+    if (stepping.empty()) return run_fused(p, n - k);  // no refining slot left to advance
+    sic_status st = run_fused(p, 1);
+    if (st != SIC_OK) return st;
+    for (int32_t slot : stepping) {
+      st = pool_refine(p, slot, p->slots[slot].l_max, nullptr);
+      if (st != SIC_OK) return st;
+    }
+  }
+  return SIC_OK;
 }
 
 sic_status apply_tuning(Pool *p, const sic_tuning *t) {
@@ -1696,7 +1726,17 @@ sic_status sic_batch_get_charges(sic_batch *b, int32_t slot, double *seg_charges
 sic_status sic_batch_step(sic_batch *b, int64_t n_steps) {
   if (!b) return SIC_EINVAL;
   if (n_steps < 0) return fail(b->pool, SIC_EINVAL, "n_steps < 0");
-  return run_fused(b->pool, n_steps);
+  return batch_step(b->pool, n_steps);
+}
+
+sic_status sic_batch_get_layout(const sic_batch *b, int32_t slot, int32_t *n_tracers_out, int64_t *total) {
+  if (!b) return SIC_EINVAL;
+  const Pool *p = b->pool;
+  if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return SIC_EINVAL;
+  const SlotHost &sh = p->slots[slot];
+  if (n_tracers_out) std::memcpy(n_tracers_out, sh.n_tracers_s.data(), sizeof(int32_t) * sh.n_tracers_s.size());
+  if (total) *total = sh.n_tracers;
+  return SIC_OK;
 }
 
 sic_status sic_batch_poll(sic_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done) {

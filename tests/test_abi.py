@@ -76,6 +76,7 @@ def test_invalid_arguments_are_rejected_before_any_device_work(lib):
     assert lib.sic_get_charges(None, None, 0) == 1
     assert lib.sic_load_state(None, 0, None, None, None, None, 0) == 1
     assert lib.sic_batch_get_charges(None, 0, None, 0) == 1
+    assert lib.sic_batch_get_layout(None, 0, None, ctypes.byref(n)) == 1
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

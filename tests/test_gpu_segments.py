@@ -337,3 +337,98 @@ def test_batch_with_segment_charges_matches_alone():
         assert e.value.status == 6
     finally:
         B.sic_batch_destroy(plain)
+
+
+def test_batch_refinement_matches_alone_bitwise():
+    """Refining simulations in a batch (each growing inside its own
+    reservation) beside non-refining ones: every instance ends bitwise equal
+    to the same simulation run alone (split U32 form)."""
+    prec = B.SIC_SPLIT_U32
+    ts = I.refinement_two_stream(n_steps=330)
+    dx = ts.L / ts.n_cells
+    specs = [(ts, dx, 60_000), (I.refinement_two_stream(n_steps=300, ppc=8), 0.5 * dx, 80_000),
+             (I.landau(n_sheets=8, n_tracers=130, n_cells=64, n_steps=250, alpha=0.1), 0.0, 0),
+             (I.landau_vertical(n_streams=20, n_positions=90, n_cells=40, n_steps=200), 0.0, 0)]
+    budget = sum(max(mt, int(np.sum((p.n_tracers + 63) // 64)) * 64) + 64 * len(p.n_tracers) for p, _, mt in specs)
+    b = B.sic_batch_create(budget, 8, 128, precision=prec, flags=B.SIC_BATCH_SEGMENT_CHARGES)
+    try:
+        slots = [B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, p.n_steps,
+                                   precision=prec, seg_charges=p.c_full, l_max=lm, max_tracers=mt)
+                 for p, lm, mt in specs]
+        B.sic_batch_step(b, 340)
+        assert sorted(B.sic_batch_poll(b)) == sorted(slots)
+        for (p, lm, mt), sl in zip(specs, slots):
+            nt_b, tot_b = B.sic_batch_get_layout(b, sl, len(p.n_tracers))
+            # alone with per-segment charges too, so both hold the same
+            # fixed-point charge words
+            with B.Simulation(p, precision=prec, l_max=lm, max_tracers=mt, seg_charges=p.seg_charges) as s:
+                s.step(p.n_steps)
+                nt_a, tot_a = s.layout()
+                x, v, _ = s.state()
+                W = s.diagnostics()["history"]["W_E"]
+                c = s.charges()
+            print(f"slot {sl}: {tot_b} tracers in the batch, {tot_a} alone", flush=True)
+            assert np.array_equal(nt_a, nt_b) and tot_a == tot_b
+            if lm:
+                assert tot_a > p.total_tracers  # it refined
+            xb, vb, st = B.sic_batch_get_state(b, sl, tot_b)
+            assert st == p.n_steps
+            assert np.array_equal(x, xb) and np.array_equal(v, vb)
+            assert np.array_equal(W, B.sic_batch_result(b, sl)["history"]["W_E"])
+            assert np.array_equal(c, B.sic_batch_get_charges(b, sl, tot_b))
+        used, _ = B.sic_batch_usage(b)
+        assert used == sum(max(mt, p.total_tracers) for p, _, mt in specs)
+        for sl in slots:
+            B.sic_batch_release(b, sl)
+        assert B.sic_batch_usage(b) == (0, 0)
+    finally:
+        B.sic_batch_destroy(b)
+
+
+def test_batch_refinement_fp64_follows_oracle():
+    p = I.refinement_two_stream(n_steps=330)
+    dx = p.L / p.n_cells
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, l_max=dx,
+                    capacity=100_000)
+    other = I.landau(n_sheets=16, n_tracers=256, n_cells=128, n_steps=400, alpha=0.05)
+    b = B.sic_batch_create(200_000, 4, 128, flags=B.SIC_BATCH_SEGMENT_CHARGES)
+    try:
+        s1 = B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, p.n_steps,
+                               l_max=dx, max_tracers=100_000)
+        s2 = B.sic_batch_admit(b, other.L, other.n_cells, other.dt, other.n_tracers, other.q, other.closed,
+                               other.x0, other.v0, other.n_steps)
+        B.sic_batch_step(b, 100)
+        B.sic_batch_step(b, 300)
+        nt, tot = B.sic_batch_get_layout(b, s1, len(p.n_tracers))
+        h = B.sic_batch_result(b, s1)["history"]
+        assert tot == ref["count"][-1] > ref["count"][0]
+        assert np.array_equal(nt, ref["n_tracers"])
+        err = envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt)
+        print(f"batch refinement fp64: {tot} tracers, envelope error {err:.3e}", flush=True)
+        assert err < 1e-10
+        ro = O.run_problem(other)
+        ho = B.sic_batch_result(b, s2)["history"]
+        assert envelope_rel(ho["W_E"], ro["hist"][:, 2], other.dt) < 1e-10
+    finally:
+        B.sic_batch_destroy(b)
+
+
+def test_batch_refinement_needs_segment_charges_and_budget():
+    p = I.refinement_two_stream(n_steps=10)
+    plain = B.sic_batch_create(100_000, 2, 128)
+    try:
+        with pytest.raises(B.SicError) as e:
+            B.sic_batch_admit(plain, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, 10, l_max=0.1)
+        assert e.value.status == 6
+    finally:
+        B.sic_batch_destroy(plain)
+    b = B.sic_batch_create(50_000, 4, 128, flags=B.SIC_BATCH_SEGMENT_CHARGES)
+    try:
+        B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, 10, l_max=0.1,
+                          max_tracers=40_000)
+        assert B.sic_batch_usage(b) == (40_000, 1)
+        # the reservation counts: a second one does not fit the budget
+        assert B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, 10, l_max=0.1,
+                                 max_tracers=40_000, raise_busy=False) is None
+    finally:
+        B.sic_batch_destroy(b)
