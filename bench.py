@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split_f32", "split_u32"])
+    ap.add_argument("--deposit-order", type=int, default=0, choices=[0, 1, 2],
+                    help="0 constant segments, 1 piecewise-linear segments, 2 first-order weighting")
+    ap.add_argument("--segment-charges", action="store_true",
+                    help="store a charge per segment (the form vertical sheets and refinement use)")
     ap.add_argument("--plain-instances", type=int, default=256)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,17 +92,19 @@ def device_inputs(problem, torch):
     return x0, v0
 
 
-def build_batch(B, specs, precision, torch, history_rows=256):
+def build_batch(B, specs, precision, torch, history_rows=256, deposit_order=0, seg=False):
     total = sum(s.tracers for s in specs)
     max_cells = max(s.n_cells for s in specs)
-    b = B.sic_batch_create(total, len(specs), max_cells, precision=precision, history_rows=history_rows)
+    b = B.sic_batch_create(total, len(specs), max_cells, precision=precision, history_rows=history_rows,
+                           deposit_order=deposit_order, flags=B.SIC_BATCH_SEGMENT_CHARGES if seg else 0)
     t0 = time.time()
     cells = 0
     for i, s in enumerate(specs):
         p = s.build()
         x0, v0 = device_inputs(p, torch)
+        c0 = torch.from_numpy(p.seg_charges).cuda() if seg else None
         B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x0, v0, p.n_steps,
-                          precision=precision)
+                          precision=precision, deposit_order=deposit_order, seg_charges=c0)
         cells += p.n_cells
         if (i + 1) % 512 == 0:
             log(f"admitted {i + 1}/{len(specs)} instances ({time.time() - t0:.1f}s)")
@@ -283,7 +289,8 @@ def main():
     specs = I.batch_mix(args.instances)
     log(f"building batch of {len(specs)} instances ({args.precision})")
     t_setup = time.time()
-    b, total, cells = build_batch(B, specs, precision, torch)
+    b, total, cells = build_batch(B, specs, precision, torch, deposit_order=args.deposit_order,
+                                  seg=args.segment_charges)
     tuned = None
     if args.tile or args.block or args.grid:
         B.sic_batch_set_tuning(b, args.tile, args.block, args.grid)
@@ -301,7 +308,11 @@ def main():
     log(f"batched: {ms_per_step:.3f} ms/step, {value:.4e} tracer-updates/s")
 
     tr_ms, so_ms = kernel_timing(B, b)
-    bytes_launch = BYTES_PER_TRACER * total + BYTES_PER_CELL * cells
+    # a charge word per tracer is read with per-segment charges; linear
+    # segments also read and clear a ramp array per cell
+    bytes_tracer = BYTES_PER_TRACER + (8 if args.segment_charges else 0)
+    bytes_cell = BYTES_PER_CELL + (8 if args.deposit_order == 1 else 0)
+    bytes_launch = bytes_tracer * total + bytes_cell * cells
     achieved = bytes_launch / (tr_ms * 1e-3) / 1e9
     copy_gbps = B.sic_copy_bandwidth(4 << 30, 5)
     log(f"tracer kernel {tr_ms:.3f} ms ({achieved:.0f} GB/s), solve kernel {so_ms:.3f} ms, copy {copy_gbps:.0f} GB/s")
@@ -352,9 +363,12 @@ def main():
         "config": {"workload": f"batched mix of {len(specs)} SIC 1D1V instances (Landau/two-stream, "
                                "32-512 sheets x 64-2048 tracers, 64-1024 cells), one shared step",
                    "instances": len(specs), "tracers": total, "cells": cells, "precision": args.precision,
+                   "deposit_order": args.deposit_order, "segment_charges": bool(args.segment_charges),
                    "tuning": tuning, "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": profiled_traffic(args.precision, args.instances),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": (profiled_traffic(args.precision, args.instances)
+                                                                    if args.deposit_order == 0 and not args.segment_charges
+                                                                    else None),
                      "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
         "deposit": deposit,
