@@ -448,7 +448,12 @@ __device__ __forceinline__ double linear_gradient(const SegGeo &m, const SegGeo 
   const double dm = min_image_cells(m.c - i.c, half_nc, nc);
   const double dp = min_image_cells(p.c - i.c, half_nc, nc);
   if (!((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))) return 0.0;
-  return (qp / fabs(p.d) - qm / fabs(m.d)) / (dp - dm);
+  // (qp / |p.d| - qm / |m.d|) / (dp - dm) with one division; the quotient
+  // form only where the common denominator would leave the normal range
+  const double lm = fabs(m.d), lp = fabs(p.d);
+  const double den = (lm * lp) * (dp - dm);
+  if (fabs(den) > 0x1p-900) return (qp * lm - qm * lp) / den;
+  return (qp / lp - qm / lm) / (dp - dm);
 }
 
 // FP64: deposit segment i given its geometry and gradient (mesh units).
@@ -521,104 +526,98 @@ __device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, 
 // Every slice of the box is assigned to the grid points (cell centres) with
 // the hat W_1.  With s = u - 1/2 (grid point j at s = j) and r the charge per
 // mesh unit, grid point j receives r [H(s1 - j) - H(s0 - j)], H the
-// antiderivative of the unit hat.  Hats fully inside the segment
-// (j in [ceil(s0) + 1, floor(s1) - 1]) receive r through the difference
-// array; the remaining contributions are on grid points floor(s0),
-// floor(s0) + 1, floor(s1), floor(s1) + 1.
-
-__device__ __forceinline__ double hat_antiderivative(double t) {
-  if (t <= -1.0) return 0.0;
-  if (t <= 0.0) return 0.5 * (1.0 + t) * (1.0 + t);
-  if (t <= 1.0) return 1.0 - 0.5 * (1.0 - t) * (1.0 - t);
-  return 1.0;
-}
-
-// Visits the partial grid points j of a segment [s0, s1] (s1 > s0) in
-// order, calling f(j, integral of the hat of j over the segment); returns the
-// run of fully covered hats in [full_lo, full_hi].
-template <class F>
-__device__ __forceinline__ void cic_partials(double s0, double s1, int &full_lo, int &full_hi, F f) {
-  const int f0 = (int)floor(s0);
-  const int f1 = (int)floor(s1);
-  full_lo = (int)ceil(s0) + 1;
-  full_hi = f1 - 1;
-  const int cand[4] = {f0, f0 + 1, f1, f1 + 1};
-  int last = f0 - 1;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int j = cand[k];
-    if (j <= last) continue;  // duplicate
-    last = j;
-    if (j >= full_lo && j <= full_hi) continue;  // a fully covered hat
-    f(j, hat_antiderivative(s1 - (double)j) - hat_antiderivative(s0 - (double)j));
-  }
-}
+// antiderivative of the unit hat.  For a point s = f + t (f = floor(s)), the
+// vector H(s - j) over j is 1 up to j = f, less (1 - t)^2 / 2 at f, plus
+// t^2 / 2 at f + 1.  With n = f1 - f0 the segment therefore adds
+//   f0: a0                 f0 + 1: r - b0 (n >= 1)
+//   f0 + 2 .. f1 - 1: r    f1: r - a1 (n >= 2)        f1 + 1: b1 (n >= 1)
+// where a = r (1 - t)^2 / 2 and b = r t^2 / 2 at either end; the terms that
+// land on one grid point are summed first (n = 0: a0 - a1 at f0, b1 - b0 at
+// f0 + 1; n = 1: r - b0 - a1 at f0 + 1), so a segment costs as many LDS
+// additions as it has distinct grid points, up to four, plus the difference
+// array pair for a run of fully covered ones.
 
 __device__ __forceinline__ void deposit_cic_fp64(double u_a, double d_mesh, double q, const Geo &g, double *sP,
                                                  double *sD) {
-  if (d_mesh == 0.0) {  // a point: its hat weights
-    const double s = u_a - 0.5;
-    const double f = floor(s);
-    const double w = s - f;
-    lds_add(sP + wrap_cell((int)f, g.nc), q * (1.0 - w));
-    lds_add(sP + wrap_cell((int)f + 1, g.nc), q * w);
-    return;
-  }
   const double s0 = (d_mesh > 0.0 ? u_a : u_a + d_mesh) - 0.5;
   const double s1 = (d_mesh > 0.0 ? u_a + d_mesh : u_a) - 0.5;
-  if (!(s1 > s0)) {
-    const double f = floor(s0);
-    const double w = s0 - f;
-    lds_add(sP + wrap_cell((int)f, g.nc), q * (1.0 - w));
-    lds_add(sP + wrap_cell((int)f + 1, g.nc), q * w);
+  const double fl0 = floor(s0);
+  const double t0 = s0 - fl0;
+  const int f0 = (int)fl0;
+  if (!(s1 > s0)) {  // a point: its hat weights
+    lds_add(sP + wrap_cell(f0, g.nc), q * (1.0 - t0));
+    lds_add(sP + wrap_cell(f0 + 1, g.nc), q * t0);
     return;
   }
+  const double fl1 = floor(s1);
+  const double t1 = s1 - fl1;
+  const int n = (int)fl1 - f0;
   const double r = q / (s1 - s0);
-  int lo, hi;
-  cic_partials(s0, s1, lo, hi, [&](int j, double h) { lds_add(sP + wrap_cell(j, g.nc), r * h); });
-  if (hi >= lo) add_run(sD, lo, hi, r, g.nc);
+  const double hr = 0.5 * r;
+  const double a0 = hr * ((1.0 - t0) * (1.0 - t0)), b0 = hr * (t0 * t0);
+  const double a1 = hr * ((1.0 - t1) * (1.0 - t1)), b1 = hr * (t1 * t1);
+  lds_add(sP + wrap_cell(f0, g.nc), n == 0 ? a0 - a1 : a0);
+  lds_add(sP + wrap_cell(f0 + 1, g.nc), n == 0 ? b1 - b0 : (n == 1 ? (r - b0) - a1 : r - b0));
+  if (n >= 1) {
+    lds_add(sP + wrap_cell(f0 + n + 1, g.nc), b1);
+    if (n >= 2) {
+      lds_add(sP + wrap_cell(f0 + n, g.nc), r - a1);
+      if (n >= 3) add_run(sD, f0 + 2, f0 + n - 1, r, g.nc);
+    }
+  }
 }
 
+// Split form: the same terms in fixed-point units; the term at f1 + 1 (at
+// f0 + 1 when n = 0) takes the remainder so the segment deposits exactly qf.
 __device__ __forceinline__ void deposit_cic_split(double u_a, double d_mesh, long long qf, const Geo &g,
                                                   unsigned long long *sP, unsigned long long *sD) {
   const double qd = (double)qf;
-  if (d_mesh == 0.0) {
-    const double s = u_a - 0.5;
-    const double f = floor(s);
-    const long long p1 = llrint(qd * (s - f));
-    lds_add(sP + wrap_cell((int)f, g.nc), (unsigned long long)(qf - p1));
-    lds_add(sP + wrap_cell((int)f + 1, g.nc), (unsigned long long)p1);
-    return;
-  }
   const double s0 = (d_mesh > 0.0 ? u_a : u_a + d_mesh) - 0.5;
   const double s1 = (d_mesh > 0.0 ? u_a + d_mesh : u_a) - 0.5;
+  const double fl0 = floor(s0);
+  const double t0 = s0 - fl0;
+  const int f0 = (int)fl0;
   if (!(s1 > s0)) {
-    const double f = floor(s0);
-    const long long p1 = llrint(qd * (s0 - f));
-    lds_add(sP + wrap_cell((int)f, g.nc), (unsigned long long)(qf - p1));
-    lds_add(sP + wrap_cell((int)f + 1, g.nc), (unsigned long long)p1);
+    const long long p1 = llrint(qd * t0);
+    lds_add(sP + wrap_cell(f0, g.nc), (unsigned long long)(qf - p1));
+    lds_add(sP + wrap_cell(f0 + 1, g.nc), (unsigned long long)p1);
     return;
   }
+  const double fl1 = floor(s1);
+  const double t1 = s1 - fl1;
+  const int n = (int)fl1 - f0;
   const double r = qd / (s1 - s0);
-  int lo, hi;
-  long long rest = qf;
-  int last_j = 0;
-  long long last_p = 0;
-  bool have = false;
-  cic_partials(s0, s1, lo, hi, [&](int j, double h) {
-    if (have) lds_add(sP + wrap_cell(last_j, g.nc), (unsigned long long)last_p);
-    last_j = j;
-    last_p = llrint(r * h);
-    rest -= last_p;
-    have = true;
-  });
-  if (hi >= lo) {
-    const long long G = llrint(r);
-    add_run(sD, lo, hi, (unsigned long long)G, g.nc);
-    rest -= (long long)(hi - lo + 1) * G;
+  const double hr = 0.5 * r;
+  const double a0 = hr * ((1.0 - t0) * (1.0 - t0)), b0 = hr * (t0 * t0);
+  const double a1 = hr * ((1.0 - t1) * (1.0 - t1));
+  const long long p0 = llrint(n == 0 ? a0 - a1 : a0);
+  if (n == 0) {
+    lds_add(sP + wrap_cell(f0, g.nc), (unsigned long long)p0);
+    lds_add(sP + wrap_cell(f0 + 1, g.nc), (unsigned long long)(qf - p0));
+    return;
   }
-  // the last partial grid point takes the remainder: exactly qf in total
-  lds_add(sP + wrap_cell(last_j, g.nc), (unsigned long long)(last_p + rest));
+  const long long p1 = llrint(n == 1 ? (r - b0) - a1 : r - b0);
+  long long rest = qf - p0 - p1;
+  lds_add(sP + wrap_cell(f0, g.nc), (unsigned long long)p0);
+  lds_add(sP + wrap_cell(f0 + 1, g.nc), (unsigned long long)p1);
+  if (n >= 2) {
+    const long long pn = llrint(r - a1);
+    lds_add(sP + wrap_cell(f0 + n, g.nc), (unsigned long long)pn);
+    rest -= pn;
+    if (n >= 3) {
+      const long long G = llrint(r);
+      add_run(sD, f0 + 2, f0 + n - 1, (unsigned long long)G, g.nc);
+      rest -= (long long)(n - 2) * G;
+    }
+  }
+  lds_add(sP + wrap_cell(f0 + n + 1, g.nc), (unsigned long long)rest);
+}
+
+// A 64-bit value of one lane, broadcast to the wave.
+__device__ __forceinline__ uint64_t read_lane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 __device__ __forceinline__ double nan_max(double a, double b) {
@@ -828,21 +827,24 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       }
       if constexpr (kDep && kLin) {
         // Tracers i-1, i+1, i+2 of segment i: lane shuffles inside the chunk,
-        // halo copies (moved from their pre-step state when this kernel also
-        // moves) past its ends.
+        // halo copies past its ends.  Lanes 0, 1 and 2 take the previous, next
+        // and next-but-one halo tracer (moved from its pre-step state when this
+        // kernel also moves) and broadcast it, so the wave pays for one move.
         const int2 lk = sLinks[kk];
-        auto moved = [&](const double2 h) -> uint64_t {
-          uint64_t w = (uint64_t)__double_as_longlong(h.x);
-          if constexpr (kMove) {
-            const double e = gather_field(sE, mesh_pos<PREC>(w, g.inv_dx), g.nc);
-            w = drift<PREC>(w, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
-          }
-          return w;
-        };
         const bool have_n1 = ch.partner >= 0, have_n2 = lk.y >= 0, have_pv = lk.x >= 0;
-        const uint64_t hn1 = have_n1 ? moved(sHalo[kk]) : 0ull;
-        const uint64_t hn2 = have_n2 ? moved(sHalo2[kk]) : 0ull;
-        const uint64_t hpv = have_pv ? moved(sHaloP[kk]) : 0ull;
+        uint64_t hw = xw;
+        if (lane < 3 && (lane == 0 ? have_pv : (lane == 1 ? have_n1 : have_n2))) {
+          // sHalo, sHalo2 and sHaloP are consecutive tile_cap-long arrays
+          const double2 h = sHalo[(lane == 0 ? 2 : lane - 1) * a.tile_cap + kk];
+          hw = (uint64_t)__double_as_longlong(h.x);
+          if constexpr (kMove) {
+            const double e = gather_field(sE, mesh_pos<PREC>(hw, g.inv_dx), g.nc);
+            hw = drift<PREC>(hw, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
+          }
+        }
+        const uint64_t hpv = read_lane64(hw, 0);
+        const uint64_t hn1 = read_lane64(hw, 1);
+        const uint64_t hn2 = read_lane64(hw, 2);
         const uint64_t up1 = (uint64_t)__shfl_up((long long)xw, 1, 64);
         const uint64_t dn1 = (uint64_t)__shfl_down((long long)xw, 1, 64);
         const uint64_t dn2 = (uint64_t)__shfl_down((long long)xw, 2, 64);
