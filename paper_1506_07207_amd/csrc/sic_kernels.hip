@@ -276,21 +276,15 @@ __device__ __forceinline__ double deposit_split(uint64_t wa, uint64_t wb, long l
 // deposit; on a dense sheet a wavefront issues LDS atomics only where it
 // crosses faces, instead of one or two per tracer.  In fixed point every term
 // is an integer and the terms telescope, so each chunk deposits exactly its
-// charge.  Used for deposits that do not also move the tracers, where the
-// LDS atomics, not the state traffic, set the pace (measured: 17 % faster
-// than the per-segment form there, 8 % slower inside the fused step).
-
-// Cell of a tracer before the periodic wrap (-1 .. nc - 1); a point on a face
-// belongs to the lower cell (the W_0 tie rule, which decides where a
-// zero-length segment puts its charge).
-template <int PREC>
-__device__ __forceinline__ int point_cell_raw(uint64_t w, double dx) {
-  if constexpr (PREC == kFP64) {
-    return (int)ceil(__longlong_as_double((long long)w) / dx) - 1;
-  } else {
-    return split_frac<PREC>(split_bits(w)) == 0.0 ? split_cell(w) - 1 : split_cell(w);
-  }
-}
+// charge.  Used for deposits that do not also move the tracers (the
+// deposit-only kernel below), where the per-tracer arithmetic, not the state
+// traffic, sets the pace; inside the fused step the per-segment form is
+// faster (measured: 8 %).
+//
+// Cells here are raw: -1 .. nc - 1 before the periodic wrap, a point on a
+// face belonging to the lower cell (the W_0 tie rule, which decides where a
+// zero-length segment puts its charge): ceil(x / dx) - 1 with the rounded
+// quotient.
 
 template <class T>
 struct Crossings {
@@ -349,17 +343,17 @@ __device__ __forceinline__ Crossings<T> face_crossings(uint64_t wa, uint64_t wb,
   }
   if (c.hi < c.lo) return c;
   const double len = fabs(dm);
-  double fr = dm > 0.0 ? ((double)c.lo - ua) / len : (ua - (double)c.hi) / len;
-  fr = fmin(fmax(fr, 0.0), 1.0);  // share of the segment before its first face
+  // length of the segment before its first face, and the charge on it
+  const double before = fmin(fmax(dm > 0.0 ? (double)c.lo - ua : ua - (double)c.hi, 0.0), len);
   if constexpr (PREC == kFP64) {
     c.w = q / len;
-    c.cf = S + q * fr;
+    c.cf = S + c.w * before;
     c.cl = c.cf + (double)(c.hi - c.lo) * c.w;
   } else {
-    const double qd = (double)(long long)q;
-    const long long wfix = llrint(qd / len);
+    const double r = (double)(long long)q / len;
+    const long long wfix = llrint(r);
     c.w = (T)wfix;
-    c.cf = S + (T)llrint(qd * fr);
+    c.cf = S + (T)llrint(r * before);
     c.cl = c.cf + (T)((long long)(c.hi - c.lo) * wfix);
   }
   return c;
@@ -769,8 +763,10 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     // The state is streamed once per step: non-temporal loads and stores
     // keep it from displacing the meshes and tables in the caches.
     auto load_state = [&](int kk, uint64_t &xw, double &v, uint64_t &cw) {
-      const int kc = kk < nch ? kk : nch - 1;
-      const size_t s = (size_t)(cb + kc) * kChunk + lane;
+      // past the item's last chunk every lane reads the item's first slot: the
+      // loads are still issued, so the count of loads in flight is the same at
+      // every stage and the wait before a stage leaves the later ones in flight
+      const size_t s = kk < nch ? (size_t)(cb + kk) * kChunk + lane : (size_t)cb * kChunk;
       xw = __builtin_nontemporal_load(a.xs + s);
       if constexpr (kField) v = __builtin_nontemporal_load(a.vs + s);  // a deposit alone needs no velocity
       if constexpr (kNeedQ) cw = a.segq[s];
@@ -919,22 +915,6 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
             }
           }
         }
-        // constant segments: this lane's charge (0 without a segment), the
-        // chunk's charge before it, and the cells of its two ends
-        constexpr bool kCross = ORDER == 0 && !kMove;  // face-crossing form
-        acc_t ql = (acc_t)0, S = (acc_t)0;
-        int pa = 0, pb = 0;
-        if constexpr (kCross) {
-          if (has_seg) {
-            if constexpr (SEG) ql = PREC == kFP64 ? (acc_t)__longlong_as_double((long long)cw) : (acc_t)cw;
-            else ql = PREC == kFP64 ? (acc_t)ch.q : (acc_t)ch.q_fix;
-          }
-          if constexpr (SEG) S = wave_exclusive_sum(ql);
-          else S = (PREC == kFP64 ? (acc_t)ch.q : (acc_t)ch.q_fix) * (acc_t)lane;
-          pa = point_cell_raw<PREC>(xw, g.dx);
-          pb = __shfl_down(pa, 1, 64);  // the next tracer's start cell
-          if (tail) pb = point_cell_raw<PREC>(pw, g.dx);
-        }
         if (has_seg) {
           double len;
           double q0 = ch.q;
@@ -963,26 +943,12 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
               if constexpr (PREC == kFP64) deposit_cic_fp64(ua, dm, q0, g, sP, sD);
               else deposit_cic_split(ua, dm, q0_fix, g, sP, sD);
             }
-          } else if constexpr (!kCross) {
+          } else {
             if constexpr (PREC == kFP64) {
               len = deposit_fp64(__longlong_as_double((long long)xw), __longlong_as_double((long long)pw), q0, g,
                                  sP, sD);
             } else {
               len = deposit_split<PREC>(xw, pw, q0_fix, g, sP, sD);
-            }
-          } else {
-            const Crossings<acc_t> cr = face_crossings<PREC, acc_t>(xw, pw, pa, pb, ql, S, g, &len);
-            const bool crossing = cr.hi >= cr.lo;
-            if (crossing) {
-              lds_add(sP + wrap_cell(pa, g.nc), cr.cf);
-              if (cr.hi > cr.lo) add_run(sD, cr.lo, cr.hi - 1, cr.w, g.nc);
-            }
-            // the chunk's last segment adds the chunk's charge where it ends
-            const bool last = lane == n_valid - 1 || (lane == n_valid - 2 && ch.partner < 0);
-            if (crossing || last) {
-              acc_t e = crossing ? (acc_t)(0 - cr.cl) : (acc_t)0;
-              if (last) e += S + ql;
-              lds_add(sP + wrap_cell(pb, g.nc), e);
             }
           }
           ms = nan_max(ms, len);
@@ -998,14 +964,15 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       xr[j] = cr_[j] = 0;
       vr[j] = 0.0;
       load_state(wave + j * nwaves, xr[j], vr[j], cr_[j]);
+      // issue in stage order, as the loop does: the wait before a stage's
+      // first use then leaves the later stages' loads in flight
+      __builtin_amdgcn_sched_barrier(0);
     }
     for (int k = wave; k < nch; k += kPrefetch * nwaves) {
 #pragma unroll
       for (int j = 0; j < kPrefetch; ++j) {
-        if (k + j * nwaves < nch) {
-          process(k + j * nwaves, xr[j], vr[j], cr_[j]);
-          load_state(k + (j + kPrefetch) * nwaves, xr[j], vr[j], cr_[j]);
-        }
+        if (k + j * nwaves < nch) process(k + j * nwaves, xr[j], vr[j], cr_[j]);
+        load_state(k + (j + kPrefetch) * nwaves, xr[j], vr[j], cr_[j]);
       }
     }
 
@@ -1070,6 +1037,280 @@ size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_c
                : tracer_lds_bytes<double, 1, false>(mesh_cells, tile_cap);
   return seg ? tracer_lds_bytes<double, 0, true>(mesh_cells, tile_cap)
              : tracer_lds_bytes<double, 0, false>(mesh_cells, tile_cap);
+}
+
+// ---------------------------------------------------------------------------
+// Deposit-only kernel (constant segments, face-crossing form)
+// ---------------------------------------------------------------------------
+// A deposit that does not also move the tracers reads 8 bytes per tracer, so
+// its pace is set by the arithmetic per tracer, not by HBM.  On a sheet with
+// several tracers per cell most segments cross no cell face: all they need is
+// their length (the max-segment diagnostic) and their charge, which the
+// chunk's running sum carries to the next crossing.  So the wavefront does
+// only that per tracer, and appends every segment whose two ends lie in
+// different cells to a per-wavefront ring in LDS; the face geometry of the
+// queued segments (a division each) runs 64 at a time, with every lane busy.
+// The sum over crossings and chunk ends is the same as in the per-chunk form
+// above, term by term.
+
+constexpr int kDepQueue = 128;     // ring entries per wavefront (a flush drains 64)
+constexpr int kDepPrefetch = 8;    // chunks in flight per wavefront
+
+template <bool SEG>
+__host__ __device__ constexpr size_t dep_lds_offset_queue(int mesh_cells, int tile_cap) {
+  // P, D; descriptors; halo words and cells (padded to 8 bytes); 16 doubles
+  // of block reduction
+  return ((size_t)2 * mesh_cells * 8 + (size_t)tile_cap * (sizeof(ChunkDesc) + 8 + 4) + 8 + 16 * 8 + 15) &
+         ~(size_t)15;
+}
+
+template <bool SEG>
+__host__ __device__ constexpr size_t dep_lds_bytes(int mesh_cells, int tile_cap, int nwaves) {
+  // per queue entry: the two state words, packed cells and chunk/lane, and
+  // with per-segment charges the running and own charge
+  return dep_lds_offset_queue<SEG>(mesh_cells, tile_cap) +
+         (size_t)nwaves * kDepQueue * (16 + 8 + (SEG ? 16 : 0));
+}
+
+// Length of the segment between two state words (minimum image), in the same
+// rounding as the per-segment deposit.
+template <int PREC>
+__device__ __forceinline__ double seg_length(uint64_t wa, uint64_t wb, const Geo &g) {
+  // min(|d|, period - |d|) is |d| up to half a period and the other image
+  // beyond, and propagates NaN
+  if constexpr (PREC == kFP64) {
+    const double ad = fabs(__longlong_as_double((long long)wb) - __longlong_as_double((long long)wa));
+    return fmin(ad, g.L - ad);
+  } else {
+    const double nc = (double)g.nc;
+    const double ad = fabs(mesh_pos<PREC>(wb, g.inv_dx) - mesh_pos<PREC>(wa, g.inv_dx));
+    return fmin(ad, nc - ad) * g.dx;
+  }
+}
+
+// ceil(x / dx), the raw cell of a tracer plus one (0 .. nc).  x * inv_dx
+// is within 2^-50 relative of the rounded quotient, and |u| <= nc, so when
+// u's distance to a whole number exceeds tol = (nc + 1) 2^-49 both have the
+// same ceiling; otherwise the division decides.
+template <int PREC>
+__device__ __forceinline__ int point_cell_up(uint64_t w, const Geo &g, double tol, double tol_hi) {
+  if constexpr (PREC == kFP64) {
+    const double x = __longlong_as_double((long long)w);
+    const double u = x * g.inv_dx;
+    const double c = ceil(u);
+    const double r = c - u;
+    if (r > tol && r < tol_hi) return (int)c;
+    return (int)ceil(x / g.dx);
+  } else {
+    return split_frac<PREC>(split_bits(w)) == 0.0 ? split_cell(w) : split_cell(w) + 1;
+  }
+}
+
+template <int PREC, bool SEG>
+__global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nwaves = blockDim.x >> 6;
+  acc_t *sP = reinterpret_cast<acc_t *>(smem);
+  acc_t *sD = sP + a.mesh_cells;
+  ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sD + a.mesh_cells);
+  uint64_t *sHaloW = reinterpret_cast<uint64_t *>(sDesc + a.tile_cap);
+  int32_t *sHaloC = reinterpret_cast<int32_t *>(sHaloW + a.tile_cap);
+  double *sRed = reinterpret_cast<double *>(
+      smem + (((size_t)2 * a.mesh_cells * 8 + (size_t)a.tile_cap * (sizeof(ChunkDesc) + 8 + 4) + 7) & ~(size_t)7));
+  unsigned char *qbase = smem + dep_lds_offset_queue<SEG>(a.mesh_cells, a.tile_cap);
+  ulonglong2 *qW = reinterpret_cast<ulonglong2 *>(qbase) + wave * kDepQueue;
+  int2 *qC = reinterpret_cast<int2 *>(reinterpret_cast<ulonglong2 *>(qbase) + nwaves * kDepQueue) + wave * kDepQueue;
+  ulonglong2 *qS = reinterpret_cast<ulonglong2 *>(reinterpret_cast<int2 *>(reinterpret_cast<ulonglong2 *>(qbase) +
+                                                                          nwaves * kDepQueue) +
+                                                 nwaves * kDepQueue) +
+                   wave * kDepQueue;  // per-segment charges only
+  const int n_items = *a.n_items;
+
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const Item item = a.items[it];
+    if (item.inst < 0) continue;  // freed slot
+    const InstDesc &I = a.inst[item.inst];
+    if (a.respect_active && !I.active) continue;
+    Geo g;
+    g.L = I.L;
+    g.half_L = I.half_L;
+    g.dx = I.dx;
+    g.inv_dx = I.inv_dx;
+    g.dt = I.dt;
+    g.nc = I.n_cells;
+    const int cb = item.chunk_begin;
+    const int nch = item.chunk_end - item.chunk_begin;
+
+    for (int i = tid; i < g.nc; i += blockDim.x) {
+      sP[i] = (acc_t)0;
+      sD[i] = (acc_t)0;
+    }
+    // descriptors, and the word and cell of the tracer after each chunk
+    for (int i = tid; i < nch; i += blockDim.x) {
+      const ChunkDesc d = a.chunks[cb + i];
+      sDesc[i] = d;
+      if (d.partner >= 0) {
+        const uint64_t w = (uint64_t)__double_as_longlong(a.halo_in[d.partner].x);
+        sHaloW[i] = w;
+        sHaloC[i] = point_cell_up<PREC>(w, g, (double)(g.nc + 1) * 0x1p-49, 1.0 - (double)(g.nc + 1) * 0x1p-49);
+      }
+    }
+    __syncthreads();
+
+    double ms = 0.0;
+    bool bad = false;             // a non-finite segment length (reported as NaN)
+    int q_head = 0, q_count = 0;  // the wavefront's ring (uniform)
+
+    // The n <= 64 oldest queued segments, one per lane: the faces each
+    // crosses, and for the last segment of a chunk the chunk's charge where
+    // it ends.
+    auto drain = [&](int n) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < n) {
+        const int e = (q_head + lane) & (kDepQueue - 1);
+        const ulonglong2 w = qW[e];
+        const int2 c = qC[e];
+        const int pa = (c.x & 0xffff) - 1;
+        const int pb = ((c.x >> 16) & 0xffff) - 1;
+        const bool end = (c.y >> 20) & 1;
+        acc_t S, ql;
+        if constexpr (SEG) {
+          const ulonglong2 sq = qS[e];
+          if constexpr (PREC == kFP64) {
+            S = __longlong_as_double((long long)sq.x);
+            ql = __longlong_as_double((long long)sq.y);
+          } else {
+            S = sq.x;
+            ql = sq.y;
+          }
+        } else {
+          const ChunkDesc &d = sDesc[(c.y >> 6) & 0x3fff];
+          ql = PREC == kFP64 ? (acc_t)d.q : (acc_t)d.q_fix;
+          S = ql * (acc_t)(c.y & 63);
+        }
+        acc_t eb = (acc_t)0;  // added to the cell where the segment ends
+        bool add_b = end;
+        if (pa != pb) {
+          double len;
+          const Crossings<acc_t> cr = face_crossings<PREC, acc_t>(w.x, w.y, pa, pb, ql, S, g, &len);
+          if (cr.hi >= cr.lo) {
+            lds_add(sP + wrap_cell(pa, g.nc), cr.cf);
+            if (cr.hi > cr.lo) add_run(sD, cr.lo, cr.hi - 1, cr.w, g.nc);
+            eb = (acc_t)(0 - cr.cl);
+            add_b = true;
+          }
+        }
+        if (end) eb += S + ql;
+        if (add_b) lds_add(sP + wrap_cell(pb, g.nc), eb);
+      }
+      q_head = (q_head + n) & (kDepQueue - 1);
+      q_count -= n;
+    };
+
+    auto load_state = [&](int kk, uint64_t &xw, uint64_t &cw) {
+      const size_t s = kk < nch ? (size_t)(cb + kk) * kChunk + lane : (size_t)cb * kChunk;  // as in k_tracers
+      xw = __builtin_nontemporal_load(a.xs + s);
+      if constexpr (SEG) cw = a.segq[s];
+    };
+    const double tol = (double)(g.nc + 1) * 0x1p-49, tol_hi = 1.0 - tol;
+    auto process = [&](int kk, uint64_t xw, uint64_t cw) {
+      const int n_valid = __builtin_amdgcn_readfirstlane(sDesc[kk].n_valid);
+      const bool open_end = __builtin_amdgcn_readfirstlane(sDesc[kk].partner) < 0;
+      const int last = open_end ? n_valid - 2 : n_valid - 1;  // lane of the chunk's last segment
+      const bool has_seg = lane <= last;
+      // the segment's far end: the next lane, or past the chunk the partner's
+      // first tracer
+      uint64_t xb = (uint64_t)__shfl_down((long long)xw, 1, 64);
+      const int ca = point_cell_up<PREC>(xw, g, tol, tol_hi);
+      int cb1 = __shfl_down(ca, 1, 64);
+      if (!open_end) {
+        const bool tail = lane == n_valid - 1;
+        const uint64_t hw = sHaloW[kk];
+        const int hc = sHaloC[kk];
+        xb = tail ? hw : xb;
+        cb1 = tail ? hc : cb1;
+      }
+      if (has_seg) {
+        const double len = seg_length<PREC>(xw, xb, g);
+        ms = fmax(ms, len);
+        bad = bad || len != len;
+      }
+      // queue the segments whose ends lie in different cells, and the
+      // chunk's last segment
+      const bool rec = has_seg && (ca != cb1 || lane == last);
+      acc_t S = (acc_t)0, ql = (acc_t)0;
+      if constexpr (SEG) {
+        if (has_seg) ql = PREC == kFP64 ? (acc_t)__longlong_as_double((long long)cw) : (acc_t)cw;
+        S = wave_exclusive_sum(ql);
+      }
+      const uint64_t mask = __ballot(rec);
+      if (mask) {
+        if (rec) {
+          const int rank =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+          const int e = (q_head + q_count + rank) & (kDepQueue - 1);
+          qW[e] = make_ulonglong2(xw, xb);
+          qC[e] = make_int2(ca | (cb1 << 16), (kk << 6) | lane | ((lane == last) << 20));
+          if constexpr (SEG) {
+            if constexpr (PREC == kFP64) {
+              qS[e] = make_ulonglong2((uint64_t)__double_as_longlong(S), (uint64_t)__double_as_longlong(ql));
+            } else {
+              qS[e] = make_ulonglong2((uint64_t)S, (uint64_t)ql);
+            }
+          }
+        }
+        q_count += __popcll(mask);
+        if (q_count >= 64) drain(64);
+      }
+    };
+
+    uint64_t xr[kDepPrefetch], cr_[kDepPrefetch];
+#pragma unroll
+    for (int j = 0; j < kDepPrefetch; ++j) {
+      xr[j] = cr_[j] = 0;
+      load_state(wave + j * nwaves, xr[j], cr_[j]);
+      __builtin_amdgcn_sched_barrier(0);  // stage order, as in the loop
+    }
+    for (int k = wave; k < nch; k += kDepPrefetch * nwaves) {
+#pragma unroll
+      for (int j = 0; j < kDepPrefetch; ++j) {
+        if (k + j * nwaves < nch) process(k + j * nwaves, xr[j], cr_[j]);
+        load_state(k + (j + kDepPrefetch) * nwaves, xr[j], cr_[j]);
+      }
+    }
+    if (q_count > 0) drain(q_count);
+
+    if (bad) ms = __longlong_as_double(0x7ff8000000000000ll);
+    ms = wave_max(ms);
+    if (lane == 0) sRed[wave] = ms;
+    __syncthreads();
+    if (tid == 0) {
+      double x = 0.0;
+      for (int w = 0; w < nwaves; ++w) x = nan_max(x, sRed[w]);
+      a.partials[it].maxseg = x;
+    }
+    acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + I.mesh_off;
+    acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + I.mesh_off;
+    for (int i = tid; i < g.nc; i += blockDim.x) {
+      const acc_t p = sP[i];
+      const acc_t d = sD[i];
+      if (p != (acc_t)0) {
+        if constexpr (PREC == kFP64) unsafeAtomicAdd(gP + i, p);
+        else atomicAdd(gP + i, p);
+      }
+      if (d != (acc_t)0) {
+        if constexpr (PREC == kFP64) unsafeAtomicAdd(gD + i, d);
+        else atomicAdd(gD + i, d);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1545,11 +1786,38 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, d
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+constexpr size_t kLdsMax = 160 * 1024;  // per workgroup on gfx950
+
+// The deposit-only launch of constant segments: its own LDS layout (no field,
+// a ring per wavefront), with the workgroup narrowed until it fits.
+template <int PREC, bool SEG>
+static hipError_t deposit_faces(const TracerArgs &a, int grid, int block, hipStream_t st) {
+  static bool limit_set = false;
+  if (!limit_set) {
+    const hipError_t e = hipFuncSetAttribute((const void *)k_deposit_faces<PREC, SEG>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    if (e != hipSuccess) return e;
+    limit_set = true;
+  }
+  size_t lds = dep_lds_bytes<SEG>(a.mesh_cells, a.tile_cap, block / kChunk);
+  while (lds > kLdsMax && block > kChunk) {
+    block /= 2;
+    lds = dep_lds_bytes<SEG>(a.mesh_cells, a.tile_cap, block / kChunk);
+  }
+  if (lds > kLdsMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_deposit_faces<PREC, SEG>), dim3(grid), dim3(block), lds, st, a);
+  return hipGetLastError();
+}
+
 template <int PREC, int ORDER, bool SEG>
 static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
   switch (mode) {
     case kDeposit:
-      hipLaunchKernelGGL((k_tracers<PREC, kDeposit, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
+      if constexpr (ORDER == 0) {
+        return deposit_faces<PREC, SEG>(a, grid, block, st);
+      } else {
+        hipLaunchKernelGGL((k_tracers<PREC, kDeposit, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
+      }
       break;
     case kPush:
       hipLaunchKernelGGL((k_tracers<PREC, kPush, ORDER, SEG>), dim3(grid), dim3(block), lds, st, a);
@@ -1569,13 +1837,16 @@ static hipError_t tracers_prec(int mode, const TracerArgs &a, int grid, int bloc
 template <int PREC, int ORDER, bool SEG>
 static hipError_t set_lds_limit(size_t bytes) {
   const int b = (int)bytes;
-  const void *fns[] = {(const void *)k_tracers<PREC, kDeposit, ORDER, SEG>,
-                       (const void *)k_tracers<PREC, kPush, ORDER, SEG>,
+  const void *fns[] = {(const void *)k_tracers<PREC, kPush, ORDER, SEG>,
                        (const void *)k_tracers<PREC, kPush | kDeposit, ORDER, SEG>,
                        (const void *)k_tracers<PREC, kKickHalf, ORDER, SEG>};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
+  }
+  if constexpr (ORDER != 0) {
+    return hipFuncSetAttribute((const void *)k_tracers<PREC, kDeposit, ORDER, SEG>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
   }
   return hipSuccess;
 }
