@@ -347,13 +347,14 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
 
 // Work-item size in chunks for a slot of n_chunks chunks.  A batch uses one
 // size for every slot; a single simulation sizes its items to give the
-// machine about 2048 of them.
+// machine about 2048 of them, up to the largest item (fewer, larger items
+// spend less on zeroing and merging the item's LDS mesh).
 int slot_tile(const Pool *p, int64_t n_chunks) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
   const int wave_min = p->block / kChunk;
   if (p->batch) return std::max(kDefaultBatchTile, wave_min);
   const int64_t per = (n_chunks + 2047) / 2048;
-  int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(64, per));
+  int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(kMaxTile, per));
   t = (t + 3) / 4 * 4;
   return std::max(t, wave_min);
 }
@@ -368,13 +369,14 @@ void apply_launch_shape(Pool *p) {
     // those workgroups more waves so the CU still has enough loads in flight.
     const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
     const size_t per_cu = lds > 0 ? kLdsPerCU / lds : 8;
-    p->block = p->batch ? kDefaultBatchBlock : kDefaultBlock;
+    // items of 128 chunks or more have work for 8 wavefronts each
+    p->block = (p->batch || p->tile >= 128) ? kDefaultBatchBlock : kDefaultBlock;
     if (per_cu <= 1) p->block = 1024;
     else if (per_cu == 2) p->block = std::max(p->block, 512);
   }
   if (p->tune.grid_blocks > 0) p->grid = p->tune.grid_blocks;
   else if (p->batch) p->grid = kDefaultBatchGrid;
-  else p->grid = std::max(1, std::min<int>(kDefaultGrid, p->n_items_h));
+  else p->grid = std::max(1, std::min<int>(p->tile >= 128 ? kDefaultBatchGrid : kDefaultGrid, p->n_items_h));
 }
 
 // Uploads the device-side item count (the high-water mark of the item arena).
