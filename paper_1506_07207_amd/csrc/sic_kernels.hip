@@ -9,6 +9,10 @@
 //              accumulates the item's charge in a private LDS copy of that
 //              simulation's mesh and merges it into the global mesh with one
 //              atomic per touched cell.
+//   k_deposit_faces  the deposit alone (constant segments): per tracer only
+//              its cell and segment length; the segments that cross a cell
+//              face are queued per wavefront and their face geometry runs 64
+//              at a time.
 //   k_solve    one workgroup per simulation: finishes the deposit (prefix sum
 //              of the covered-run difference array), removes the mean density,
 //              integrates Gauss's law for the face fields, averages them to
