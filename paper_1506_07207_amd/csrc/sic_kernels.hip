@@ -133,8 +133,14 @@ __device__ __forceinline__ uint64_t advance_split(uint64_t w, double du, int nc)
   int carry;
   const uint32_t bits = split_quantise<PREC>(r, carry);
   long long cell = (long long)split_cell(w) + (long long)k + carry;
-  cell %= nc;
-  if (cell < 0) cell += nc;
+  // a move of less than a period needs one conditional wrap; the (slow,
+  // 64-bit) remainder only for longer ones
+  if (cell >= nc) cell -= nc;
+  else if (cell < 0) cell += nc;
+  if ((unsigned long long)cell >= (unsigned long long)nc) {
+    cell %= nc;
+    if (cell < 0) cell += nc;
+  }
   return pack_split((int)cell, bits);
 }
 
