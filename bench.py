@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--plain-instances", type=int, default=256)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-simulation set-ups")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="CPU work of the oracle baseline (core-seconds)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="worker processes for the oracle (0: the host share)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape with the autotuner first")
@@ -148,6 +149,48 @@ def time_plain(B, specs, precision, steps, torch):
     for sim in sims:
         sim.close()
     return n_tr * steps / dt, n_tr, dt
+
+
+def time_single_configs(B, I, torch):
+    """The single-simulation set-ups of the parity tests, each run alone for
+    its full step count, twice: the first run captures the step graphs it
+    needs (HIP graphs of up to 32 steps), the second is timed (events on the
+    launch stream).  Reports the time per step, the resulting
+    tracer-updates/s, and the kernels each step launches (the fused tracer
+    kernel and the solve)."""
+    cases = [
+        ("cold oscillation, FP64 (1 x 1024 tracers, 128 cells)", I.cold_oscillation(), B.SIC_FP64),
+        ("Landau damping, FP64 (256 x 512 tracers, 256 cells)", I.landau(), B.SIC_FP64),
+        ("two-stream, split int cell + f32 offset (512 x 4096 tracers, 1024 cells)", I.two_stream(),
+         B.SIC_SPLIT_F32),
+        ("two-stream, split int cell + u32 fraction (512 x 4096 tracers, 1024 cells)", I.two_stream(),
+         B.SIC_SPLIT_U32),
+        ("large served job, FP64 (2048 x 16384 tracers, 4096 cells, 64 steps)",
+         I.landau(n_sheets=2048, n_tracers=16384, n_cells=4096, n_steps=64), B.SIC_FP64),
+    ]
+    out = []
+    for name, p, prec in cases:
+        x0, v0 = device_inputs(p, torch)
+        sim = B.Simulation(p, precision=prec, history_rows=64, x0=x0, v0=v0)
+        del x0, v0
+        try:
+            sim.step(p.n_steps)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.step(p.n_steps)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+        finally:
+            sim.close()
+        n = p.total_tracers
+        out.append({"workload": name, "tracers": n, "cells": p.n_cells, "steps": p.n_steps, "ms": ms,
+                    "us_per_step": 1e3 * ms / p.n_steps, "tracer_updates_per_s": n * p.n_steps / (ms * 1e-3),
+                    "kernels_per_step": 2})
+        log(f"single: {name}: {1e3 * ms / p.n_steps:.1f} us/step, {n * p.n_steps / (ms * 1e-3):.3e} tracer-updates/s")
+    torch.cuda.empty_cache()
+    return out
 
 
 DEPOSIT_BYTES_PER_TRACER = 8   # the position word, read once
@@ -323,6 +366,8 @@ def main():
     log(f"standalone deposit: {deposit['ms']:.3f} ms for {deposit['tracers']:.3e} tracers "
         f"({deposit['achieved']:.0f} GB/s, {deposit['segments_per_s']:.3e} segments/s)")
 
+    single = None if args.no_single else time_single_configs(B, I, torch)
+
     plain = None
     if not args.no_plain:
         rng = np.random.default_rng(7)
@@ -372,6 +417,7 @@ def main():
                      "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
         "deposit": deposit,
+        "single": single,
         "plain": plain,
         "serving": serve,
         "cpu_baseline": cpu,
