@@ -1066,20 +1066,27 @@ size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_c
 constexpr int kDepQueue = 128;     // ring entries per wavefront (a flush drains 64)
 constexpr int kDepPrefetch = 8;    // chunks in flight per wavefront
 
-template <bool SEG>
+// The word and cell (plus one) of the tracer after a chunk.
+struct alignas(16) DepHalo {
+  uint64_t w;
+  int32_t c;
+  int32_t pad;
+};
+
 __host__ __device__ constexpr size_t dep_lds_offset_queue(int mesh_cells, int tile_cap) {
-  // P, D; descriptors; halo words and cells (padded to 8 bytes); 16 doubles
-  // of block reduction
-  return ((size_t)2 * mesh_cells * 8 + (size_t)tile_cap * (sizeof(ChunkDesc) + 8 + 4) + 8 + 16 * 8 + 15) &
-         ~(size_t)15;
+  // P, D; descriptors; halos; 16 doubles of block reduction
+  return (size_t)2 * mesh_cells * 8 + (size_t)tile_cap * (sizeof(ChunkDesc) + sizeof(DepHalo)) + 16 * 8;
 }
 
+// The ring of one wavefront is three arrays (kept apart so that the lanes of
+// one queue write or read touch consecutive LDS words): the segment's two
+// state words; the cells of its ends (plus one, 16 bits each) and its local
+// chunk and lane; with per-segment charges, the chunk's charge before it and
+// its own.  24 (40) bytes per entry keep three 512-thread workgroups of a
+// 1024-cell mesh on a CU.
 template <bool SEG>
 __host__ __device__ constexpr size_t dep_lds_bytes(int mesh_cells, int tile_cap, int nwaves) {
-  // per queue entry: the two state words, packed cells and chunk/lane, and
-  // with per-segment charges the running and own charge
-  return dep_lds_offset_queue<SEG>(mesh_cells, tile_cap) +
-         (size_t)nwaves * kDepQueue * (16 + 8 + (SEG ? 16 : 0));
+  return dep_lds_offset_queue(mesh_cells, tile_cap) + (size_t)nwaves * kDepQueue * (16 + 8 + (SEG ? 16 : 0));
 }
 
 // Length of the segment between two state words (minimum image), in the same
@@ -1127,17 +1134,12 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
   acc_t *sP = reinterpret_cast<acc_t *>(smem);
   acc_t *sD = sP + a.mesh_cells;
   ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sD + a.mesh_cells);
-  uint64_t *sHaloW = reinterpret_cast<uint64_t *>(sDesc + a.tile_cap);
-  int32_t *sHaloC = reinterpret_cast<int32_t *>(sHaloW + a.tile_cap);
-  double *sRed = reinterpret_cast<double *>(
-      smem + (((size_t)2 * a.mesh_cells * 8 + (size_t)a.tile_cap * (sizeof(ChunkDesc) + 8 + 4) + 7) & ~(size_t)7));
-  unsigned char *qbase = smem + dep_lds_offset_queue<SEG>(a.mesh_cells, a.tile_cap);
-  ulonglong2 *qW = reinterpret_cast<ulonglong2 *>(qbase) + wave * kDepQueue;
-  int2 *qC = reinterpret_cast<int2 *>(reinterpret_cast<ulonglong2 *>(qbase) + nwaves * kDepQueue) + wave * kDepQueue;
-  ulonglong2 *qS = reinterpret_cast<ulonglong2 *>(reinterpret_cast<int2 *>(reinterpret_cast<ulonglong2 *>(qbase) +
-                                                                          nwaves * kDepQueue) +
-                                                 nwaves * kDepQueue) +
-                   wave * kDepQueue;  // per-segment charges only
+  DepHalo *sHalo = reinterpret_cast<DepHalo *>(sDesc + a.tile_cap);
+  double *sRed = reinterpret_cast<double *>(sHalo + a.tile_cap);
+  ulonglong2 *qW = reinterpret_cast<ulonglong2 *>(smem + dep_lds_offset_queue(a.mesh_cells, a.tile_cap));
+  int2 *qC = reinterpret_cast<int2 *>(qW + nwaves * kDepQueue) + wave * kDepQueue;
+  ulonglong2 *qS = reinterpret_cast<ulonglong2 *>(qC + (nwaves - wave) * kDepQueue) + wave * kDepQueue;  // SEG
+  qW += wave * kDepQueue;
   const int n_items = *a.n_items;
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -1161,12 +1163,12 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
     }
     // descriptors, and the word and cell of the tracer after each chunk
     for (int i = tid; i < nch; i += blockDim.x) {
-      const ChunkDesc d = a.chunks[cb + i];
-      sDesc[i] = d;
-      if (d.partner >= 0) {
-        const uint64_t w = (uint64_t)__double_as_longlong(a.halo_in[d.partner].x);
-        sHaloW[i] = w;
-        sHaloC[i] = point_cell_up<PREC>(w, g, (double)(g.nc + 1) * 0x1p-49, 1.0 - (double)(g.nc + 1) * 0x1p-49);
+      sDesc[i] = a.chunks[cb + i];
+      const int pc = a.chunks[cb + i].partner;
+      if (pc >= 0) {
+        const uint64_t w = (uint64_t)__double_as_longlong(a.halo_in[pc].x);
+        sHalo[i].w = w;
+        sHalo[i].c = point_cell_up<PREC>(w, g, (double)(g.nc + 1) * 0x1p-49, 1.0 - (double)(g.nc + 1) * 0x1p-49);
       }
     }
     __syncthreads();
@@ -1188,7 +1190,11 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
         const int2 c = qC[e];
         const int pa = (c.x & 0xffff) - 1;
         const int pb = ((c.x >> 16) & 0xffff) - 1;
-        const bool end = (c.y >> 20) & 1;
+        const ChunkDesc &d = sDesc[(c.y >> 6) & 0x3fff];
+        const int ln = c.y & 63;
+        // the chunk's last segment: its last lane, or the one before for an
+        // open sheet's end
+        const bool end = ln == (d.partner < 0 ? d.n_valid - 2 : d.n_valid - 1);
         acc_t S, ql;
         if constexpr (SEG) {
           const ulonglong2 sq = qS[e];
@@ -1200,9 +1206,8 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
             ql = sq.y;
           }
         } else {
-          const ChunkDesc &d = sDesc[(c.y >> 6) & 0x3fff];
           ql = PREC == kFP64 ? (acc_t)d.q : (acc_t)d.q_fix;
-          S = ql * (acc_t)(c.y & 63);
+          S = ql * (acc_t)ln;
         }
         acc_t eb = (acc_t)0;  // added to the cell where the segment ends
         bool add_b = end;
@@ -1241,10 +1246,9 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
       int cb1 = __shfl_down(ca, 1, 64);
       if (!open_end) {
         const bool tail = lane == n_valid - 1;
-        const uint64_t hw = sHaloW[kk];
-        const int hc = sHaloC[kk];
-        xb = tail ? hw : xb;
-        cb1 = tail ? hc : cb1;
+        const DepHalo h = sHalo[kk];
+        xb = tail ? h.w : xb;
+        cb1 = tail ? h.c : cb1;
       }
       if (has_seg) {
         const double len = seg_length<PREC>(xw, xb, g);
@@ -1259,14 +1263,14 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
         if (has_seg) ql = PREC == kFP64 ? (acc_t)__longlong_as_double((long long)cw) : (acc_t)cw;
         S = wave_exclusive_sum(ql);
       }
-      const uint64_t mask = __ballot(rec);
+      const uint64_t mask = __builtin_amdgcn_ballot_w64(rec);
       if (mask) {
         if (rec) {
           const int rank =
               __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
           const int e = (q_head + q_count + rank) & (kDepQueue - 1);
           qW[e] = make_ulonglong2(xw, xb);
-          qC[e] = make_int2(ca | (cb1 << 16), (kk << 6) | lane | ((lane == last) << 20));
+          qC[e] = make_int2(ca | (cb1 << 16), (kk << 6) | lane);
           if constexpr (SEG) {
             if constexpr (PREC == kFP64) {
               qS[e] = make_ulonglong2((uint64_t)__double_as_longlong(S), (uint64_t)__double_as_longlong(ql));
@@ -1275,7 +1279,7 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
             }
           }
         }
-        q_count += __popcll(mask);
+        q_count += __builtin_popcountll(mask);
         if (q_count >= 64) drain(64);
       }
     };
