@@ -654,7 +654,7 @@ sic_status launch_tracer_mode(Pool *p, int mode, int slot, hipStream_t st) {
 
 sic_status launch_solve_mode(Pool *p, int flags, int slot, hipStream_t st) {
   SolveArgs a = solve_args(p, flags, slot);
-  LAUNCHCHK(p, launch_solve(p->prec, a, slot >= 0 ? 1 : p->slot_cap, st));
+  LAUNCHCHK(p, launch_solve(p->prec, a, slot >= 0 ? 1 : p->slot_cap, p->max_cells, st));
   return SIC_OK;
 }
 
@@ -738,6 +738,24 @@ sic_status run_fused(Pool *p, int64_t n) {
     sic_status s = get_graph(p, k, &ex);
     if (s != SIC_OK) return s;
     HIPCHK(p, hipGraphLaunch(ex, p->stream));
+    if (k & 1) p->parity ^= 1;
+    n -= k;
+  }
+  return SIC_OK;
+}
+
+// A small simulation: all its steps in launches of one resident workgroup
+// (at most kResidentSteps steps each, to keep launches short).
+constexpr int64_t kResidentSteps = 8192;
+
+sic_status run_resident(Pool *p, int64_t n) {
+  const SlotHost &sh = p->slots[0];
+  while (n > 0) {
+    const int64_t k = std::min<int64_t>(n, kResidentSteps);
+    TracerArgs a = tracer_args(p, kPush | kDeposit, 0);
+    a.halo_out = p->halo[p->parity ^ (int)(k & 1)];
+    SolveArgs sa = solve_args(p, kHavePush | kHaveDeposit, 0);
+    LAUNCHCHK(p, launch_resident(p->prec, p->seg, a, sa, sh.chunk_begin, sh.n_chunks, sh.n_cells, k, p->stream));
     if (k & 1) p->parity ^= 1;
     n -= k;
   }
@@ -1489,6 +1507,7 @@ sic_status sim_step(Pool *p, int64_t n) {
     }
     return st;
   }
+  if (p->order == 0 && !p->timing && sh.n_chunks <= resident_max_chunks()) return run_resident(p, n);
   return run_fused(p, n);
 }
 

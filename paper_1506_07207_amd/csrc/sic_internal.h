@@ -32,7 +32,6 @@ namespace sic {
 constexpr int kChunk = 64;          // tracer slots per chunk = wavefront width
 constexpr int kMaxCells = 4096;     // mirrors SIC_MAX_CELLS
 constexpr int kSolveThreads = 256;  // field-solve workgroup
-constexpr int kMaxCellsPerThread = kMaxCells / kSolveThreads;
 
 enum Prec : int { kFP64 = 0, kSplitF32 = 1, kSplitU32 = 2 };
 
@@ -203,7 +202,8 @@ int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a,
                    size_t lds_bytes, void *stream);
 int set_tracer_lds_limit(int prec, int order, bool seg, size_t lds_bytes);
 size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_cap);
-int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream);
+// max_cells: the largest mesh of the slots the launch may solve.
+int launch_solve(int prec, const SolveArgs &a, int n_blocks, int max_cells, void *stream);
 int launch_ingest(int prec, const IngestArgs &a, void *stream);
 int launch_extract(int prec, const ExtractArgs &a, void *stream);
 int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
@@ -213,6 +213,13 @@ int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream);
 // is the slot of the tracer before chunk c's first one (-1: none).
 int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const uint64_t *segq, uint64_t *cedge,
                         int32_t chunk_begin, int32_t n_chunks, void *stream);
+// A small simulation's n_steps fused steps (push, deposit, solve) in one
+// launch of one workgroup; chunks [chunk_begin, chunk_begin + n_chunks) of
+// slot 0, constant segments.  a.halo_out receives the first-tracer halos of
+// the final state.
+int resident_max_chunks();
+int launch_resident(int prec, bool seg, const TracerArgs &a, const SolveArgs &sa, int chunk_begin, int n_chunks,
+                    int n_cells, int64_t n_steps, void *stream);
 int launch_refine_mark(int prec, const RefineArgs &a, void *stream);
 int launch_refine_scatter(int prec, const RefineArgs &a, void *stream);
 

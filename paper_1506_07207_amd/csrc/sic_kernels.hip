@@ -13,6 +13,8 @@
 //              its cell and segment length; the segments that cross a cell
 //              face are queued per wavefront and their face geometry runs 64
 //              at a time.
+//   k_resident a small simulation (up to 32 chunks) stepped many times in one
+//              launch of one workgroup: state in registers, mesh in LDS.
 //   k_solve    one workgroup per simulation: finishes the deposit (prefix sum
 //              of the covered-run difference array), removes the mean density,
 //              integrates Gauss's law for the face fields, averages them to
@@ -1374,58 +1376,68 @@ __device__ __forceinline__ double block_max(double v, double *sWave) {
 
 }  // namespace
 
-template <int PREC>
-__global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
+// The solve of one slot by one workgroup of kSolveThreads threads: charge
+// per cell from the P/D (and R) accumulators, which it clears; mean removal,
+// Gauss's law, cell-centre field, field energy; the diagnostics row and the
+// step count.  ke, mom, ms are the slot's kinetic-energy, momentum and
+// max-segment sums of the step.  The accumulators may be the slot's global
+// mesh (k_solve) or a workgroup's LDS copy (k_resident); with sE the field is
+// also left in LDS.
+// The slot's constants the solve needs, read once by its caller.
+struct SlotConst {
+  int nc;
+  double L, dx, dt, q_unit;
+  int64_t mesh_off, hist_off, hist_cap;
+};
+
+__device__ __forceinline__ SlotConst slot_const(const InstDesc &I) {
+  SlotConst k;
+  k.nc = I.n_cells;
+  k.L = I.L;
+  k.dx = I.dx;
+  k.dt = I.dt;
+  k.q_unit = I.q_unit;
+  k.mesh_off = I.mesh_off;
+  k.hist_off = I.hist_off;
+  k.hist_cap = I.hist_cap;
+  return k;
+}
+
+// step0 and flags0 are the slot's step and sticky flags before this solve;
+// returns the flags after it (the same value in every thread).  With
+// write_field false the field and density are left in sE only (the resident
+// kernel writes them to global memory on its last step).
+template <int PREC, int CELLS, class Acc>
+__device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const SlotConst &kc, int64_t step0,
+                                          int flags0, Acc *gP, Acc *gD, Acc *gRamp, double ke, double mom,
+                                          double ms, double *sE, bool write_field) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
   __shared__ double sWd[4];
   __shared__ long long sWi[4];
   __shared__ double sLastF[kSolveThreads];
-
-  const int slot = a.slot_list ? a.slot_list[blockIdx.x] : (int)blockIdx.x;
   InstDesc *Ip = a.inst + slot;
-  if (!Ip->live) return;
-  if (a.respect_active && !Ip->active) return;
   const int tid = threadIdx.x;
-  const int nc = Ip->n_cells;
-  const double L = Ip->L, dx = Ip->dx, dt = Ip->dt;
-  const double q_unit = Ip->q_unit;
-  const int64_t step0 = Ip->step;
-  const int2 si = a.slot_items[slot];
-  const int item_begin = si.x, item_count = si.y;
-
-  // 1. work-item partials, in item order
-  double ke = 0.0, mom = 0.0, ms = 0.0;
-  for (int i = tid; i < item_count; i += kSolveThreads) {
-    const Partial p = a.partials[item_begin + i];
-    ke += p.ke;
-    mom += p.mom;
-    ms = nan_max(ms, p.maxseg);
-  }
-  if (a.flags & kHavePush) {
-    ke = block_sum(ke, sWd);
-    mom = block_sum(mom, sWd);
-  }
-  if (a.flags & kHaveDeposit) ms = block_max(ms, sWd);
+  const int nc = kc.nc;
+  const double L = kc.L, dx = kc.dx, dt = kc.dt;
+  const double q_unit = kc.q_unit;
 
   // 2. charge per cell: Q_j = P_j + sum_{m <= j} D_m; clear the accumulators
   const int per = (nc + kSolveThreads - 1) / kSolveThreads;
   const int j0 = tid * per;
-  acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + Ip->mesh_off;
-  acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + Ip->mesh_off;
-  double *gE = a.meshE + Ip->mesh_off;
-  double *gR = a.meshRho + Ip->mesh_off;
-  acc_t pv[kMaxCellsPerThread], dv[kMaxCellsPerThread];
+  double *gE = a.meshE + kc.mesh_off;
+  double *gR = a.meshRho + kc.mesh_off;
+  acc_t pv[CELLS], dv[CELLS];
   acc_t dsum = (acc_t)0;
 #pragma unroll
-  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+  for (int k = 0; k < CELLS; ++k) {
     pv[k] = (acc_t)0;
     dv[k] = (acc_t)0;
     const int j = j0 + k;
     if (k < per && j < nc) {
-      pv[k] = gP[j];
-      dv[k] = gD[j];
-      gP[j] = (acc_t)0;
-      gD[j] = (acc_t)0;
+      pv[k] = (acc_t)gP[j];
+      dv[k] = (acc_t)gD[j];
+      gP[j] = (Acc)0;
+      gD[j] = (Acc)0;
     }
     dsum += dv[k];
   }
@@ -1436,25 +1448,24 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   const acc_t dbase = scan(dsum) - dsum;
   // Linear ramps of piecewise-linear segments: the charge adds the second
   // prefix sum of R (zero for piecewise-constant segments).
-  acc_t r2[kMaxCellsPerThread];
+  acc_t r2[CELLS];
 #pragma unroll
-  for (int k = 0; k < kMaxCellsPerThread; ++k) r2[k] = (acc_t)0;
-  if (a.order == 1 && a.meshR != nullptr) {  // only piecewise-linear segments have ramps
-    acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + Ip->mesh_off;
+  for (int k = 0; k < CELLS; ++k) r2[k] = (acc_t)0;
+  if (gRamp != nullptr) {  // only piecewise-linear segments have ramps
     acc_t rsum = (acc_t)0;
 #pragma unroll
-    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    for (int k = 0; k < CELLS; ++k) {
       const int j = j0 + k;
       if (k < per && j < nc) {
-        r2[k] = gR[j];
-        gR[j] = (acc_t)0;
+        r2[k] = (acc_t)gRamp[j];
+        gRamp[j] = (Acc)0;
       }
       rsum += r2[k];
     }
     const acc_t base1 = scan(rsum) - rsum;
     acc_t run1 = base1, s1sum = (acc_t)0;
 #pragma unroll
-    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    for (int k = 0; k < CELLS; ++k) {
       run1 += r2[k];
       r2[k] = run1;
       if ((k < per) && (j0 + k < nc)) s1sum += run1;
@@ -1462,17 +1473,17 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
     const acc_t base2 = scan(s1sum) - s1sum;
     acc_t run2 = base2;
 #pragma unroll
-    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    for (int k = 0; k < CELLS; ++k) {
       if ((k < per) && (j0 + k < nc)) run2 += r2[k];
       r2[k] = run2;
     }
   }
-  double Q[kMaxCellsPerThread];
+  double Q[CELLS];
   acc_t qsum_acc = (acc_t)0;
   {
     acc_t run = dbase;
 #pragma unroll
-    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    for (int k = 0; k < CELLS; ++k) {
       run += dv[k];
       const acc_t qa = pv[k] + run + r2[k];
       const bool in = (k < per) && (j0 + k < nc);
@@ -1488,10 +1499,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   // 3. Gauss's law on faces: F_{j+1/2} = F_{j-1/2} + (Q_j - Qtot/nc),
   //    F shifted to zero mean; E_j = (F_{j-1/2} + F_{j+1/2}) / 2.
   const double qmean = Qtot / (double)nc;
-  double F[kMaxCellsPerThread];
+  double F[CELLS];
   double rsum = 0.0;
 #pragma unroll
-  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+  for (int k = 0; k < CELLS; ++k) {
     const bool in = (k < per) && (j0 + k < nc);
     const double r = in ? (Q[k] - qmean) : 0.0;
     rsum += r;
@@ -1502,7 +1513,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   {
     double run = fbase;
 #pragma unroll
-    for (int k = 0; k < kMaxCellsPerThread; ++k) {
+    for (int k = 0; k < CELLS; ++k) {
       const bool in = (k < per) && (j0 + k < nc);
       run += F[k];
       F[k] = in ? run : 0.0;
@@ -1512,7 +1523,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   const double fmean = block_sum(fsum, sWd) / (double)nc;
   double lastF = 0.0;
 #pragma unroll
-  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+  for (int k = 0; k < CELLS; ++k) {
     if ((k < per) && (j0 + k < nc)) {
       F[k] -= fmean;
       lastF = F[k];
@@ -1524,13 +1535,16 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   double w2 = 0.0;
   bool finite = true;
 #pragma unroll
-  for (int k = 0; k < kMaxCellsPerThread; ++k) {
+  for (int k = 0; k < CELLS; ++k) {
     const int j = j0 + k;
     if ((k < per) && (j < nc)) {
       const double e = 0.5 * (prevF + F[k]);
       prevF = F[k];
-      gE[j] = e;
-      gR[j] = (Q[k] - qmean) / dx;
+      if (sE) sE[j] = e;
+      if (write_field) {
+        gE[j] = e;
+        gR[j] = (Q[k] - qmean) / dx;
+      }
       w2 += e * e;
       finite = finite && (e - e == 0.0);
     }
@@ -1539,19 +1553,19 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   const int bad = block_sum(finite ? 0 : 1, reinterpret_cast<int *>(sWi));
 
   // 4. diagnostics and step bookkeeping
+  const bool pushed = (a.flags & kHavePush) != 0;
+  const int64_t step = pushed ? step0 + 1 : step0;
+  int f = 0;
+  if (bad || !(W - W == 0.0)) f |= 1;
+  if (a.flags & kHaveDeposit) {
+    if (ms != ms) f |= 1;
+    else if (ms > 0.45 * L) f |= 2;
+  }
+  const int flags = flags0 | f;
   if (tid == 0) {
-    const bool pushed = (a.flags & kHavePush) != 0;
-    const int64_t step = pushed ? step0 + 1 : step0;
-    int f = 0;
-    if (bad || !(W - W == 0.0)) f |= 1;
-    if (a.flags & kHaveDeposit) {
-      if (ms != ms) f |= 1;
-      else if (ms > 0.45 * L) f |= 2;
-    }
-    const int flags = Ip->flags | f;
     Ip->flags = flags;
-    const int64_t cap = Ip->hist_cap;
-    DiagRow *H = a.hist + Ip->hist_off;
+    const int64_t cap = kc.hist_cap;
+    DiagRow *H = a.hist + kc.hist_off;
     DiagRow r;
     r.step = step;
     r.t = (double)step * dt;
@@ -1575,6 +1589,233 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
         Ip->active = 0;
         a.done[slot] = 1;
       }
+    }
+  }
+  return flags;
+}
+
+// CELLS: cells per thread the solve is unrolled for (at least the pool's
+// largest mesh over kSolveThreads; the unused ones add exact zeros, so every
+// instance gives the same bits).
+template <int PREC, int CELLS>
+__global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+  __shared__ double sWd[4];
+  const int slot = a.slot_list ? a.slot_list[blockIdx.x] : (int)blockIdx.x;
+  InstDesc *Ip = a.inst + slot;
+  if (!Ip->live) return;
+  if (a.respect_active && !Ip->active) return;
+  const int tid = threadIdx.x;
+  const int2 si = a.slot_items[slot];
+  const int item_begin = si.x, item_count = si.y;
+
+  // 1. work-item partials, in item order
+  double ke = 0.0, mom = 0.0, ms = 0.0;
+  for (int i = tid; i < item_count; i += kSolveThreads) {
+    const Partial p = a.partials[item_begin + i];
+    ke += p.ke;
+    mom += p.mom;
+    ms = nan_max(ms, p.maxseg);
+  }
+  if (a.flags & kHavePush) {
+    ke = block_sum(ke, sWd);
+    mom = block_sum(mom, sWd);
+  }
+  if (a.flags & kHaveDeposit) ms = block_max(ms, sWd);
+  acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + Ip->mesh_off;
+  acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + Ip->mesh_off;
+  acc_t *gRamp = (a.order == 1 && a.meshR) ? reinterpret_cast<acc_t *>(a.meshR) + Ip->mesh_off : nullptr;
+  solve_slot<PREC, CELLS>(a, slot, slot_const(*Ip), Ip->step, Ip->flags, gP, gD, gRamp, ke, mom, ms,
+                          (double *)nullptr, true);
+}
+
+// ---------------------------------------------------------------------------
+// Resident small simulation
+// ---------------------------------------------------------------------------
+// A simulation of at most kResidentChunks chunks runs many steps in one
+// launch of one workgroup: its tracers stay in registers (each wavefront
+// owns chunks w, w + 4, ...), the mesh accumulators and the field in LDS, and
+// each step is push, deposit and solve separated by workgroup barriers.  The
+// arithmetic is that of the fused step (same move, same segment deposit,
+// same solve code), so only the order of the floating-point sums of the
+// deposit and of the kinetic-energy and momentum diagnostics can differ; the
+// split forms give the same bits.  Small simulations are latency-bound: this
+// replaces two kernel launches per step with one launch per call.
+
+constexpr int kResidentWaves = kSolveThreads / kChunk;   // 4
+constexpr int kResidentPerWave = 8;
+constexpr int kResidentChunks = kResidentWaves * kResidentPerWave;  // 32 chunks, 2048 slots
+
+// P, D, E; then (16-byte aligned) descriptors, new first-tracer words and
+// charge edges
+__host__ __device__ constexpr size_t resident_desc_offset(int n_cells) {
+  return ((size_t)n_cells * 24 + 15) & ~(size_t)15;
+}
+__host__ __device__ constexpr size_t resident_lds_bytes(int n_cells, bool seg) {
+  return resident_desc_offset(n_cells) + (size_t)kResidentChunks * (sizeof(ChunkDesc) + 8 + (seg ? 16 : 0));
+}
+
+// A workgroup barrier that orders LDS only: global stores in flight (the
+// diagnostics rows) are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int PREC, bool SEG, int CELLS>
+__global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveArgs sa, int chunk_begin,
+                                                            int n_chunks, int64_t n_steps) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sRed[3 * kResidentWaves];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int slot = 0;
+  const InstDesc *Ip = a.inst + slot;
+  const int nc = Ip->n_cells;
+  acc_t *sP = reinterpret_cast<acc_t *>(smem);
+  acc_t *sD = sP + nc;
+  double *sE = reinterpret_cast<double *>(sD + nc);
+  ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(smem + resident_desc_offset(nc));
+  uint64_t *sHx = reinterpret_cast<uint64_t *>(sDesc + kResidentChunks);
+  uint64_t *sEdge = sHx + kResidentChunks;  // per-segment charges
+  Geo g;
+  g.L = Ip->L;
+  g.half_L = Ip->half_L;
+  g.dx = Ip->dx;
+  g.inv_dx = Ip->inv_dx;
+  g.dt = Ip->dt;
+  g.nc = nc;
+  const double q_unit = Ip->q_unit;
+  const SlotConst kc = slot_const(*Ip);
+  int64_t step_now = Ip->step;
+  int flags = Ip->flags;
+
+  for (int i = tid; i < nc; i += kSolveThreads) {
+    sP[i] = (acc_t)0;
+    sD[i] = (acc_t)0;
+    sE[i] = a.meshE[Ip->mesh_off + i];
+  }
+  for (int i = tid; i < n_chunks; i += kSolveThreads) {
+    sDesc[i] = a.chunks[chunk_begin + i];
+    if constexpr (SEG) {
+      sEdge[2 * i] = a.cedge[2 * (size_t)(chunk_begin + i)];
+      sEdge[2 * i + 1] = a.cedge[2 * (size_t)(chunk_begin + i) + 1];
+    }
+  }
+  // the wavefront's chunks, in registers for the whole launch
+  uint64_t xr[kResidentPerWave], cwr[kResidentPerWave];
+  double vr[kResidentPerWave];
+#pragma unroll
+  for (int j = 0; j < kResidentPerWave; ++j) {
+    const int c = wave + j * kResidentWaves;
+    xr[j] = cwr[j] = 0;
+    vr[j] = 0.0;
+    if (c < n_chunks) {
+      const size_t sidx = (size_t)(chunk_begin + c) * kChunk + lane;
+      xr[j] = a.xs[sidx];
+      vr[j] = a.vs[sidx];
+      if constexpr (SEG) cwr[j] = a.segq[sidx];
+    }
+  }
+  __syncthreads();
+
+  for (int64_t step = 0; step < n_steps; ++step) {
+    // push: gather, kick, drift; the first tracer of each chunk is
+    // published for the segment that ends at it
+    double ke = 0.0, mom = 0.0, ms = 0.0;
+#pragma unroll
+    for (int j = 0; j < kResidentPerWave; ++j) {
+      const int c = wave + j * kResidentWaves;
+      if (c < n_chunks) {
+        const ChunkDesc &ch = sDesc[c];
+        const int n_valid = __builtin_amdgcn_readfirstlane(ch.n_valid);
+        const bool valid = lane < n_valid;
+        uint64_t xw = xr[j];
+        double v = vr[j];
+        const double e = gather_field(sE, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
+        const double vn = v + g.dt * e;
+        double m;
+        if constexpr (SEG) {
+          const uint64_t up = (uint64_t)__shfl_up((long long)cwr[j], 1, 64);
+          m = tracer_mass<PREC>(lane == 0 ? sEdge[2 * c] : up, cwr[j], q_unit);
+        } else {
+          const bool end =
+              (lane == 0 && (ch.flags & kChunkOpenStart)) || (lane == n_valid - 1 && ch.partner < 0);
+          m = end ? 0.5 * ch.q : ch.q;
+        }
+        const double qv = valid ? m : 0.0;
+        ke += 0.5 * qv * v * vn;
+        mom += qv * (0.5 * (v + vn));
+        const uint64_t xn = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
+        xr[j] = valid ? xn : xw;
+        vr[j] = valid ? vn : v;
+        if (lane == 0) sHx[c] = xr[j];
+      }
+    }
+    lds_barrier();
+    // deposit of the moved segments into the LDS mesh
+#pragma unroll
+    for (int j = 0; j < kResidentPerWave; ++j) {
+      const int c = wave + j * kResidentWaves;
+      if (c < n_chunks) {
+        const ChunkDesc &ch = sDesc[c];
+        const int n_valid = __builtin_amdgcn_readfirstlane(ch.n_valid);
+        const uint64_t xw = xr[j];
+        uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
+        bool has_seg = lane < n_valid;
+        if (lane == n_valid - 1) {
+          if (ch.partner < 0) has_seg = false;  // open sheet: the last tracer ends the chain
+          else pw = sHx[ch.partner - chunk_begin];
+        }
+        if (has_seg) {
+          double len;
+          if constexpr (PREC == kFP64) {
+            const double q0 = SEG ? __longlong_as_double((long long)cwr[j]) : ch.q;
+            len = deposit_fp64(__longlong_as_double((long long)xw), __longlong_as_double((long long)pw), q0, g,
+                               sP, sD);
+          } else {
+            const long long q0 = SEG ? (long long)cwr[j] : ch.q_fix;
+            len = deposit_split<PREC>(xw, pw, q0, g, sP, sD);
+          }
+          ms = nan_max(ms, len);
+        }
+      }
+    }
+    ke = wave_sum(ke);
+    mom = wave_sum(mom);
+    ms = wave_max(ms);
+    if (lane == 0) {
+      sRed[wave] = ke;
+      sRed[kResidentWaves + wave] = mom;
+      sRed[2 * kResidentWaves + wave] = ms;
+    }
+    lds_barrier();
+    ke = mom = ms = 0.0;
+    for (int w = 0; w < kResidentWaves; ++w) {
+      ke += sRed[w];
+      mom += sRed[kResidentWaves + w];
+      ms = nan_max(ms, sRed[2 * kResidentWaves + w]);
+    }
+    // solve (clears the accumulators, leaves the field in sE; in global
+    // memory too after the last step)
+    flags = solve_slot<PREC, CELLS>(sa, slot, kc, step_now, flags, sP, sD, (acc_t *)nullptr, ke, mom, ms, sE,
+                                    step == n_steps - 1);
+    step_now += 1;
+    lds_barrier();
+  }
+
+  // state and first-tracer halos back to global memory
+#pragma unroll
+  for (int j = 0; j < kResidentPerWave; ++j) {
+    const int c = wave + j * kResidentWaves;
+    if (c < n_chunks) {
+      const size_t sidx = (size_t)(chunk_begin + c) * kChunk + lane;
+      a.xs[sidx] = xr[j];
+      a.vs[sidx] = vr[j];
+      if (lane == 0) a.halo_out[chunk_begin + c] = make_double2(__longlong_as_double((long long)xr[j]), vr[j]);
     }
   }
 }
@@ -1909,16 +2150,86 @@ int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a,
   return (int)dispatch<LaunchTracers>(prec, order, seg, mode, a, grid, block, lds, (hipStream_t)stream);
 }
 
-int launch_solve(int prec, const SolveArgs &a, int n_blocks, void *stream) {
+template <int PREC, bool SEG, int CELLS>
+static hipError_t resident_launch(const TracerArgs &a, const SolveArgs &sa, int chunk_begin, int n_chunks,
+                                  int64_t n_steps, size_t lds, hipStream_t st) {
+  static bool limit_set = false;
+  if (!limit_set) {
+    const hipError_t e = hipFuncSetAttribute((const void *)k_resident<PREC, SEG, CELLS>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)resident_lds_bytes(kMaxCells, true));
+    if (e != hipSuccess) return e;
+    limit_set = true;
+  }
+  hipLaunchKernelGGL((k_resident<PREC, SEG, CELLS>), dim3(1), dim3(kSolveThreads), lds, st, a, sa, chunk_begin,
+                     n_chunks, n_steps);
+  return hipGetLastError();
+}
+
+// Cells per solve thread the kernels are built for: 1, 4 or 16.
+static int solve_cells(int max_cells) {
+  const int per = (max_cells + kSolveThreads - 1) / kSolveThreads;
+  return per <= 1 ? 1 : (per <= 4 ? 4 : 16);
+}
+
+template <int PREC, bool SEG>
+static hipError_t resident_prec(const TracerArgs &a, const SolveArgs &sa, int chunk_begin, int n_chunks,
+                                int n_cells, int64_t n_steps, size_t lds, hipStream_t st) {
+  switch (solve_cells(n_cells)) {
+    case 1: return resident_launch<PREC, SEG, 1>(a, sa, chunk_begin, n_chunks, n_steps, lds, st);
+    case 4: return resident_launch<PREC, SEG, 4>(a, sa, chunk_begin, n_chunks, n_steps, lds, st);
+    default: return resident_launch<PREC, SEG, 16>(a, sa, chunk_begin, n_chunks, n_steps, lds, st);
+  }
+}
+
+int resident_max_chunks() { return kResidentChunks; }
+
+int launch_resident(int prec, bool seg, const TracerArgs &a, const SolveArgs &sa, int chunk_begin, int n_chunks,
+                    int n_cells, int64_t n_steps, void *stream) {
+  if (n_steps <= 0) return 0;
+  if (n_chunks < 1 || n_chunks > kResidentChunks || n_cells < 1 || n_cells > kMaxCells)
+    return (int)hipErrorInvalidValue;
+  const size_t lds = resident_lds_bytes(n_cells, seg);
+  hipStream_t st = (hipStream_t)stream;
+  switch (prec) {
+    case kFP64:
+      return (int)(seg ? resident_prec<kFP64, true>(a, sa, chunk_begin, n_chunks, n_cells, n_steps, lds, st)
+                       : resident_prec<kFP64, false>(a, sa, chunk_begin, n_chunks, n_cells, n_steps, lds, st));
+    case kSplitF32:
+      return (int)(seg ? resident_prec<kSplitF32, true>(a, sa, chunk_begin, n_chunks, n_cells, n_steps, lds, st)
+                       : resident_prec<kSplitF32, false>(a, sa, chunk_begin, n_chunks, n_cells, n_steps, lds, st));
+    case kSplitU32:
+      return (int)(seg ? resident_prec<kSplitU32, true>(a, sa, chunk_begin, n_chunks, n_cells, n_steps, lds, st)
+                       : resident_prec<kSplitU32, false>(a, sa, chunk_begin, n_chunks, n_cells, n_steps, lds, st));
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+}
+
+template <int CELLS>
+static hipError_t solve_cells_launch(int prec, const SolveArgs &a, int n_blocks, hipStream_t st) {
+  switch (prec) {
+    case kFP64: hipLaunchKernelGGL((k_solve<kFP64, CELLS>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
+    case kSplitF32:
+      hipLaunchKernelGGL((k_solve<kSplitF32, CELLS>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
+      break;
+    case kSplitU32:
+      hipLaunchKernelGGL((k_solve<kSplitU32, CELLS>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int launch_solve(int prec, const SolveArgs &a, int n_blocks, int max_cells, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n_blocks <= 0) return 0;
-  switch (prec) {
-    case kFP64: hipLaunchKernelGGL(k_solve<kFP64>, dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
-    case kSplitF32: hipLaunchKernelGGL(k_solve<kSplitF32>, dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
-    case kSplitU32: hipLaunchKernelGGL(k_solve<kSplitU32>, dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
-    default: return (int)hipErrorInvalidValue;
+  if (max_cells < 1 || max_cells > kMaxCells) return (int)hipErrorInvalidValue;
+  switch (solve_cells(max_cells)) {
+    case 1: return (int)solve_cells_launch<1>(prec, a, n_blocks, st);
+    case 4: return (int)solve_cells_launch<4>(prec, a, n_blocks, st);
+    default: return (int)solve_cells_launch<16>(prec, a, n_blocks, st);
   }
-  return (int)hipGetLastError();
 }
 
 int launch_ingest(int prec, const IngestArgs &a, void *stream) {
