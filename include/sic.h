@@ -164,7 +164,9 @@ sic_status sic_push(sic_sim *sim);
 /* n_steps full steps.  Each step moves the tracers with the current field,
  * deposits the new positions and solves the new field, so on return the field
  * is current for the new step.  If the field is stale it is brought up to date
- * first.  Steps run as captured HIP graphs.  Async; with refinement on
+ * first.  Steps run as captured HIP graphs; a small simulation (constant
+ * segments, at most 32 chunks of 64 tracer slots) runs them in one launch of
+ * a single workgroup instead (same arithmetic).  Async; with refinement on
  * (l_max > 0) each step also runs sic_refine, which synchronises. */
 sic_status sic_step(sic_sim *sim, int64_t n_steps);
 
