@@ -214,8 +214,6 @@ hipError_t dalloc(T **p, size_t n) {
   return hipMalloc((void **)p, n * sizeof(T));
 }
 
-size_t acc_size(int prec) { return prec == kFP64 ? sizeof(double) : sizeof(long long); }
-
 void destroy_graphs(Pool *p) {
   for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
   p->graphs.clear();
@@ -225,7 +223,7 @@ void destroy_graphs(Pool *p) {
 
 void pool_free(Pool *p) {
   if (!p) return;
-  if (p->stream || true) hipStreamSynchronize(p->stream);
+  hipStreamSynchronize(p->stream);  // teardown: nothing to report an error to
   destroy_graphs(p);
   for (auto &s : p->slots)
     if (s.d_in_off) hipFree(s.d_in_off);
@@ -707,21 +705,25 @@ sic_status run_fused(Pool *p, int64_t n) {
     std::vector<hipEvent_t> ev(3 * (size_t)n);
     for (auto &e : ev) HIPCHK(p, hipEventCreate(&e));
     sic_status s = SIC_OK;
-    for (int64_t i = 0; i < n && s == SIC_OK; ++i) {
-      hipEventRecord(ev[3 * i], p->stream);
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; i < n && s == SIC_OK && e == hipSuccess; ++i) {
+      e = hipEventRecord(ev[3 * i], p->stream);
+      if (e != hipSuccess) break;
       s = launch_tracer_mode(p, kPush | kDeposit, -1, p->stream);
       if (s != SIC_OK) break;
-      hipEventRecord(ev[3 * i + 1], p->stream);
+      e = hipEventRecord(ev[3 * i + 1], p->stream);
+      if (e != hipSuccess) break;
       s = launch_solve_mode(p, kHavePush | kHaveDeposit | (p->batch ? kBatchStep : 0), -1, p->stream);
-      hipEventRecord(ev[3 * i + 2], p->stream);
+      if (s == SIC_OK) e = hipEventRecord(ev[3 * i + 2], p->stream);
       p->parity ^= 1;
     }
-    hipError_t e = hipStreamSynchronize(p->stream);
+    const hipError_t es = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) e = es;
     double tt = 0.0, ts = 0.0;
-    for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+    for (int64_t i = 0; i < n && e == hipSuccess && s == SIC_OK; ++i) {
       float a = 0.f, b = 0.f;
-      hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
-      hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+      e = hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
       tt += a;
       ts += b;
     }
