@@ -1044,7 +1044,6 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
 
 size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_cap) {
   // the accumulators are 8 bytes in every precision
-  (void)prec;
   if (order == 1)
     return seg ? tracer_lds_bytes<double, 1, true>(mesh_cells, tile_cap)
                : tracer_lds_bytes<double, 1, false>(mesh_cells, tile_cap);
