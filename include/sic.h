@@ -228,7 +228,10 @@ int32_t sic_abi_version(void);
  *   tile_chunks:   64-tracer chunks per workgroup work item (one LDS mesh
  *                  accumulation and flush per item); 0 = automatic;
  *   block_threads: 64, 128, 256, 512 or 1024; 0 = automatic;
- *   grid_blocks:   workgroups of the persistent tracer kernel; 0 = automatic. */
+ *   grid_blocks:   workgroups of the tracer kernels, which loop over the
+ *                  work items (any count is valid); 0 = automatic: one work
+ *                  item per workgroup (batches: the item count rounded up to
+ *                  a power of two, at least 4096). */
 typedef struct sic_tuning {
     int32_t tile_chunks;
     int32_t block_threads;
@@ -319,7 +322,7 @@ sic_status sic_batch_set_timing(sic_batch *b, int32_t timing);
 sic_status sic_batch_last_timing(const sic_batch *b, double *tracer_ms, double *solve_ms);
 
 /* Autotuner.  Times every candidate launch shape (chunks per work item,
- * threads per workgroup, persistent grid size) for steps_per_trial steps on
+ * threads per workgroup, grid size) for steps_per_trial steps on
  * the handle's own resident simulations, with HIP events around each kernel,
  * then restores the simulations to their state before the call (the trial
  * steps leave no trace; the device briefly holds a second copy of the state)

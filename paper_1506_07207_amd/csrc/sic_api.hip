@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -31,8 +32,9 @@ using namespace sic;
 namespace {
 
 constexpr int kGraphSteps = 32;         // steps per captured graph
-constexpr int kDefaultGrid = 2048;       // persistent tracer workgroups, single simulations (8 per CU)
-constexpr int kDefaultBatchGrid = 4096;  // batches
+constexpr int kDefaultGrid = 2048;       // grid of a pool before its first items are placed
+constexpr int kMinBatchGrid = 4096;      // smallest default batch grid (16 workgroups per CU)
+constexpr int kMaxGrid = 1 << 20;        // largest default grid (the kernels loop over any excess items)
 constexpr int kDefaultBlock = 256;       // single simulations
 constexpr int kDefaultBatchBlock = 512;  // batches
 constexpr int kDefaultBatchTile = 256;   // chunks per batch work item (16k tracers per LDS mesh merge)
@@ -165,7 +167,7 @@ struct Pool {
   int parity = 0;
   sic_tuning tune{};  // requested (0 = automatic)
   int block = kDefaultBlock, grid = kDefaultGrid, tile = kMinTile;
-  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;  // (steps, parity, grid)
   std::vector<hipGraph_t> graph_objs;
   bool timing = false;
   double t_tracer = 0.0, t_solve = 0.0;
@@ -372,9 +374,21 @@ void apply_launch_shape(Pool *p) {
     if (per_cu <= 1) p->block = 1024;
     else if (per_cu == 2) p->block = std::max(p->block, 512);
   }
-  if (p->tune.grid_blocks > 0) p->grid = p->tune.grid_blocks;
-  else if (p->batch) p->grid = kDefaultBatchGrid;
-  else p->grid = std::max(1, std::min<int>(p->tile >= 128 ? kDefaultBatchGrid : kDefaultGrid, p->n_items_h));
+  if (p->tune.grid_blocks > 0) {
+    p->grid = p->tune.grid_blocks;
+  } else if (p->batch) {
+    // One work item per workgroup: the dispatcher starts a new workgroup as
+    // soon as one retires, so one workgroup's mesh clear and merge overlap
+    // the streaming of the others, which a persistent grid serialises.  The
+    // count is rounded up to a power of two so that a batch whose item
+    // arena grows slot by slot captures new graphs only now and then (the
+    // surplus workgroups read the item count and exit).
+    int g = kMinBatchGrid;
+    while (g < p->n_items_h && g < kMaxGrid) g *= 2;
+    p->grid = g;
+  } else {
+    p->grid = std::max(1, std::min<int>(p->n_items_h, kMaxGrid));
+  }
 }
 
 // Uploads the device-side item count (the high-water mark of the item arena).
@@ -544,7 +558,7 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
   p->timing = true;
   const int tiles[] = {32, 64, 128, 256};
   const int blocks[] = {256, 512, 1024};
-  const int grids[] = {1024, 2048, 4096};
+  const int grids[] = {0, 1024, 2048, 4096};  // 0: one work item per workgroup
   sic_tuning best = saved;
   double best_ms = 1e300;
   for (int t : tiles) {
@@ -669,7 +683,7 @@ sic_status enqueue_fused(Pool *p, hipStream_t st) {
 }
 
 sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
-  auto key = std::make_pair(k, p->parity);
+  auto key = std::make_tuple(k, p->parity, p->grid);
   auto it = p->graphs.find(key);
   if (it != p->graphs.end()) {
     *out = it->second;
