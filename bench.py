@@ -205,17 +205,19 @@ DEPOSIT_BYTES_PER_TRACER = 8   # the position word, read once
 DEPOSIT_BYTES_PER_CELL = 16    # P and D accumulators written
 
 
-def time_deposit(B, I, precision, torch, sheets=8192, tracers=16384, cells=1024, reps=10):
+def time_deposit(B, I, precision, torch, sheets=8192, tracers=16384, cells=1024, reps=50, warmup=20):
     """The standalone deposit (sic_deposit) of one large simulation: 8192
     Landau sheets x 16384 tracers (134M tracers, 1.07 GB of positions, far
     beyond the caches) on 1024 cells, timed with events on the stream the
-    kernel runs on (the current torch stream)."""
+    kernel runs on (the current torch stream).  The deposit is paced by
+    instruction issue, so the first few launches after an idle spell run at
+    a lower clock; ``warmup`` untimed launches (about 6 ms) come first."""
     p = I.landau(n_sheets=sheets, n_tracers=tracers, n_cells=cells, n_steps=1)
     x0, v0 = device_inputs(p, torch)
     sim = B.Simulation(p, precision=precision, history_rows=8, x0=x0, v0=v0)
     del x0, v0
     try:
-        for _ in range(2):
+        for _ in range(warmup):
             sim.deposit()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()

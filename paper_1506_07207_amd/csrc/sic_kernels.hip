@@ -1065,8 +1065,8 @@ size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_c
 // The sum over crossings and chunk ends is the same as in the per-chunk form
 // above, term by term.
 
-constexpr int kDepQueue = 128;     // ring entries per wavefront (a flush drains 64)
-constexpr int kDepPrefetch = 8;    // chunks in flight per wavefront
+constexpr int kDepQueue = 64;      // ring entries per wavefront (drained before it would overflow)
+constexpr int kDepPrefetch = 6;    // chunks in flight per wavefront
 
 // The word and cell (plus one) of the tracer after a chunk.
 struct alignas(16) DepHalo {
@@ -1076,16 +1076,17 @@ struct alignas(16) DepHalo {
 };
 
 __host__ __device__ constexpr size_t dep_lds_offset_queue(int mesh_cells, int tile_cap) {
-  // P, D; descriptors; halos; 16 doubles of block reduction
-  return (size_t)2 * mesh_cells * 8 + (size_t)tile_cap * (sizeof(ChunkDesc) + sizeof(DepHalo)) + 16 * 8;
+  // P, D; descriptors; halos
+  return (size_t)2 * mesh_cells * 8 + (size_t)tile_cap * (sizeof(ChunkDesc) + sizeof(DepHalo));
 }
 
 // The ring of one wavefront is three arrays (kept apart so that the lanes of
 // one queue write or read touch consecutive LDS words): the segment's two
 // state words; the cells of its ends (plus one, 16 bits each) and its local
 // chunk and lane; with per-segment charges, the chunk's charge before it and
-// its own.  24 (40) bytes per entry keep three 512-thread workgroups of a
-// 1024-cell mesh on a CU.
+// its own.  24 (40) bytes per entry: a 512-thread workgroup of a 1024-cell
+// mesh and 256 chunks per item takes 40 KB, four workgroups per CU.  At the
+// end of an item each wavefront's ring holds its segment-length maximum.
 template <bool SEG>
 __host__ __device__ constexpr size_t dep_lds_bytes(int mesh_cells, int tile_cap, int nwaves) {
   return dep_lds_offset_queue(mesh_cells, tile_cap) + (size_t)nwaves * kDepQueue * (16 + 8 + (SEG ? 16 : 0));
@@ -1125,8 +1126,11 @@ __device__ __forceinline__ int point_cell_up(uint64_t w, const Geo &g, double to
   }
 }
 
+// Without per-segment charges the kernel is held to 64 VGPRs, so that the
+// eight wavefronts of each of four workgroups per CU all fit.
 template <int PREC, bool SEG>
-__global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SEG ? 4 : 8)))
+k_deposit_faces(TracerArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
@@ -1137,8 +1141,8 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
   acc_t *sD = sP + a.mesh_cells;
   ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sD + a.mesh_cells);
   DepHalo *sHalo = reinterpret_cast<DepHalo *>(sDesc + a.tile_cap);
-  double *sRed = reinterpret_cast<double *>(sHalo + a.tile_cap);
-  ulonglong2 *qW = reinterpret_cast<ulonglong2 *>(smem + dep_lds_offset_queue(a.mesh_cells, a.tile_cap));
+  ulonglong2 *const qBase = reinterpret_cast<ulonglong2 *>(smem + dep_lds_offset_queue(a.mesh_cells, a.tile_cap));
+  ulonglong2 *qW = qBase;
   int2 *qC = reinterpret_cast<int2 *>(qW + nwaves * kDepQueue) + wave * kDepQueue;
   ulonglong2 *qS = reinterpret_cast<ulonglong2 *>(qC + (nwaves - wave) * kDepQueue) + wave * kDepQueue;  // SEG
   qW += wave * kDepQueue;
@@ -1228,6 +1232,10 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
       }
       q_head = (q_head + n) & (kDepQueue - 1);
       q_count -= n;
+      // the entries just read are written again by the next appends
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 
     auto load_state = [&](int kk, uint64_t &xw, uint64_t &cw) {
@@ -1267,6 +1275,8 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
       }
       const uint64_t mask = __builtin_amdgcn_ballot_w64(rec);
       if (mask) {
+        const int n_new = __builtin_popcountll(mask);
+        if (q_count + n_new > kDepQueue) drain(q_count);
         if (rec) {
           const int rank =
               __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
@@ -1281,8 +1291,7 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
             }
           }
         }
-        q_count += __builtin_popcountll(mask);
-        if (q_count >= 64) drain(64);
+        q_count += n_new;
       }
     };
 
@@ -1304,11 +1313,11 @@ __global__ void __launch_bounds__(1024) k_deposit_faces(TracerArgs a) {
 
     if (bad) ms = __longlong_as_double(0x7ff8000000000000ll);
     ms = wave_max(ms);
-    if (lane == 0) sRed[wave] = ms;
+    if (lane == 0) reinterpret_cast<double *>(qW)[0] = ms;  // the ring is empty now
     __syncthreads();
     if (tid == 0) {
       double x = 0.0;
-      for (int w = 0; w < nwaves; ++w) x = nan_max(x, sRed[w]);
+      for (int w = 0; w < nwaves; ++w) x = nan_max(x, reinterpret_cast<const double *>(qBase + w * kDepQueue)[0]);
       a.partials[it].maxseg = x;
     }
     acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + I.mesh_off;
