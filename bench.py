@@ -62,7 +62,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split_f32", "split_u32"])
     ap.add_argument("--deposit-order", type=int, default=0, choices=[0, 1, 2],
@@ -205,13 +205,15 @@ DEPOSIT_BYTES_PER_TRACER = 8   # the position word, read once
 DEPOSIT_BYTES_PER_CELL = 16    # P and D accumulators written
 
 
-def time_deposit(B, I, precision, torch, sheets=8192, tracers=16384, cells=1024, reps=50, warmup=20):
+def time_deposit(B, I, precision, torch, sheets=8192, tracers=16384, cells=1024, reps=100, warmup=150):
     """The standalone deposit (sic_deposit) of one large simulation: 8192
     Landau sheets x 16384 tracers (134M tracers, 1.07 GB of positions, far
     beyond the caches) on 1024 cells, timed with events on the stream the
     kernel runs on (the current torch stream).  The deposit is paced by
-    instruction issue, so the first few launches after an idle spell run at
-    a lower clock; ``warmup`` untimed launches (about 6 ms) come first."""
+    instruction issue, and the engine clock takes about 100 launches (30 ms)
+    to ramp up after the GPU was idle or only streaming memory (windows of 20
+    launches: 0.31, 0.29, 0.28, 0.27, 0.26 ms, then flat), so ``warmup``
+    untimed launches come first."""
     p = I.landau(n_sheets=sheets, n_tracers=tracers, n_cells=cells, n_steps=1)
     x0, v0 = device_inputs(p, torch)
     sim = B.Simulation(p, precision=precision, history_rows=8, x0=x0, v0=v0)

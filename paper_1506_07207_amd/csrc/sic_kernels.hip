@@ -1373,15 +1373,6 @@ __device__ __forceinline__ T block_sum(T v, T *sWave) {
   return r;
 }
 
-__device__ __forceinline__ double block_max(double v, double *sWave) {
-  v = wave_max(v);
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sWave[wave] = v;
-  __syncthreads();
-  const double r = nan_max(nan_max(sWave[0], sWave[1]), nan_max(sWave[2], sWave[3]));
-  __syncthreads();
-  return r;
-}
 
 }  // namespace
 
@@ -1558,8 +1549,17 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
       finite = finite && (e - e == 0.0);
     }
   }
-  const double W = 0.5 * dx * block_sum(w2, sWd);
-  const int bad = block_sum(finite ? 0 : 1, reinterpret_cast<int *>(sWi));
+  // the field energy and the count of non-finite values, in one pass
+  w2 = wave_sum(w2);
+  int nbad = wave_sum(finite ? 0 : 1);
+  if ((tid & 63) == 0) {
+    sWd[tid >> 6] = w2;
+    sWi[tid >> 6] = nbad;
+  }
+  __syncthreads();
+  const double W = 0.5 * dx * (sWd[0] + sWd[1] + sWd[2] + sWd[3]);
+  const int bad = (int)(sWi[0] + sWi[1] + sWi[2] + sWi[3]);
+  __syncthreads();
 
   // 4. diagnostics and step bookkeeping
   const bool pushed = (a.flags & kHavePush) != 0;
@@ -1618,19 +1618,41 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   const int2 si = a.slot_items[slot];
   const int item_begin = si.x, item_count = si.y;
 
-  // 1. work-item partials, in item order
+  // 1. work-item partials, in item order: each thread sums items tid,
+  // tid + 256, ... (loads issued four at a time), then the wavefront and
+  // workgroup sums, all three in one pass
+  __shared__ double sMom[4], sMs[4];
+  constexpr int kU = 4;
   double ke = 0.0, mom = 0.0, ms = 0.0;
-  for (int i = tid; i < item_count; i += kSolveThreads) {
-    const Partial p = a.partials[item_begin + i];
-    ke += p.ke;
-    mom += p.mom;
-    ms = nan_max(ms, p.maxseg);
+  for (int i0 = tid; i0 < item_count; i0 += kU * kSolveThreads) {
+    Partial pr[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kSolveThreads;
+      if (i < item_count) pr[u] = a.partials[item_begin + i];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + u * kSolveThreads < item_count) {
+        ke += pr[u].ke;
+        mom += pr[u].mom;
+        ms = nan_max(ms, pr[u].maxseg);
+      }
+    }
   }
-  if (a.flags & kHavePush) {
-    ke = block_sum(ke, sWd);
-    mom = block_sum(mom, sWd);
+  ke = wave_sum(ke);
+  mom = wave_sum(mom);
+  ms = wave_max(ms);
+  const int wave = tid >> 6;
+  if ((tid & 63) == 0) {
+    sWd[wave] = ke;
+    sMom[wave] = mom;
+    sMs[wave] = ms;
   }
-  if (a.flags & kHaveDeposit) ms = block_max(ms, sWd);
+  __syncthreads();
+  ke = sWd[0] + sWd[1] + sWd[2] + sWd[3];
+  mom = sMom[0] + sMom[1] + sMom[2] + sMom[3];
+  ms = nan_max(nan_max(sMs[0], sMs[1]), nan_max(sMs[2], sMs[3]));
   acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + Ip->mesh_off;
   acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + Ip->mesh_off;
   acc_t *gRamp = (a.order == 1 && a.meshR) ? reinterpret_cast<acc_t *>(a.meshR) + Ip->mesh_off : nullptr;
