@@ -1403,15 +1403,39 @@ __device__ __forceinline__ SlotConst slot_const(const InstDesc &I) {
   return k;
 }
 
+// The slot's point (P) and difference (D) accumulators of this thread's
+// cells, read and cleared: the first half of the solve, apart so that a
+// caller can have these loads in flight with others.
+template <int PREC, int CELLS, class Acc, class T>
+__device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD, T (&pv)[CELLS], T (&dv)[CELLS]) {
+  const int nc = kc.nc;
+  const int per = (nc + kSolveThreads - 1) / kSolveThreads;
+  const int j0 = threadIdx.x * per;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) {
+    pv[k] = (T)0;
+    dv[k] = (T)0;
+    const int j = j0 + k;
+    if (k < per && j < nc) {
+      pv[k] = (T)gP[j];
+      dv[k] = (T)gD[j];
+      gP[j] = (Acc)0;
+      gD[j] = (Acc)0;
+    }
+  }
+}
+
 // step0 and flags0 are the slot's step and sticky flags before this solve;
-// returns the flags after it (the same value in every thread).  With
-// write_field false the field and density are left in sE only (the resident
-// kernel writes them to global memory on its last step).
-template <int PREC, int CELLS, class Acc>
+// pv, dv this thread's accumulators from solve_take; returns the flags after
+// it (the same value in every thread).  With write_field false the field and
+// density are left in sE only (the resident kernel writes them to global
+// memory on its last step).
+template <int PREC, int CELLS, class Acc, class T>
 __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const SlotConst &kc, int64_t step0,
-                                          int flags0, Acc *gP, Acc *gD, Acc *gRamp, double ke, double mom,
-                                          double ms, double *sE, bool write_field) {
+                                          int flags0, const T (&pv)[CELLS], const T (&dv)[CELLS], Acc *gRamp,
+                                          double ke, double mom, double ms, double *sE, bool write_field) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+  static_assert(std::is_same<acc_t, T>::value, "accumulator type");
   __shared__ double sWd[4];
   __shared__ long long sWi[4];
   __shared__ double sLastF[kSolveThreads];
@@ -1421,26 +1445,14 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
   const double L = kc.L, dx = kc.dx, dt = kc.dt;
   const double q_unit = kc.q_unit;
 
-  // 2. charge per cell: Q_j = P_j + sum_{m <= j} D_m; clear the accumulators
+  // 2. charge per cell: Q_j = P_j + sum_{m <= j} D_m
   const int per = (nc + kSolveThreads - 1) / kSolveThreads;
   const int j0 = tid * per;
   double *gE = a.meshE + kc.mesh_off;
   double *gR = a.meshRho + kc.mesh_off;
-  acc_t pv[CELLS], dv[CELLS];
   acc_t dsum = (acc_t)0;
 #pragma unroll
-  for (int k = 0; k < CELLS; ++k) {
-    pv[k] = (acc_t)0;
-    dv[k] = (acc_t)0;
-    const int j = j0 + k;
-    if (k < per && j < nc) {
-      pv[k] = (acc_t)gP[j];
-      dv[k] = (acc_t)gD[j];
-      gP[j] = (Acc)0;
-      gD[j] = (Acc)0;
-    }
-    dsum += dv[k];
-  }
+  for (int k = 0; k < CELLS; ++k) dsum += dv[k];
   auto scan = [&](acc_t v) -> acc_t {
     if constexpr (PREC == kFP64) return block_incl_scan(v, sWd);
     else return block_incl_scan(v, sWi);
@@ -1617,6 +1629,11 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   const int tid = threadIdx.x;
   const int2 si = a.slot_items[slot];
   const int item_begin = si.x, item_count = si.y;
+  const SlotConst kc = slot_const(*Ip);
+  acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + kc.mesh_off;
+  acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + kc.mesh_off;
+  acc_t pv[CELLS], dv[CELLS];
+  solve_take<PREC, CELLS>(kc, gP, gD, pv, dv);  // in flight with the partial loads below
 
   // 1. work-item partials, in item order: each thread sums items tid,
   // tid + 256, ... (loads issued four at a time), then the wavefront and
@@ -1653,10 +1670,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   ke = sWd[0] + sWd[1] + sWd[2] + sWd[3];
   mom = sMom[0] + sMom[1] + sMom[2] + sMom[3];
   ms = nan_max(nan_max(sMs[0], sMs[1]), nan_max(sMs[2], sMs[3]));
-  acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + Ip->mesh_off;
-  acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + Ip->mesh_off;
-  acc_t *gRamp = (a.order == 1 && a.meshR) ? reinterpret_cast<acc_t *>(a.meshR) + Ip->mesh_off : nullptr;
-  solve_slot<PREC, CELLS>(a, slot, slot_const(*Ip), Ip->step, Ip->flags, gP, gD, gRamp, ke, mom, ms,
+  acc_t *gRamp = (a.order == 1 && a.meshR) ? reinterpret_cast<acc_t *>(a.meshR) + kc.mesh_off : nullptr;
+  solve_slot<PREC, CELLS>(a, slot, kc, Ip->step, Ip->flags, pv, dv, gRamp, ke, mom, ms,
                           (double *)nullptr, true);
 }
 
@@ -1832,7 +1847,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveA
     }
     // solve (clears the accumulators, leaves the field in sE; in global
     // memory too after the last step)
-    flags = solve_slot<PREC, CELLS>(sa, slot, kc, step_now, flags, sP, sD, (acc_t *)nullptr, ke, mom, ms, sE,
+    using sacc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+    sacc_t pv[CELLS], dv[CELLS];
+    solve_take<PREC, CELLS>(kc, sP, sD, pv, dv);
+    flags = solve_slot<PREC, CELLS>(sa, slot, kc, step_now, flags, pv, dv, (acc_t *)nullptr, ke, mom, ms, sE,
                                     step == n_steps - 1);
     step_now += 1;
     lds_barrier();
