@@ -561,15 +561,14 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
   const sic_tuning saved = p->tune;
   const bool saved_timing = p->timing;
   p->timing = true;
-  const int tiles[] = {32, 64, 128, 256};
+  const int tiles[] = {0, 16, 32, 64, 128, 256};  // 0: the default item size
   const int blocks[] = {256, 512, 1024};
   const int grids[] = {0, 1024, 2048, 4096};  // 0: one work item per workgroup
   sic_tuning best = saved;
   double best_ms = 1e300;
   for (int t : tiles) {
-    if (!p->batch && t > 64) continue;
     for (int b : blocks) {
-      if (t * kChunk < b) continue;  // every wave gets at least one chunk
+      if (t > 0 && t * kChunk < b) continue;  // every wave gets at least one chunk
       for (int g : grids) {
         sic_tuning cand{t, b, g, 0};
         p->tune = cand;
