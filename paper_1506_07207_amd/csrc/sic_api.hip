@@ -167,7 +167,8 @@ struct Pool {
   int parity = 0;
   sic_tuning tune{};  // requested (0 = automatic)
   int block = kDefaultBlock, grid = kDefaultGrid, tile = kMinTile;
-  std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;  // (steps, parity, grid)
+  int solve_grid = 1;  // solve workgroups of a whole-pool step: live slot indices, rounded up
+  std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;  // (steps, parity, grid, solve grid)
   std::vector<hipGraph_t> graph_objs;
   bool timing = false;
   double t_tracer = 0.0, t_solve = 0.0;
@@ -394,6 +395,22 @@ void apply_launch_shape(Pool *p) {
   } else {
     p->grid = std::max(1, std::min<int>(p->n_items_h, kMaxGrid));
   }
+}
+
+// The whole-pool solve launches one workgroup per slot index up to the
+// highest live one (slots are taken lowest first), rounded up to a power of
+// two so that graphs are captured again only when that crosses one; the
+// workgroups of slots that are not live return at once.
+void update_solve_grid(Pool *p) {
+  int32_t hw = 0;
+  for (int32_t i = p->slot_cap - 1; i >= 0; --i)
+    if (p->slots[i].live) {
+      hw = i + 1;
+      break;
+    }
+  int g = 1;
+  while (g < hw) g *= 2;
+  p->solve_grid = std::min(g, (int)p->slot_cap);
 }
 
 // Uploads the device-side item count (the high-water mark of the item arena).
@@ -670,7 +687,7 @@ sic_status launch_tracer_mode(Pool *p, int mode, int slot, hipStream_t st) {
 
 sic_status launch_solve_mode(Pool *p, int flags, int slot, hipStream_t st) {
   SolveArgs a = solve_args(p, flags, slot);
-  LAUNCHCHK(p, launch_solve(p->prec, a, slot >= 0 ? 1 : p->slot_cap, p->max_cells, st));
+  LAUNCHCHK(p, launch_solve(p->prec, a, slot >= 0 ? 1 : p->solve_grid, p->max_cells, st));
   return SIC_OK;
 }
 
@@ -687,7 +704,7 @@ sic_status enqueue_fused(Pool *p, hipStream_t st) {
 }
 
 sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
-  auto key = std::make_tuple(k, p->parity, p->grid);
+  auto key = std::make_tuple(k, p->parity, p->grid, p->solve_grid);
   auto it = p->graphs.find(key);
   if (it != p->graphs.end()) {
     *out = it->second;
@@ -1092,6 +1109,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   }
   p->used_tracers += reserve_tr;
   p->used_slots += 1;
+  update_solve_grid(p);
   // ingest: place tracers, deposit, solve, half back-kick
   int le = ingest_slot(p, slot, dx0, nullptr, dv0, dc0, nullptr);
   if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
@@ -1266,6 +1284,7 @@ sic_status pool_release(Pool *p, int32_t slot) {
   p->used_tracers -= sh.max_tracers;
   p->used_slots -= 1;
   sh.live = false;
+  update_solve_grid(p);
   sh.chunk_in_off.clear();
   if (sh.d_in_off) {
     hipFree(sh.d_in_off);
