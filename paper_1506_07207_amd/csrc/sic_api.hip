@@ -568,8 +568,8 @@ sic_status snapshot_restore(Pool *p, Snapshot &s) {
 // Times every candidate launch shape on the pool's own resident simulations
 // (HIP events around each kernel), then restores the state and keeps the
 // fastest shape.  Candidates: chunks per work item (LDS mesh merges per
-// tracer), threads per workgroup (waves sharing one LDS mesh) and persistent
-// grid size.
+// tracer), threads per workgroup (waves sharing one LDS mesh) and grid size
+// (one item per workgroup, or fewer workgroups looping over the items).
 sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *best_ms_out) {
   if (steps < 1) return fail(p, SIC_EINVAL, "steps_per_trial < 1");
   Snapshot snap;
