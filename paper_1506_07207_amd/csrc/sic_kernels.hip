@@ -631,16 +631,71 @@ __device__ __forceinline__ double nan_max(double a, double b) {
   return (b > a || b != b) ? b : a;
 }
 
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// A 4- or 8-byte value moved across lanes by a DPP control (CTRL), written
+// in the rows of ROWS; lanes left without a source, and rows not written,
+// get 0.  Register moves: no LDS round trip.
+template <int CTRL, int ROWS, class T>
+__device__ __forceinline__ T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  T r;
+  if constexpr (sizeof(T) == 4) {
+    int i;
+    __builtin_memcpy(&i, &v, 4);
+    i = __builtin_amdgcn_update_dpp(0, i, CTRL, ROWS, 0xf, true);
+    __builtin_memcpy(&r, &i, 4);
+  } else {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, true);
+    u = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    __builtin_memcpy(&r, &u, 8);
+  }
+  return r;
+}
+
+// Inclusive scan over the wavefront (lane i: v_0 op ... op v_i; all 64
+// lanes active): within each 16-lane row by shifts of 1, 2, 4 and 8 lanes,
+// then across rows by broadcasting lane 15 into rows 1 and 3 and lane 31
+// into rows 2 and 3.  Empty sources contribute 0 (an identity for the sums
+// and for the maximum of non-negative values here).
+template <class T, class Op>
+__device__ __forceinline__ T wave_incl_scan(T v, Op op) {
+  v = op(v, dpp_move<0x111, 0xf>(v));  // row_shr:1
+  v = op(v, dpp_move<0x112, 0xf>(v));  // row_shr:2
+  v = op(v, dpp_move<0x114, 0xf>(v));  // row_shr:4
+  v = op(v, dpp_move<0x118, 0xf>(v));  // row_shr:8
+  v = op(v, dpp_move<0x142, 0xa>(v));  // row_bcast:15
+  v = op(v, dpp_move<0x143, 0xc>(v));  // row_bcast:31
   return v;
 }
+
+// Lane 63's value in every lane.
+template <class T>
+__device__ __forceinline__ T from_lane63(T v) {
+  T r;
+  if constexpr (sizeof(T) == 4) {
+    int i;
+    __builtin_memcpy(&i, &v, 4);
+    i = __builtin_amdgcn_readlane(i, 63);
+    __builtin_memcpy(&r, &i, 4);
+  } else {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    u = read_lane64(u, 63);
+    __builtin_memcpy(&r, &u, 8);
+  }
+  return r;
+}
+
+// Sum and NaN-propagating maximum over the wavefront, the same bits in every
+// lane (all 64 lanes active).
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  return from_lane63(wave_incl_scan(v, [](T x, T y) { return x + y; }));
+}
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
-  return v;
+  return from_lane63(wave_incl_scan(v, [](double x, double y) { return nan_max(x, y); }));
 }
 
 }  // namespace
@@ -1349,11 +1404,7 @@ template <class T>
 __device__ __forceinline__ T block_incl_scan(T v, T *sWave) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T n = __shfl_up(v, off, 64);
-    if (lane >= off) v += n;
-  }
+  v = wave_incl_scan(v, [](T x, T y) { return x + y; });
   if (lane == 63) sWave[wave] = v;
   __syncthreads();
   T base = (T)0;
