@@ -3,9 +3,9 @@
 //   k_tracers  one pass over the tracers: gather + leapfrog move (section 2.3,
 //              "gather" with first-order weighting of section 2.4, "move"),
 //              and/or the exact segment deposit (section 2.3, eqs. "overlap"
-//              and "rho_sum") of the resulting positions.  Persistent
-//              workgroups walk a list of work items; one item is a run of
-//              64-tracer chunks of one simulation.  Each workgroup
+//              and "rho_sum") of the resulting positions.  Workgroups walk
+//              a list of work items (by default one item each); one item is
+//              a run of 64-tracer chunks of one simulation.  Each workgroup
 //              accumulates the item's charge in a private LDS copy of that
 //              simulation's mesh and merges it into the global mesh with one
 //              atomic per touched cell.
@@ -698,6 +698,38 @@ __device__ __forceinline__ double wave_max(double v) {
   return from_lane63(wave_incl_scan(v, [](double x, double y) { return nan_max(x, y); }));
 }
 
+// The value of the next lane (lane_down1) or of the previous one (lane_up1),
+// a lane at the wavefront's edge keeping its own: __shfl_down / __shfl_up
+// by one lane, as a DPP register move (all 64 lanes active).
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_wave_shift(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  T r;
+  if constexpr (sizeof(T) == 4) {
+    int i;
+    __builtin_memcpy(&i, &v, 4);
+    i = __builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false);
+    __builtin_memcpy(&r, &i, 4);
+  } else {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    const int lo0 = (int)(uint32_t)u, hi0 = (int)(uint32_t)(u >> 32);
+    const int lo = __builtin_amdgcn_update_dpp(lo0, lo0, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(hi0, hi0, CTRL, 0xf, 0xf, false);
+    u = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    __builtin_memcpy(&r, &u, 8);
+  }
+  return r;
+}
+template <class T>
+__device__ __forceinline__ T lane_down1(T v) {
+  return dpp_wave_shift<0x130>(v);  // wave_shl:1
+}
+template <class T>
+__device__ __forceinline__ T lane_up1(T v) {
+  return dpp_wave_shift<0x138>(v);  // wave_shr:1
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -847,8 +879,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       // tracer (cl) and, for linear segments, the next one (cn).
       uint64_t cl = 0, cn = 0;
       if constexpr (kNeedQ) {
-        const uint64_t up = (uint64_t)__shfl_up((long long)cw, 1, 64);
-        const uint64_t dn = (uint64_t)__shfl_down((long long)cw, 1, 64);
+        const uint64_t up = lane_up1(cw);
+        const uint64_t dn = lane_down1(cw);
         cl = lane == 0 ? sEdge[2 * kk] : up;
         cn = lane == n_valid - 1 ? sEdge[2 * kk + 1] : dn;
       }
@@ -908,8 +940,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         const uint64_t hpv = read_lane64(hw, 0);
         const uint64_t hn1 = read_lane64(hw, 1);
         const uint64_t hn2 = read_lane64(hw, 2);
-        const uint64_t up1 = (uint64_t)__shfl_up((long long)xw, 1, 64);
-        const uint64_t dn1 = (uint64_t)__shfl_down((long long)xw, 1, 64);
+        const uint64_t up1 = lane_up1(xw);
+        const uint64_t dn1 = lane_down1(xw);
         const uint64_t dn2 = (uint64_t)__shfl_down((long long)xw, 2, 64);
         const uint64_t xm1 = lane > 0 ? up1 : hpv;
         const bool has_m1 = lane > 0 || have_pv;
@@ -965,7 +997,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         }
       }
       if constexpr (kDep && !kLin) {
-        uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
+        uint64_t pw = lane_down1(xw);
         const bool tail = (lane == n_valid - 1);
         bool has_seg = valid;
         if (tail) {
@@ -1306,9 +1338,9 @@ k_deposit_faces(TracerArgs a) {
       const bool has_seg = lane <= last;
       // the segment's far end: the next lane, or past the chunk the partner's
       // first tracer
-      uint64_t xb = (uint64_t)__shfl_down((long long)xw, 1, 64);
+      uint64_t xb = lane_down1(xw);
       const int ca = point_cell_up<PREC>(xw, g, tol, tol_hi);
-      int cb1 = __shfl_down(ca, 1, 64);
+      int cb1 = lane_down1(ca);
       if (!open_end) {
         const bool tail = lane == n_valid - 1;
         const DepHalo h = sHalo[kk];
@@ -1836,7 +1868,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveA
         const double vn = v + g.dt * e;
         double m;
         if constexpr (SEG) {
-          const uint64_t up = (uint64_t)__shfl_up((long long)cwr[j], 1, 64);
+          const uint64_t up = lane_up1(cwr[j]);
           m = tracer_mass<PREC>(lane == 0 ? sEdge[2 * c] : up, cwr[j], q_unit);
         } else {
           const bool end =
@@ -1861,7 +1893,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveA
         const ChunkDesc &ch = sDesc[c];
         const int n_valid = __builtin_amdgcn_readfirstlane(ch.n_valid);
         const uint64_t xw = xr[j];
-        uint64_t pw = (uint64_t)__shfl_down((long long)xw, 1, 64);
+        uint64_t pw = lane_down1(xw);
         bool has_seg = lane < n_valid;
         if (lane == n_valid - 1) {
           if (ch.partner < 0) has_seg = false;  // open sheet: the last tracer ends the chain
@@ -2059,7 +2091,7 @@ __global__ void __launch_bounds__(256) k_refine_mark(RefineArgs a) {
   const InstDesc &I = a.inst[ch.inst];
   const size_t s = (size_t)c * kChunk + lane;
   const uint64_t w = a.xs[s];
-  uint64_t wn = (uint64_t)__shfl_down((long long)w, 1, 64);
+  uint64_t wn = lane_down1(w);
   double vn = 0.0, du = 0.0;
   const bool flag = refine_segment<PREC>(a, ch, I, lane, w, wn, vn, du);
   const uint64_t mask = __ballot(flag);
@@ -2084,8 +2116,8 @@ __global__ void __launch_bounds__(256) k_refine_scatter(RefineArgs a) {
   const uint64_t w = a.xs[s];
   const double v = a.vs[s];
   const uint64_t cq = a.segq[s];
-  uint64_t wn = (uint64_t)__shfl_down((long long)w, 1, 64);
-  double vn = __shfl_down(v, 1, 64);
+  uint64_t wn = lane_down1(w);
+  double vn = lane_down1(v);
   double du = 0.0;
   refine_segment<PREC>(a, ch, I, lane, w, wn, vn, du);
   // the marking pass decided (the host sized the output from its counts)
