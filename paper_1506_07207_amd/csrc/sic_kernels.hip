@@ -371,23 +371,17 @@ __device__ __forceinline__ Crossings<T> face_crossings(uint64_t wa, uint64_t wb,
   return c;
 }
 
+template <class T, class Op>
+__device__ __forceinline__ T wave_incl_scan(T v, Op op);
 template <class T>
-__device__ __forceinline__ T shfl_up_acc(T v, int off) {
-  if constexpr (std::is_same<T, double>::value) return __shfl_up(v, off, 64);
-  else return (T)__shfl_up((long long)v, off, 64);
-}
+__device__ __forceinline__ T lane_up1(T v);
 
-// Exclusive prefix sum over the wavefront (called by all 64 lanes).
+// Exclusive prefix sum over the wavefront (called by all 64 lanes): the
+// inclusive scan moved up one lane.
 template <class T>
 __device__ __forceinline__ T wave_exclusive_sum(T v) {
   const int lane = threadIdx.x & 63;
-  T incl = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T u = shfl_up_acc(incl, off);
-    if (lane >= off) incl += u;
-  }
-  const T prev = shfl_up_acc(incl, 1);
+  const T prev = lane_up1(wave_incl_scan(v, [](T x, T y) { return x + y; }));
   return lane == 0 ? (T)0 : prev;
 }
 
@@ -942,7 +936,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         const uint64_t hn2 = read_lane64(hw, 2);
         const uint64_t up1 = lane_up1(xw);
         const uint64_t dn1 = lane_down1(xw);
-        const uint64_t dn2 = (uint64_t)__shfl_down((long long)xw, 2, 64);
+        const uint64_t dn2 = lane_down1(dn1);  // two lanes on (used below lane n_valid - 2 only)
         const uint64_t xm1 = lane > 0 ? up1 : hpv;
         const bool has_m1 = lane > 0 || have_pv;
         const uint64_t xp1 = lane < n_valid - 1 ? dn1 : hn1;
