@@ -123,3 +123,34 @@ def test_admission_refusals():
             B.sic_batch_release(b, 2)  # not live
     finally:
         B.sic_batch_destroy(b)
+
+
+def test_sparse_live_slots_after_release():
+    """The whole-batch solve launches one workgroup per slot index up to the
+    highest live one: with slots 1..5 released, slots 0 and 6 (and a slot
+    admitted afterwards into the freed range) must still get their solves,
+    bitwise as alone (split form)."""
+    prec = B.SIC_SPLIT_U32
+    probs = [I.random_sheets(40 + i, 3, [70, 64, 130], 64, L=2.0, dt=0.05, n_steps=30, jitter=0.3)
+             for i in range(7)]
+    late = I.landau(n_sheets=8, n_tracers=128, n_cells=64, n_steps=30, alpha=0.05)
+    total = sum(p.total_tracers for p in probs) + late.total_tracers
+    b = B.sic_batch_create(total + 1000, 8, 64, precision=prec)
+    try:
+        slots = [_admit(b, p, prec) for p in probs]
+        assert slots == list(range(7))
+        B.sic_batch_step(b, 4)
+        for s in slots[1:6]:
+            B.sic_batch_release(b, s)
+        s_late = _admit(b, late, prec)
+        assert s_late == 1  # lowest free slot
+        B.sic_batch_step(b, 40)
+        done = B.sic_batch_poll(b)
+        assert sorted(done) == [0, 1, 6]
+        for p, s in ((probs[0], 0), (probs[6], 6), (late, s_late)):
+            x, v, _ = _alone(p, prec)
+            xb, vb, step = B.sic_batch_get_state(b, s, p.total_tracers)
+            assert step == p.n_steps
+            assert np.array_equal(xb, x) and np.array_equal(vb, v)
+    finally:
+        B.sic_batch_destroy(b)
