@@ -181,19 +181,27 @@ def test_refinement_run_other_deposit_orders_match_oracle(order):
 
     In the folded vortex the piecewise-linear gradients divide by small
     centroid separations, and the run is chaotic: the oracle itself departs
-    from its own history by more than 1e-10 once its initial positions move
-    by one ulp.  The field energy is held to 1e-10 up to that step (measured
-    here), and past it oracle-resynchronised single steps are held to
-    1e-10."""
+    from its own history once its initial positions move by one ulp.  The
+    GPU's deposit differs from the oracle's by rounding in every step, so
+    its error grows the same way: the field energy is held to 1e-10 up to
+    the step where the oracle's own departure under perturbations of a few
+    ulps first reaches 1e-11 (a decade of margin, measured here), and past
+    it oracle-resynchronised single steps are held to 1e-10."""
     p = I.refinement_two_stream(n_steps=320)
     dx = p.L / p.n_cells
     kw = dict(l_max=dx, capacity=200_000, order=order)
     ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, **kw)
-    rng = np.random.default_rng(1)
-    x_ulp = p.x0 + rng.choice([-1.0, 0.0, 1.0], len(p.x0)) * np.spacing(p.x0)
-    own = _envelope_errors(O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, x_ulp, p.v0,
-                                     p.n_steps, **kw)["hist"][:, 2], ref["hist"][:, 2], p.dt)
-    horizon = int(np.argmax(own > 1e-10)) if np.any(own > 1e-10) else p.n_steps + 1
+    # the predictability horizon: the earliest step at which one of three
+    # oracle runs from initial positions moved by up to two ulps departs from
+    # the reference by 1e-11
+    horizon = p.n_steps + 1
+    for seed in (1, 2, 3):
+        rng = np.random.default_rng(seed)
+        x_ulp = p.x0 + rng.choice([-2.0, -1.0, 0.0, 1.0, 2.0], len(p.x0)) * np.spacing(p.x0)
+        own = _envelope_errors(O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, x_ulp,
+                                         p.v0, p.n_steps, **kw)["hist"][:, 2], ref["hist"][:, 2], p.dt)
+        if np.any(own > 1e-11):
+            horizon = min(horizon, int(np.argmax(own > 1e-11)))
     with B.Simulation(p, l_max=dx, max_tracers=200_000, deposit_order=order) as s:
         s.step(p.n_steps)
         h = s.diagnostics()["history"]
