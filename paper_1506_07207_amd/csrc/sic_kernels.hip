@@ -838,8 +838,18 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           if (pc >= 0) sHalo[i] = a.halo3_in[3 * pc + kHaloFirst];
           if (lk.y >= 0) sHalo2[i] = a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)];
           if (lk.x >= 0) sHaloP[i] = a.halo3_in[3 * (lk.x >> 2) + (lk.x & 3)];
-        } else {
-          if (pc >= 0) sHalo[i] = a.halo_in[pc];
+        } else if (pc >= 0) {
+          double2 h = a.halo_in[pc];
+          if constexpr (kMove) {
+            // the partner's move, from its state before this step: done here
+            // once per chunk by one thread rather than by a whole wavefront
+            // for its last lane
+            uint64_t pw = (uint64_t)__double_as_longlong(h.x);
+            const double e = gather_field(sE, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
+            pw = drift<PREC>(pw, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
+            h.x = __longlong_as_double((long long)pw);
+          }
+          sHalo[i] = h;
         }
       }
       __syncthreads();
@@ -998,14 +1008,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           if (ch.partner < 0) {
             has_seg = false;  // open sheet: the last tracer ends the chain
           } else {
-            const double2 h = sHalo[kk];
-            pw = (uint64_t)__double_as_longlong(h.x);
-            if constexpr (kMove) {
-              // the partner's move, recomputed from its state before this step
-              const double e = gather_field(sE, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
-              const double hv = h.y + g.dt * e;
-              pw = drift<PREC>(pw, hv, g.dt, g.L, g.inv_dx, g.nc);
-            }
+            pw = (uint64_t)__double_as_longlong(sHalo[kk].x);  // moved at staging when this step moves
           }
         }
         if (has_seg) {
