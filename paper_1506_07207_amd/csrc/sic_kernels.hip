@@ -906,8 +906,10 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
             m = end ? 0.5 * ch.q : ch.q;
           }
           const double qv = valid ? m : 0.0;
-          ke += 0.5 * qv * v * vn;
-          mom += qv * (0.5 * (v + vn));
+          // twice the kinetic energy and momentum: the factor 1/2 is applied
+          // to the item's sums (a power of two, so the same bits)
+          ke += qv * v * vn;
+          mom += qv * (v + vn);
           const uint64_t xn = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
           xw = valid ? xn : xw;
           v = valid ? vn : v;
@@ -1093,8 +1095,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         x = nan_max(x, sRed[32 + w]);
       }
       if constexpr (kMove) {
-        a.partials[it].ke = kk;
-        a.partials[it].mom = m;
+        a.partials[it].ke = 0.5 * kk;
+        a.partials[it].mom = 0.5 * m;
       }
       if constexpr (kDep) a.partials[it].maxseg = x;
     }
@@ -1873,8 +1875,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveA
           m = end ? 0.5 * ch.q : ch.q;
         }
         const double qv = valid ? m : 0.0;
-        ke += 0.5 * qv * v * vn;
-        mom += qv * (0.5 * (v + vn));
+        ke += qv * v * vn;  // twice the kinetic energy and momentum, halved below
+        mom += qv * (v + vn);
         const uint64_t xn = drift<PREC>(xw, vn, g.dt, g.L, g.inv_dx, g.nc);
         xr[j] = valid ? xn : xw;
         vr[j] = valid ? vn : v;
@@ -1925,6 +1927,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveA
       mom += sRed[kResidentWaves + w];
       ms = nan_max(ms, sRed[2 * kResidentWaves + w]);
     }
+    ke *= 0.5;
+    mom *= 0.5;
     // solve (clears the accumulators, leaves the field in sE; in global
     // memory too after the last step)
     using sacc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
