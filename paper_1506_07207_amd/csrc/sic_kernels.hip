@@ -125,6 +125,17 @@ __device__ __forceinline__ double gather_field(const double *E, double u, int nc
   return (1.0 - s) * E[j0] + s * E[j1];
 }
 
+// The same interpolation from a field array with one ghost cell on each side
+// (E[-1] = E[nc-1], E[nc] = E[0]): no periodic wrap of the two indices; the
+// clamp keeps non-finite positions inside the array.
+__device__ __forceinline__ double gather_field_ghost(const double *E, double u, int nc) {
+  const double g = u - 0.5;
+  const double f = floor(g);
+  const double s = g - f;
+  const int j = min(max((int)f, -1), nc - 1);
+  return (1.0 - s) * E[j] + s * E[j + 1];
+}
+
 // Split-form word moved by du cells: t = fraction + du, the cell advances by
 // floor(t) (periodically) and the rest is re-quantised.
 template <int PREC>
@@ -740,7 +751,7 @@ __device__ __forceinline__ T lane_up1(T v) {
 // constant segments.  SEG: per-segment charges (a charge word per tracer).
 template <class Acc, int ORDER, bool SEG>
 __host__ __device__ constexpr size_t tracer_lds_bytes(int mesh_cells, int tile_cap) {
-  return (size_t)(2 + (ORDER == 1)) * mesh_cells * sizeof(Acc) + (size_t)mesh_cells * sizeof(double) +
+  return (size_t)(2 + (ORDER == 1)) * mesh_cells * sizeof(Acc) + (size_t)(mesh_cells + 2) * sizeof(double) +
          (size_t)tile_cap *
              (sizeof(ChunkDesc) + (ORDER == 1 ? 3 : 1) * sizeof(double2) + (ORDER == 1 ? sizeof(int2) : 0) +
               (SEG ? 2 * sizeof(uint64_t) : 0)) +
@@ -773,8 +784,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   acc_t *sD = sP + a.mesh_cells;
   constexpr bool kLin = ORDER == 1;
   acc_t *sR = sD + a.mesh_cells;  // linear segments only
-  double *sE = reinterpret_cast<double *>(sR + (kLin ? a.mesh_cells : 0));
-  ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sE + a.mesh_cells);
+  double *sE = reinterpret_cast<double *>(sR + (kLin ? a.mesh_cells : 0)) + 1;  // ghost cells at -1 and nc
+  ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sE + a.mesh_cells + 1);
   double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);  // order 0: next tracer; order 1: next
   double2 *sHalo2 = sHalo + a.tile_cap;                               // order 1: next but one
   double2 *sHaloP = sHalo2 + a.tile_cap;                              // order 1: previous
@@ -821,6 +832,12 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       }
       if constexpr (kField) sE[i] = a.meshE[I.mesh_off + i];
     }
+    if constexpr (kField) {
+      if (tid == 0) {
+        sE[-1] = a.meshE[I.mesh_off + g.nc - 1];
+        sE[g.nc] = a.meshE[I.mesh_off];
+      }
+    }
     for (int i = tid; i < nch; i += blockDim.x) {
       sDesc[i] = a.chunks[cb + i];
       if constexpr (kLin && kDep) sLinks[i] = a.links[cb + i];
@@ -845,7 +862,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
             // once per chunk by one thread rather than by a whole wavefront
             // for its last lane
             uint64_t pw = (uint64_t)__double_as_longlong(h.x);
-            const double e = gather_field(sE, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
+            const double e = gather_field_ghost(sE, mesh_pos<PREC>(pw, g.inv_dx), g.nc);
             pw = drift<PREC>(pw, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
             h.x = __longlong_as_double((long long)pw);
           }
@@ -889,7 +906,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         cn = lane == n_valid - 1 ? sEdge[2 * kk + 1] : dn;
       }
       if constexpr (kField) {
-        const double e = gather_field(sE, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
+        const double e = gather_field_ghost(sE, mesh_pos<PREC>(xw, g.inv_dx), g.nc);
         if constexpr (kKick) {
           const double vk = v - (0.5 * g.dt) * e;
           v = valid ? vk : v;
@@ -939,7 +956,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           const double2 h = sHalo[(lane == 0 ? 2 : lane - 1) * a.tile_cap + kk];
           hw = (uint64_t)__double_as_longlong(h.x);
           if constexpr (kMove) {
-            const double e = gather_field(sE, mesh_pos<PREC>(hw, g.inv_dx), g.nc);
+            const double e = gather_field_ghost(sE, mesh_pos<PREC>(hw, g.inv_dx), g.nc);
             hw = drift<PREC>(hw, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
           }
         }
