@@ -851,10 +851,21 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       for (int i = tid; i < nch; i += blockDim.x) {
         const int pc = sDesc[i].partner;
         if constexpr (kLin) {
+          // the three halo tracers, moved here (once per chunk, one thread)
+          // when this step moves, as for the constant scheme below
+          auto moved = [&](double2 h) {
+            if constexpr (kMove) {
+              uint64_t w = (uint64_t)__double_as_longlong(h.x);
+              const double e = gather_field_ghost(sE, mesh_pos<PREC>(w, g.inv_dx), g.nc);
+              w = drift<PREC>(w, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
+              h.x = __longlong_as_double((long long)w);
+            }
+            return h;
+          };
           const int2 lk = sLinks[i];
-          if (pc >= 0) sHalo[i] = a.halo3_in[3 * pc + kHaloFirst];
-          if (lk.y >= 0) sHalo2[i] = a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)];
-          if (lk.x >= 0) sHaloP[i] = a.halo3_in[3 * (lk.x >> 2) + (lk.x & 3)];
+          if (pc >= 0) sHalo[i] = moved(a.halo3_in[3 * pc + kHaloFirst]);
+          if (lk.y >= 0) sHalo2[i] = moved(a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)]);
+          if (lk.x >= 0) sHaloP[i] = moved(a.halo3_in[3 * (lk.x >> 2) + (lk.x & 3)]);
         } else if (pc >= 0) {
           double2 h = a.halo_in[pc];
           if constexpr (kMove) {
@@ -945,20 +956,15 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       }
       if constexpr (kDep && kLin) {
         // Tracers i-1, i+1, i+2 of segment i: lane shuffles inside the chunk,
-        // halo copies past its ends.  Lanes 0, 1 and 2 take the previous, next
-        // and next-but-one halo tracer (moved from its pre-step state when this
-        // kernel also moves) and broadcast it, so the wave pays for one move.
+        // halo copies past its ends (moved at staging when this kernel also
+        // moves).  Lanes 0, 1 and 2 read the previous, next and next-but-one
+        // halo tracer and broadcast it.
         const int2 lk = sLinks[kk];
         const bool have_n1 = ch.partner >= 0, have_n2 = lk.y >= 0, have_pv = lk.x >= 0;
         uint64_t hw = xw;
         if (lane < 3 && (lane == 0 ? have_pv : (lane == 1 ? have_n1 : have_n2))) {
           // sHalo, sHalo2 and sHaloP are consecutive tile_cap-long arrays
-          const double2 h = sHalo[(lane == 0 ? 2 : lane - 1) * a.tile_cap + kk];
-          hw = (uint64_t)__double_as_longlong(h.x);
-          if constexpr (kMove) {
-            const double e = gather_field_ghost(sE, mesh_pos<PREC>(hw, g.inv_dx), g.nc);
-            hw = drift<PREC>(hw, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
-          }
+          hw = (uint64_t)__double_as_longlong(sHalo[(lane == 0 ? 2 : lane - 1) * a.tile_cap + kk].x);
         }
         const uint64_t hpv = read_lane64(hw, 0);
         const uint64_t hn1 = read_lane64(hw, 1);
