@@ -1541,8 +1541,11 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
                                           double ke, double mom, double ms, double *sE, bool write_field) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
   static_assert(std::is_same<acc_t, T>::value, "accumulator type");
-  __shared__ double sWd[4];
-  __shared__ long long sWi[4];
+  // The cells are partitioned over kSolveThreads threads; a wider workgroup
+  // (the resident kernel's) runs the same code, its other threads holding no
+  // cells and adding zeros, so the result has the same bits.
+  __shared__ double sWd[16];
+  __shared__ long long sWi[16];
   __shared__ double sLastF[kSolveThreads];
   InstDesc *Ip = a.inst + slot;
   const int tid = threadIdx.x;
@@ -1646,9 +1649,9 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
       lastF = F[k];
     }
   }
-  sLastF[tid] = lastF;
+  if (tid < kSolveThreads) sLastF[tid] = lastF;
   __syncthreads();
-  double prevF = (tid == 0) ? sLastF[(nc - 1) / per] : sLastF[tid - 1];
+  double prevF = (tid == 0) ? sLastF[(nc - 1) / per] : (tid < kSolveThreads ? sLastF[tid - 1] : 0.0);
   double w2 = 0.0;
   bool finite = true;
 #pragma unroll
@@ -1784,8 +1787,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
 // Resident small simulation
 // ---------------------------------------------------------------------------
 // A simulation of at most kResidentChunks chunks runs many steps in one
-// launch of one workgroup: its tracers stay in registers (each wavefront
-// owns chunks w, w + 4, ...), the mesh accumulators and the field in LDS, and
+// launch of one workgroup: its tracers stay in registers (each of the W
+// wavefronts owns chunks w, w + W, ...), the mesh accumulators and the field in LDS, and
 // each step is push, deposit and solve separated by workgroup barriers.  The
 // arithmetic is that of the fused step (same move, same segment deposit,
 // same solve code), so only the order of the floating-point sums of the
@@ -1793,9 +1796,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
 // split forms give the same bits.  Small simulations are latency-bound: this
 // replaces two kernel launches per step with one launch per call.
 
-constexpr int kResidentWaves = kSolveThreads / kChunk;   // 4
-constexpr int kResidentPerWave = 8;
-constexpr int kResidentChunks = kResidentWaves * kResidentPerWave;  // 32 chunks, 2048 slots
+constexpr int kResidentChunks = 32;  // chunks (2048 tracer slots) a resident launch holds
 
 // P, D, E; then (16-byte aligned) descriptors, new first-tracer words and
 // charge edges
@@ -1814,10 +1815,13 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int PREC, bool SEG, int CELLS>
-__global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveArgs sa, int chunk_begin,
-                                                            int n_chunks, int64_t n_steps) {
+template <int PREC, bool SEG, int CELLS, int NT>
+__global__ void __launch_bounds__(NT) k_resident(TracerArgs a, SolveArgs sa, int chunk_begin, int n_chunks,
+                                                 int64_t n_steps) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
+  // NT / 64 wavefronts share the chunks (wave w takes w, w + waves, ...)
+  constexpr int kResidentWaves = NT / kChunk;
+  constexpr int kResidentPerWave = kResidentChunks / kResidentWaves;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sRed[3 * kResidentWaves];
   const int tid = threadIdx.x;
@@ -1844,12 +1848,12 @@ __global__ void __launch_bounds__(kSolveThreads) k_resident(TracerArgs a, SolveA
   int64_t step_now = Ip->step;
   int flags = Ip->flags;
 
-  for (int i = tid; i < nc; i += kSolveThreads) {
+  for (int i = tid; i < nc; i += NT) {
     sP[i] = (acc_t)0;
     sD[i] = (acc_t)0;
     sE[i] = a.meshE[Ip->mesh_off + i];
   }
-  for (int i = tid; i < n_chunks; i += kSolveThreads) {
+  for (int i = tid; i < n_chunks; i += NT) {
     sDesc[i] = a.chunks[chunk_begin + i];
     if constexpr (SEG) {
       sEdge[2 * i] = a.cedge[2 * (size_t)(chunk_begin + i)];
@@ -2306,18 +2310,23 @@ int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a,
   return (int)dispatch<LaunchTracers>(prec, order, seg, mode, a, grid, block, lds, (hipStream_t)stream);
 }
 
+// Meshes of up to 1024 cells run the resident kernel with 8 wavefronts (four
+// chunks each: twice the latency hiding of four; 16 wavefronts would leave
+// 128 VGPRs and spill); larger ones, whose solve holds 16 cells per thread
+// in registers, with four.
 template <int PREC, bool SEG, int CELLS>
 static hipError_t resident_launch(const TracerArgs &a, const SolveArgs &sa, int chunk_begin, int n_chunks,
                                   int64_t n_steps, size_t lds, hipStream_t st) {
+  constexpr int NT = CELLS <= 4 ? 512 : kSolveThreads;
   static bool limit_set = false;
   if (!limit_set) {
-    const hipError_t e = hipFuncSetAttribute((const void *)k_resident<PREC, SEG, CELLS>,
+    const hipError_t e = hipFuncSetAttribute((const void *)k_resident<PREC, SEG, CELLS, NT>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)resident_lds_bytes(kMaxCells, true));
     if (e != hipSuccess) return e;
     limit_set = true;
   }
-  hipLaunchKernelGGL((k_resident<PREC, SEG, CELLS>), dim3(1), dim3(kSolveThreads), lds, st, a, sa, chunk_begin,
+  hipLaunchKernelGGL((k_resident<PREC, SEG, CELLS, NT>), dim3(1), dim3(NT), lds, st, a, sa, chunk_begin,
                      n_chunks, n_steps);
   return hipGetLastError();
 }
