@@ -37,6 +37,12 @@ CASES = [
     # the largest mesh (16 cells per solve thread) and the smallest (one cell)
     ("cells4096", lambda: I.random_sheets(5, 3, [700, 640, 690], 4096, L=3.0, dt=0.02, jitter=0.3,
                                           vscale=0.2)),
+    # the widest workgroup's largest mesh (1024 cells: 8 wavefronts) and one
+    # cell more (the 4-wavefront kernel with 16 cells per solve thread)
+    ("cells1024", lambda: I.random_sheets(8, 4, [512, 300, 450, 700], 1024, L=2.0, dt=0.03, jitter=0.4,
+                                          vscale=0.3)),
+    ("cells1025", lambda: I.random_sheets(9, 4, [512, 300, 450, 700], 1025, L=2.0, dt=0.03, jitter=0.4,
+                                          vscale=0.3)),
     ("cells1", lambda: I.random_sheets(6, 2, [129, 64], 1, L=1.5, dt=0.05, jitter=0.8, closed=[1, 0])),
 ]
 
