@@ -160,3 +160,37 @@ def test_large_job_single_step():
     xs_h = xs.cpu().numpy()
     assert np.max(periodic_diff(xs_h[idx], ref["x"][idx], p.L)) < 1e-12 * p.L
     assert rel_inf(d["E"], ref["E"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(B.SIC_FP64, 1e-10), (B.SIC_SPLIT_U32, 1e-8)])
+def test_standalone_deposit_full_size(prec, tol):
+    """The standalone deposit the benchmark times, at its size and default
+    launch shape: one Landau simulation of 8192 sheets x 16384 tracers on
+    1024 cells.  All sheets of this set-up share one line of positions (they
+    differ in velocity and charge), so by the linearity of the deposit the
+    exact result is the deposit of that line carrying the sheets' total
+    charge, which the oracle computes.  The split form holds the positions
+    to 2^-32 of a cell, hence its looser bound."""
+    import torch
+
+    p = I.landau(n_sheets=8192, n_tracers=16384, n_cells=1024, n_steps=1)
+    print(f"case standalone deposit {p.total_tracers} tracers prec={prec}", flush=True)
+    line = np.asarray(p.line, np.float64)
+    assert np.all(p.closed == 1) and np.all(p.n_tracers == len(line))
+    q_tot = float(np.sum(p.q))
+    Q, ms = O.deposit(p.L, p.n_cells, np.array([len(line)], np.int32), np.array([q_tot]), np.array([1], np.int32),
+                      line)
+    dx = p.L / p.n_cells
+    rho_o = Q / dx - Q.sum() / p.L
+    x0 = torch.from_numpy(line).cuda().repeat(p.n_sheets)
+    v0 = torch.from_numpy(p.sheet_v).cuda().repeat_interleave(int(p.n_tracers[0]))
+    with B.Simulation(p, precision=prec, history_rows=8, x0=x0, v0=v0) as s:
+        del x0, v0
+        s.deposit()
+        s.solve()
+        d = s.diagnostics(history=False)
+    assert rel_inf(d["rho"], rho_o, scale=max(1.0, np.max(np.abs(rho_o)))) < tol
+    # split: each sheet's charge is held in fixed point
+    assert abs(d["last"]["total_charge"] - q_tot * len(line)) <= (1e-12 if prec == B.SIC_FP64 else 1e-9) * abs(
+        q_tot * len(line))
+    assert abs(d["last"]["max_segment"] - ms) <= (1e-13 if prec == B.SIC_FP64 else 1e-8) * p.L
