@@ -104,15 +104,20 @@ def test_two_stream_resynchronised_steps_through_the_run(prec, tol):
             assert np.max(periodic_diff(xg, one["x"], p.L)) < pos_tol, step
 
 
-@pytest.mark.parametrize("order", [0, 1, 2])
-def test_mixed_batch_sampled_instances(order):
+@pytest.mark.parametrize("order,seg,prec,tol", [(0, False, B.SIC_FP64, 1e-10), (1, False, B.SIC_FP64, 1e-10),
+                                                (2, False, B.SIC_FP64, 1e-10), (0, True, B.SIC_FP64, 1e-10),
+                                                (0, False, B.SIC_SPLIT_U32, 1e-6)],
+                         ids=["order0", "order1", "order2", "seg", "split_u32"])
+def test_mixed_batch_sampled_instances(order, seg, prec, tol):
     """All 4096 instances resident and stepped together (default launch shape
-    of the benchmark, and of its --deposit-order 1 and 2 runs); a sample of
-    them is compared with the oracle run alone."""
+    of the benchmark, and of its --deposit-order 1 / 2, --segment-charges and
+    --precision split_u32 runs); a sample of them is compared with the FP64
+    oracle run alone."""
     specs = I.batch_mix(4096)
     total = sum(s.tracers for s in specs)
-    print(f"case mixed batch order={order}", flush=True)
-    b = B.sic_batch_create(total, len(specs), 1024, history_rows=64, deposit_order=order)
+    print(f"case mixed batch order={order} seg={seg} prec={prec}", flush=True)
+    b = B.sic_batch_create(total, len(specs), 1024, precision=prec, history_rows=64, deposit_order=order,
+                           flags=B.SIC_BATCH_SEGMENT_CHARGES if seg else 0)
     import torch
 
     try:
@@ -120,8 +125,9 @@ def test_mixed_batch_sampled_instances(order):
             p = s.build()
             x0 = torch.from_numpy(p.line).cuda().repeat(p.n_sheets)
             v0 = torch.from_numpy(p.sheet_v).cuda().repeat_interleave(int(p.n_tracers[0]))
+            c0 = torch.from_numpy(p.seg_charges).cuda() if seg else None
             B.sic_batch_admit(b, p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x0, v0, p.n_steps,
-                              deposit_order=order)
+                              precision=prec, deposit_order=order, seg_charges=c0)
         steps = 6
         B.sic_batch_step(b, steps)
         work = np.array([s.tracers for s in specs])
@@ -130,14 +136,17 @@ def test_mixed_batch_sampled_instances(order):
         sample = list(rng.choice(small, size=6, replace=False)) + [int(np.argmax(work))]
         for i in sample:
             p = specs[i].build()
-            ref = O.run_problem(p, steps, order=order)
+            if seg:
+                ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, steps)
+            else:
+                ref = O.run_problem(p, steps, order=order)
             r = B.sic_batch_result(b, int(i), p.n_cells)
             h = r["history"]
             assert h["step"][-1] == steps
             err = np.max(np.abs(h["W_E"] - ref["hist"][:, 2]) / np.max(ref["hist"][:, 2]))
-            assert err < 1e-10, (i, err)
+            assert err < tol, (i, err)
             if order != 2:
-                assert rel_inf(r["E"], ref["E"]) < 1e-10
+                assert rel_inf(r["E"], ref["E"]) < tol
             else:
                 # W_1 weighting: the oracle's trapezoid pieces carry position
                 # rounding into its charge; Gauss's law carries a charge
