@@ -1,0 +1,123 @@
+"""Pins of the FP64 CPU oracle against values the paper prints, kept as text
+fixtures under ``tests/golden/`` with their citations.
+
+The two-stream fixture holds what section 3.2 states about the cold
+two-stream dispersion relation (the instability threshold in k v0 and the
+largest growth rate) and the set-up of the section 2.6 experiment.  The
+oracle must reproduce the stated rate on that set-up, grow at the dispersion
+relation's root below the threshold and not grow above it.  Beams carry half
+the unit mean density each, so w_b = sqrt(1/2).
+"""
+import math
+from pathlib import Path
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_1506_07207_amd import inputs as I
+
+GOLDEN = Path(__file__).parent / "golden"
+WB = math.sqrt(0.5)
+
+
+def load_golden(name):
+    """``key = value  # citation`` lines; '#' starts a comment."""
+    out = {}
+    for line in (GOLDEN / name).read_text().splitlines():
+        body = line.split("#", 1)[0].strip()
+        if body:
+            key, val = (s.strip() for s in body.split("=", 1))
+            out[key] = float(val)
+    return out
+
+
+TS = load_golden("two_stream_section_3_2.txt")
+
+
+def unstable_rate(kv0, wb=WB):
+    """Growth rate of the unstable branch of the cold two-beam dielectric
+    function: eps = 0 is a quadratic in w^2 with roots
+    w^2 = (k v0)^2 + wb^2 -+ wb sqrt(wb^2 + 4 (k v0)^2); the minus root is
+    negative, i.e. w is imaginary, below the threshold."""
+    w2 = kv0 ** 2 + wb ** 2 - wb * math.sqrt(wb ** 2 + 4.0 * kv0 ** 2)
+    return math.sqrt(-w2) if w2 < 0.0 else 0.0
+
+
+def growth_fit(hist, t0, t1):
+    t, W = hist[:, 1], hist[:, 2]
+    sel = (t >= t0) & (t <= t1)
+    return np.polyfit(t[sel], np.log(W[sel]), 1)[0] / 2
+
+
+def test_fixture_is_the_dispersion_relation():
+    """The fixture's threshold and peak rate against the quartic itself
+    (numpy's polynomial roots of eps = 0, cleared of denominators): the
+    largest imaginary part over k v0 is max_growth_over_wb * w_b, and no root
+    has one at or above the threshold."""
+
+    def max_im(a):
+        # (w^2 - a^2)^2 = wb^2 ((w + a)^2 + (w - a)^2) = 2 wb^2 (w^2 + a^2)
+        c = [1.0, 0.0, -2.0 * a * a - 2.0 * WB ** 2, 0.0, a ** 4 - 2.0 * WB ** 2 * a * a]
+        return float(np.max(np.roots(c).imag))
+
+    grid = np.linspace(0.01, 1.5, 1491) * WB
+    ims = np.array([max_im(a) for a in grid])
+    assert abs(ims.max() / WB - TS["max_growth_over_wb"]) < 1e-6
+    thr = TS["unstable_below_kv0_over_wb"] * WB
+    assert np.all(ims[grid >= thr * (1 + 1e-9)] < 1e-7)
+    assert np.all(ims[grid <= thr * (1 - 1e-3)] > 0.0)
+    for a in (0.3, 0.6, 0.9, 1.2):
+        assert abs(max_im(a * WB) - unstable_rate(a * WB)) < 1e-9
+
+
+def test_generator_builds_the_section_2_6_set_up():
+    p = I.refinement_two_stream()
+    dx = p.L / p.n_cells
+    assert p.n_cells == TS["n_cells"]
+    assert p.dt == TS["dt"]
+    assert list(p.n_tracers) == [TS["tracers_per_cell_per_stream"] * TS["n_cells"]] * 2
+    # displacement from the Lagrangian grid, largest at the fundamental's crest
+    n = int(p.n_tracers[0])
+    q = np.arange(n) * (p.L / n)
+    d = p.x0[:n] - q
+    d -= p.L * np.round(d / p.L)
+    assert abs(np.max(np.abs(d)) / dx - TS["displacement_over_dx"]) < 1e-4
+    # beams at +-v0 with v0 at the fastest growth of the fundamental
+    kv0 = p.meta["k"] * p.meta["v0"]
+    assert abs(unstable_rate(kv0) / WB - TS["max_growth_over_wb"]) < 1e-12
+
+
+def test_section_2_6_set_up_grows_at_half_the_beam_frequency():
+    """The paper's own run, no refinement: between t = 12 and 19 the growing
+    mode dominates the beams' oscillating modes (excited by the pure
+    displacement) and is still linear (W_E under 5 % of saturation); its rate
+    is w_b / 2 to 3 %, the spread of the fit over nearby windows."""
+    p = I.refinement_two_stream(n_steps=250)
+    h = O.run_problem(p)["hist"]
+    assert h[h[:, 1] <= 19.0, 2].max() < 0.05 * h[:, 2].max()
+    gamma = growth_fit(h, 12.0, 19.0)
+    assert abs(gamma / (TS["max_growth_over_wb"] * WB) - 1.0) < 0.03, gamma
+
+
+def test_instability_threshold():
+    """Just below the threshold (0.9 of it) the perturbation grows at the
+    dispersion relation's root; just above (1.1 of it) every mode is real, so
+    the field energy keeps the scale of its initial value over 40 time units
+    (a growing mode, even at a tenth of the rate below, would multiply it
+    several times over)."""
+    thr = TS["unstable_below_kv0_over_wb"] * WB
+    k = 0.5
+    for f in (0.9, 1.1):
+        kv0 = f * thr
+        p = I.cold_two_stream(k=k, v0=kv0 / k, alpha=1e-6, n_tracers=1024, n_cells=128, dt=0.05, n_steps=800)
+        h = O.run_problem(p)["hist"]
+        W = h[:, 2]
+        if f < 1.0:
+            expect = unstable_rate(kv0)
+            assert expect > 0.2
+            assert abs(growth_fit(h, 15.0, 38.0) / expect - 1.0) < 0.02
+            assert W[-1] > 1e5 * W[0]
+        else:
+            assert unstable_rate(kv0) == 0.0
+            assert W.max() < 2.0 * W[0]
+            assert W[h[:, 1] > 20.0].max() > 0.5 * W[0]  # it oscillates, it is not frozen
