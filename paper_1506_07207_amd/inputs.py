@@ -272,6 +272,38 @@ def refinement_two_stream(ppc: int = 10, n_cells: int = 100, k: float = 0.5, dt:
                             np.array([0.5, 0.5]), dict(k=k, v0=v0, ppc=ppc))
 
 
+def convergence_landau(n_tracers: int, n_cells: int, n_streams: int = 20, vmax_units: float = 4.0,
+                       vth: float = 1.0, vth_over_vph: float = 0.6, v1_over_vth: float = 0.026,
+                       gold_cells: int = 1200, periods: float = 1.0) -> Problem:
+    """The warm-plasma set-up of the convergence study (paper section 3.3):
+    ``n_streams`` horizontal sheets spread evenly over +-vmax_units vth with
+    Maxwellian weights, ``n_tracers`` evenly spaced tracers each, velocities
+    perturbed by v1 sin(k x) at the box's fundamental mode.  The box makes
+    vth / (L / T_p) = vth_over_vph with T_p = 2 pi (omega_p = 1); the step is
+    dx / vth for the cell size of a ``gold_cells``-cell run, the same for every
+    run; the run lasts ``periods`` plasma periods."""
+    L = 2.0 * math.pi * vth / vth_over_vph
+    k = 2.0 * math.pi / L
+    v, w = maxwellian_sheets(n_streams, vth, vmax_units)
+    q = lagrangian_grid(n_tracers, L)
+    v1 = v1_over_vth * vth
+    dt = (L / gold_cells) / vth
+    n_steps = int(round(periods * 2.0 * math.pi / dt))
+    return Problem(
+        name="convergence_landau",
+        L=float(L),
+        n_cells=int(n_cells),
+        dt=float(dt),
+        n_steps=n_steps,
+        n_tracers=np.full(n_streams, n_tracers, dtype=np.int32),
+        q=w * (L / n_tracers),
+        closed=np.ones(n_streams, dtype=np.int32),
+        x_full=np.tile(q, n_streams),
+        v_full=np.concatenate([vm + v1 * np.sin(k * q) for vm in v]),
+        meta=dict(k=k, v1=v1, vth=vth),
+    )
+
+
 def uniform_sheet(n_tracers: int, n_cells: int, L: float, v: float = 0.0, shift: float = 0.0,
                   dt: float = 0.1, n_steps: int = 10) -> Problem:
     """A single unperturbed sheet x_t = shift + t L / N_t (wrapped into [0, L))."""

@@ -121,3 +121,41 @@ def test_instability_threshold():
             assert unstable_rate(kv0) == 0.0
             assert W.max() < 2.0 * W[0]
             assert W[h[:, 1] > 20.0].max() > 0.5 * W[0]  # it oscillates, it is not frozen
+
+
+CV = load_golden("convergence_section_3_3.txt")
+
+
+def _epot(p, order):
+    return O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, p.n_steps, order=order)["hist"][:, 2]
+
+
+def test_generator_builds_the_section_3_3_set_up():
+    p = I.convergence_landau(64, 128)
+    vth = p.meta["vth"]
+    assert p.n_sheets == CV["n_streams"]
+    # streams at the midpoints of n_streams equal intervals of +-vmax (the
+    # sin perturbation averages out over the evenly spaced tracers)
+    m = int(CV["n_streams"])
+    mid = (-1.0 + (np.arange(m) + 0.5) * (2.0 / m)) * CV["vmax_over_vth"] * vth
+    assert np.max(np.abs(p.v0.reshape(m, -1).mean(axis=1) - mid)) < 1e-12
+    assert abs(vth / (p.L / (2 * math.pi)) - CV["vth_over_vph"]) < 1e-12
+    assert abs(p.meta["v1"] / vth - CV["v1_over_vth"]) < 1e-15
+    assert abs(p.dt - (p.L / CV["gold_n_cells"]) / vth) < 1e-15
+    assert abs(np.sum(p.q * p.n_tracers) - p.L) < 1e-12 * p.L  # mean density 1
+
+
+def test_potential_energy_error_falls_at_twice_the_order():
+    """Section 3.3's convergence study: the error of E_pot(t) over one plasma
+    period falls with the tracer count at twice the order of the field, -2 for
+    constant and -4 for linear segments, while the tracer spacing dominates
+    (here 16-64 tracers per stream on 128 cells).  The gold run is the oracle
+    itself with 4096 tracers per stream on the same mesh, so that the mesh's
+    own error, common to all runs, drops out of the difference."""
+    Ns = np.array([16, 32, 64])
+    for order, key, tol in ((0, "epot_slope_constant", 0.15), (1, "epot_slope_linear", 0.25)):
+        gold = _epot(I.convergence_landau(4096, 128), order)
+        errs = [np.mean(np.abs(_epot(I.convergence_landau(int(N), 128), order) - gold)) for N in Ns]
+        slopes = np.diff(np.log(errs)) / np.diff(np.log(Ns))
+        assert np.all(np.abs(slopes - CV[key]) < tol), (order, slopes)
+        assert CV[key] == 2 * CV["field_order_constant" if order == 0 else "field_order_linear"]

@@ -9,6 +9,9 @@ from oracle import oracle as O
 from paper_1506_07207_amd import inputs as I
 from tests.exact_deposit import exact_deposit, exact_deposit_linear
 from tests.test_oracle_pins import _dyadic_sheets
+from tests.test_oracle_golden import load_golden
+
+CV = load_golden("convergence_section_3_3.txt")
 
 EPS = np.finfo(np.float64).eps
 
@@ -120,12 +123,12 @@ def _sheet_density_error(N, nc, order, alpha=0.3, k=0.5):
 def test_linear_segments_converge_one_order_faster():
     """Density error against the exact cell averages, with fewer tracers
     than cells: first order for constant segments, second for linear ones
-    (section 3.3, convergence study)."""
+    (section 3.3, convergence study; the orders from the golden fixture)."""
     Ns = np.array([16, 32, 64, 128])
     e0 = np.array([_sheet_density_error(N, 512, 0) for N in Ns])
     e1 = np.array([_sheet_density_error(N, 512, 1) for N in Ns])
     s0 = np.polyfit(np.log(Ns), np.log(e0), 1)[0]
     s1 = np.polyfit(np.log(Ns), np.log(e1), 1)[0]
-    assert -1.3 < s0 < -0.7, s0
-    assert s1 < -1.7, s1
+    assert abs(s0 - CV["field_order_constant"]) < 0.3, s0
+    assert s1 < CV["field_order_linear"] + 0.3, s1
     assert np.all(e1 < e0)
