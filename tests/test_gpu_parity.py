@@ -127,6 +127,27 @@ def test_cold_oscillation_full_run_fp64():
     assert rel_inf(d["E"], ref["E"]) < TOL
 
 
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("n", [16, 64])
+def test_convergence_set_up_full_run(order, n):
+    """The warm plasma of section 3.3's convergence study (20 streams, velocity
+    perturbation, one plasma period), at tracer counts of its spacing-dominated
+    regime, constant and linear segments."""
+    p = I.convergence_landau(n, 128)
+    print(f"case convergence set-up n={n} order={order}, {p.n_steps} steps", flush=True)
+    ref = O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, p.v0, p.n_steps, order=order)
+    with B.Simulation(p, deposit_order=order) as s:
+        s.step(p.n_steps)
+        x, v, step = s.state()
+        d = s.diagnostics()
+    assert step == p.n_steps
+    h = d["history"]
+    assert envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt) < TOL
+    assert np.max(periodic_diff(x, ref["x"], p.L)) < 1e-10 * p.L
+    assert np.max(np.abs(v - ref["v"])) < 1e-10
+    assert rel_inf(d["E"], ref["E"]) < TOL
+
+
 def test_landau_full_run_fp64():
     p = I.landau()
     print("case landau 256x512 cells 256, 1000 steps", flush=True)
