@@ -86,6 +86,24 @@ def _dyadic_sheets(rng, n_sheets, L, den=64):
     return sheets
 
 
+def test_wrap_lands_in_the_box_at_the_nearest_point():
+    """Every position wraps into [0, L) and lands on the representable point
+    nearest to it on the circle (exact rationals): x - L is exact on [L, 2L),
+    and a tiny negative x, whose x + L rounds up to L, is the point 0."""
+    for L in (1.0, 4.0 * math.pi, 0.1):
+        ulp = np.spacing(L)
+        xs = [0.0, -1e-300, -2.0 ** -60 * L, -L, -L + ulp, -0.5 * L, L - ulp, L, L + ulp, 2.0 * L - 2 * ulp,
+              2.0 * L, 7.3 * L, -5.1 * L, 1e6 * L + 0.3]
+        for x in xs:
+            r = O.wrap(x, L)
+            assert 0.0 <= r < L, (x, L, r)
+            d = (Fraction(r) - Fraction(x)) % Fraction(L)
+            d = min(d, Fraction(L) - d)  # distance on the circle
+            assert d <= Fraction(np.spacing(max(abs(x), L))), (x, L, r)
+    assert O.wrap(-1e-300, 1.0) == 0.0
+    assert O.wrap(1.0, 1.0) == 0.0 and O.wrap(-1.0, 1.0) == 0.0
+
+
 @pytest.mark.parametrize("nc", [1, 2, 3, 4, 8, 13])
 def test_deposit_matches_exact_rational(nc):
     """Overlap deposit (eqs. overlap/rho_sum) equals exact rational brute force."""

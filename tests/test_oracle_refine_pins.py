@@ -117,6 +117,13 @@ def test_refinement_splits_long_segments_at_their_centre():
     nt3, x3, _, _, added = O.refine(L, 0.3, [2], [0], np.array([0.875, 0.25]), np.array([0.0, 1.0]),
                                     np.array([1.0, 0.0]))
     assert added == 1 and list(x3) == [0.875, 0.0625, 0.25]
+    # "longer than" is strict: a segment of exactly l_max (dyadic, so the
+    # length is exact) stays whole, one a rounding unit longer is split
+    seg = np.array([0.25, 0.5])
+    _, xt, _, _, added = O.refine(L, 0.25, [2], [0], seg, np.zeros(2), np.array([1.0, 0.0]))
+    assert added == 0 and list(xt) == [0.25, 0.5]
+    _, xt, _, _, added = O.refine(L, np.nextafter(0.25, 0.0), [2], [0], seg, np.zeros(2), np.array([1.0, 0.0]))
+    assert added == 1 and list(xt) == [0.25, 0.375, 0.5]
 
 
 @pytest.mark.parametrize("order", [0, 2])
