@@ -27,7 +27,7 @@ def _ulp_sensitivity(p, Q, trials=4):
     return worst
 
 
-@pytest.mark.parametrize("nc", [3, 16, 100, 1024])
+@pytest.mark.parametrize("nc", [1, 2, 3, 16, 100, 1024, 4096])
 def test_linear_deposit_matches_oracle_ragged(nc):
     closed = [1, 1, 0, 1, 0, 1, 1, 0, 1, 1, 0, 1]
     p = I.random_sheets(40 + nc, len(RAGGED), RAGGED, nc, L=2.9, jitter=0.7, closed=closed)

@@ -26,7 +26,7 @@ def _random_charges(p, seed):
 
 
 @pytest.mark.parametrize("order", [0, 1, 2])
-@pytest.mark.parametrize("nc", [1, 16, 100, 1024])
+@pytest.mark.parametrize("nc", [1, 2, 16, 100, 1024, 4096])
 def test_segment_charge_deposit_matches_oracle(order, nc):
     p = I.random_sheets(300 + nc, len(RAGGED), RAGGED, nc, L=1.9, jitter=0.5, closed=CLOSED)
     c = _random_charges(p, nc)
