@@ -123,13 +123,23 @@ static void add_interval(double lo, double hi, double w, double L, int nc, doubl
     }
 }
 
+/* Running maximum of segment lengths; a NaN length (a segment with a
+ * non-finite end) makes the result NaN for good, so it reaches the flags. */
+static double longest(double m, double len)
+{
+    if (isnan(m) || isnan(len)) return NAN;
+    return len > m ? len : m;
+}
+
 /* Deposit one segment from tracer position a to tracer position b (both in
  * [0, L)) carrying charge q: the box function of height 1/length is
  * integrated over every cell it overlaps (eqs. "overlap" and "rho_sum",
- * multiplied by the cell volume).  Returns the segment length. */
+ * multiplied by the cell volume).  Returns the segment length (NaN, with
+ * nothing deposited, when an end is not a finite position). */
 double orc_deposit_segment(double a, double b, double q, double L, int nc, double *Q)
 {
     double d = orc_min_image(a, b, L);
+    if (!isfinite(d)) return NAN; /* a non-finite end: nothing deposited, length NaN */
     if (d == 0.0) {
         Q[orc_point_cell(a, L, nc)] += q;
         return 0.0;
@@ -170,7 +180,7 @@ void orc_deposit_c(double L, int nc, int n_sheets, const int32_t *n_tracers, con
         for (int t = 0; t < nseg; ++t) {
             int u = (t + 1 == nt) ? 0 : t + 1;
             double len = orc_deposit_segment(x[base + t], x[base + u], c[base + t], L, nc, Q);
-            if (len > maxseg) maxseg = len;
+            maxseg = longest(maxseg, len);
         }
         base += nt;
     }
@@ -238,9 +248,10 @@ void orc_deposit_linear_c(double L, int nc, int n_sheets, const int32_t *n_trace
             d[t] = orc_min_image(a[t], x[base + u], L);
             c[t] = a[t] + 0.5 * d[t];
             r0[t] = d[t] != 0.0 ? cq[base + t] / fabs(d[t]) : 0.0;
-            if (fabs(d[t]) > maxseg) maxseg = fabs(d[t]);
+            maxseg = longest(maxseg, fabs(d[t]));
         }
         for (int t = 0; t < nseg; ++t) {
+            if (!isfinite(d[t])) continue; /* a non-finite end: nothing deposited */
             if (d[t] == 0.0) {
                 Q[orc_point_cell(a[t], L, nc)] += cq[base + t];
                 continue;
@@ -290,10 +301,16 @@ void orc_deposit_linear(double L, int nc, int n_sheets, const int32_t *n_tracers
  * segment's box function is assigned to the grid points X_j = (j + 1/2) dx
  * with the first-order weight W_1(x - X_j) = max(0, 1 - |x - X_j| / dx), so
  * grid point j receives h * integral over the segment of W_1(x - X_j) dx,
- * h = q / length.  The hat is linear between its kinks X_j - dx, X_j,
- * X_j + dx, so the integral is taken piece by piece with the trapezoid rule,
- * which is exact for linear integrands.  A zero-length segment is a point
- * charge: W_1 weights of the point.  The result is the charge per grid point
+ * h = q / length.  Every hat is linear between consecutive grid points, so
+ * the grid points inside the segment cut it into pieces on each of which
+ * only the two grid points X_m, X_{m+1} around it have weight, linear in x;
+ * the integral of a linear function over a piece is its length times its
+ * value at the midpoint.  A piece [p0, p1] therefore gives its charge
+ * h (p1 - p0) to X_m and X_{m+1} in the proportions 1 - t and t, t the
+ * midpoint's distance from X_m in cells.  Consecutive pieces share their
+ * end points, so the pieces of a segment add up to its charge to rounding
+ * however short it is.  A zero-length segment is a point charge: W_1
+ * weights of the point.  The result is the charge per grid point
  * (dx * density), as for the other deposits. */
 static double hat(double x, double X, double dx)
 {
@@ -315,7 +332,8 @@ void orc_deposit_cic_c(double L, int nc, int n_sheets, const int32_t *n_tracers,
             int u = (t + 1 == nt) ? 0 : t + 1;
             double a = x[base + t];
             double d = orc_min_image(a, x[base + u], L);
-            if (fabs(d) > maxseg) maxseg = fabs(d);
+            maxseg = longest(maxseg, fabs(d));
+            if (!isfinite(d)) continue; /* a non-finite end: nothing deposited */
             if (d == 0.0) {
                 long j0 = (long)floor(a / dx - 0.5);
                 for (long j = j0; j <= j0 + 1; ++j)
@@ -324,20 +342,23 @@ void orc_deposit_cic_c(double L, int nc, int n_sheets, const int32_t *n_tracers,
             }
             double lo = d > 0.0 ? a : a + d, hi = d > 0.0 ? a + d : a;
             double h = c[base + t] / (hi - lo);
-            long j0 = (long)floor(lo / dx - 0.5) - 1, j1 = (long)floor(hi / dx - 0.5) + 2;
-            for (long j = j0; j <= j1; ++j) {
-                double X = ((double)j + 0.5) * dx;
-                double knots[5] = {lo, X - dx, X, X + dx, hi};
-                double acc = 0.0;
-                /* pieces between consecutive kinks that lie inside [lo, hi] */
-                double prev = lo;
-                for (int k = 1; k < 5; ++k) {
-                    double nxt = knots[k];
-                    if (k < 4 && (nxt <= lo || nxt >= hi)) continue;
-                    if (nxt > prev) acc += 0.5 * (hat(prev, X, dx) + hat(nxt, X, dx)) * (nxt - prev);
-                    prev = nxt;
+            /* grid interval m is [X_m, X_{m+1}]; start from the one holding lo
+             * (a rounding of lo / dx that lands one interval off only gives an
+             * empty first piece or a first piece reaching a rounding past X_m) */
+            long m = (long)floor(lo / dx - 0.5);
+            double p0 = lo;
+            for (;;) {
+                double Xr = ((double)(m + 1) + 0.5) * dx;
+                double p1 = Xr < hi ? Xr : hi;
+                if (p1 > p0) {
+                    double piece = h * (p1 - p0);
+                    double tm = (0.5 * (p0 + p1) - ((double)m + 0.5) * dx) / dx;
+                    Q[mod_cell(m, nc)] += piece * (1.0 - tm);
+                    Q[mod_cell(m + 1, nc)] += piece * tm;
+                    p0 = p1;
                 }
-                if (acc > 0.0) Q[mod_cell(j, nc)] += h * acc;
+                if (p1 >= hi) break;
+                ++m;
             }
         }
         base += nt;
@@ -418,6 +439,7 @@ void orc_solve(double L, int nc, const double *Q, double *E, double *W_E, double
  * from the two grid points X_j = (j + 1/2) dx around x (periodic). */
 double orc_gather(double L, int nc, const double *E, double x)
 {
+    if (!isfinite(x)) return NAN; /* no mesh point to read */
     double dx = L / nc;
     long j0 = (long)floor(x / dx - 0.5);
     double X0 = ((double)j0 + 0.5) * dx;
@@ -544,13 +566,18 @@ int64_t orc_refine(double L, double l_max, int n_sheets, int32_t *n_tracers, con
     return add;
 }
 
-static double row_flags(double L, int nc, const double *E, double maxseg)
+/* Status flags of one diagnostics row, two independent bits: NONFINITE when
+ * a field value, the longest segment, or the kinetic energy or momentum of
+ * the move into this step is not finite (moved_finite = 0); LONG_SEGMENT
+ * when the longest segment is finite and longer than 0.45 L (segments join
+ * tracers the shorter way round, so none can exceed L/2). */
+static double row_flags(double L, int nc, const double *E, double maxseg, int moved_finite)
 {
-    double f = 0.0;
+    int nonfinite = !moved_finite || !isfinite(maxseg);
     for (int j = 0; j < nc; ++j)
-        if (!isfinite(E[j])) { f += ORC_FLAG_NONFINITE; break; }
-    if (!isfinite(maxseg)) { if (f == 0.0) f += ORC_FLAG_NONFINITE; }
-    else if (maxseg > 0.45 * L) f += ORC_FLAG_LONG_SEGMENT;
+        if (!isfinite(E[j])) nonfinite = 1;
+    double f = nonfinite ? ORC_FLAG_NONFINITE : 0.0;
+    if (isfinite(maxseg) && maxseg > 0.45 * L) f += ORC_FLAG_LONG_SEGMENT;
     return f;
 }
 
@@ -598,7 +625,7 @@ int orc_run_seg(int order, double L, int nc, double dt, int n_sheets, int32_t *n
     }
     double *row = hist;
     row[0] = (double)step0; row[1] = (double)step0 * dt; row[2] = W; row[3] = NAN; row[4] = NAN;
-    row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
+    row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms, 1);
     if (count_out) count_out[0] = n;
     for (int64_t it = 0; it < n_steps; ++it) {
         double ke, mom;
@@ -614,7 +641,8 @@ int orc_run_seg(int order, double L, int nc, double dt, int n_sheets, int32_t *n
         orc_solve(L, nc, Q, E, &W, &qt);
         row = hist + (it + 1) * ORC_ROW;
         row[0] = (double)(step0 + it + 1); row[1] = (double)(step0 + it + 1) * dt; row[2] = W;
-        row[3] = NAN; row[4] = NAN; row[5] = qt; row[6] = ms; row[7] = row_flags(L, nc, E, ms);
+        row[3] = NAN; row[4] = NAN; row[5] = qt; row[6] = ms;
+        row[7] = row_flags(L, nc, E, ms, isfinite(ke) && isfinite(mom));
         if (count_out) count_out[it + 1] = n;
     }
     if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);

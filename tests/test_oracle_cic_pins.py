@@ -61,3 +61,25 @@ def test_short_segment_tends_to_the_cic_point_weights():
             expect[j0 % nc] += 1 - s
             expect[(j0 + 1) % nc] += s
             assert np.max(np.abs(Q - expect)) < 10 * (eps / dx) ** 2 + 1e-12
+
+
+@pytest.mark.parametrize("nc", [1024, 4096])
+def test_cic_deposit_conserves_charge_on_fine_meshes(nc):
+    """The hats sum to one at every point, so the W_1 deposit of a segment is
+    exactly its charge.  Short jittered segments on a fine mesh (lengths down
+    to a small fraction of a cell, folds) keep the total to rounding."""
+    ragged = [2, 3, 4, 63, 64, 65, 127, 128, 129, 300]
+    closed = [1, 1, 0, 1, 0, 1, 1, 0, 1, 1]
+    p = I.random_sheets(70 + nc, len(ragged), ragged, nc, L=2.3, jitter=0.8, closed=closed)
+    Q, _ = O.deposit(p.L, nc, p.n_tracers, p.q, p.closed, p.x0, order=2)
+    nseg = np.where(np.asarray(p.closed) == 1, p.n_tracers, np.asarray(p.n_tracers) - 1)
+    exact = float(np.sum(np.asarray(p.q) * nseg))
+    assert abs(Q.sum() - exact) < 1e-14 * exact
+    # and segment by segment: a single short segment anywhere on the mesh
+    rng = np.random.default_rng(nc)
+    dx = p.L / nc
+    for _ in range(200):
+        a = rng.uniform(0, p.L)
+        b = (a + rng.choice([-1.0, 1.0]) * dx * 10.0 ** rng.uniform(-9, 0.5)) % p.L
+        Q, _ = O.deposit(p.L, nc, [2], [1.0], [0], np.array([a, b]), order=2)
+        assert abs(Q.sum() - 1.0) < 4 * EPS and np.all(Q >= -4 * EPS)

@@ -46,9 +46,12 @@ MUTANTS = {
         "if ((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))", "if (dp != dm)"),
     "linear_centroid_at_the_start": ("c[t] = a[t] + 0.5 * d[t];", "c[t] = a[t];"),
     # first-order weighting (section 2.4)
-    "cic_left_riemann_sum": (
-        "acc += 0.5 * (hat(prev, X, dx) + hat(nxt, X, dx)) * (nxt - prev);", "acc += hat(prev, X, dx) * (nxt - prev);"),
-    "cic_grid_points_on_faces": ("double X = ((double)j + 0.5) * dx;", "double X = (double)j * dx;"),
+    "cic_piece_value_at_its_left_end": (
+        "double tm = (0.5 * (p0 + p1) - ((double)m + 0.5) * dx) / dx;",
+        "double tm = (p0 - ((double)m + 0.5) * dx) / dx;"),
+    "cic_pieces_cut_at_faces": ("double Xr = ((double)(m + 1) + 0.5) * dx;", "double Xr = (double)(m + 1) * dx;"),
+    "cic_piece_weights_transposed": (
+        "Q[mod_cell(m, nc)] += piece * (1.0 - tm);", "Q[mod_cell(m, nc)] += piece * tm;"),
     # refinement (section 2.6)
     "refined_tracer_off_centre": (
         "nx[out] = orc_wrap(x[base + t] + 0.5 * d, L);", "nx[out] = orc_wrap(x[base + t] + 0.25 * d, L);"),
@@ -57,6 +60,11 @@ MUTANTS = {
     # '>= l_max' in both passes: for representable lengths, '> prev(l_max)'
     "refinement_at_equal_length": (
         "int64_t n = 0, add = 0;", "int64_t n = 0, add = 0; l_max = nextafter(l_max, 0.0);"),
+    # diagnostics flags
+    "flags_ignore_the_move": (
+        "row[7] = row_flags(L, nc, E, ms, isfinite(ke) && isfinite(mom));", "row[7] = row_flags(L, nc, E, ms, 1);"),
+    "long_segment_flag_dropped": (
+        "if (isfinite(maxseg) && maxseg > 0.45 * L) f += ORC_FLAG_LONG_SEGMENT;", "(void)0;"),
     # periodic wrap
     "wrap_leaves_a_rounded_up_L": ("return (y >= L) ? 0.0 : y;", "return y;"),
 }

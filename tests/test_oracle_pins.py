@@ -367,3 +367,29 @@ def test_warm_two_stream_growth_rate():
     sel = (t >= 16) & (t <= 30)
     gamma = np.polyfit(t[sel], np.log(W[sel]), 1)[0] / 2
     assert abs(gamma / root.imag - 1.0) < 0.02, gamma
+
+
+def test_nonfinite_state_flags():
+    """A non-finite velocity makes the tracer's position non-finite after the
+    next move: its two segments deposit nothing, the longest segment and the
+    kinetic energy are NaN, and every row from then on has the NONFINITE bit.
+    A velocity so large that its kinetic energy overflows, with every
+    position still finite, sets the bit through the kinetic energy alone."""
+    p = I.landau(n_sheets=4, n_tracers=32, n_cells=16, n_steps=3)
+    v0 = np.array(p.v0)
+    v0[5] = np.nan
+    r = O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, v0, 3)
+    h = r["hist"]
+    assert h[0, 7] == 0 and np.isfinite(h[0, 2])
+    assert np.all(h[1:, 7] == 1)
+    assert np.all(np.isnan(h[1:, 6])) and np.all(np.isfinite(h[1:, 2]))
+    assert np.isnan(h[0, 3])  # the move from step 0 had a NaN velocity
+    # the two segments of tracer 5 (sheet 0) carry no charge after the move
+    assert abs(h[1, 5] - (h[0, 5] - 2 * p.q[0])) < 1e-12 * h[0, 5]
+    v0 = np.array(p.v0)
+    v0[7] = 1e300
+    r = O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, p.x0, v0, 2)
+    h = r["hist"]
+    assert np.all(np.isfinite(r["x"]))
+    assert h[0, 7] == 0 and np.isinf(h[0, 3])
+    assert np.all(h[1:, 7].astype(int) & 1)
