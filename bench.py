@@ -61,8 +61,12 @@ def profiled_traffic(precision, instances):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed steps first: by default the timed window starts past the two-stream "
+                         "instances' saturation, where the sheets have folded")
+    ap.add_argument("--early-steps", type=int, default=20,
+                    help="also time this many steps right after 5 warm-up steps (0: skip)")
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split_f32", "split_u32"])
     ap.add_argument("--deposit-order", type=int, default=0, choices=[0, 1, 2],
@@ -112,13 +116,19 @@ def build_batch(B, specs, precision, torch, history_rows=256, deposit_order=0, s
     return b, total, cells
 
 
-def time_batched(B, b, steps, warmup, torch):
-    B.sic_batch_step(b, warmup)
+def time_batched(B, b, steps, torch):
+    """Wall time of ``steps`` batch steps, bracketed by device syncs."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     B.sic_batch_step(b, steps)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def updates_in_window(specs, first, last):
+    """Tracer-updates of batch steps first+1 .. last: an instance advances
+    until its own step count is reached and is then masked."""
+    return sum(s.tracers * max(0, min(s.n_steps, last) - min(s.n_steps, first)) for s in specs)
 
 
 def kernel_timing(B, b, steps=5):
@@ -171,10 +181,16 @@ def time_single_configs(B, I, torch):
         ("large served job, FP64 (2048 x 16384 tracers, 4096 cells, 64 steps)",
          I.landau(n_sheets=2048, n_tracers=16384, n_cells=4096, n_steps=64), B.SIC_FP64),
     ]
+    # the oracle's field-energy history of the full two-stream run, stored by
+    # tests/golden/make_two_stream_ensemble.py: the timed split-form runs
+    # report their error against it
+    ref_path = os.path.join(ROOT, "tests", "golden", "two_stream_full_ensemble.txt")
+    ref_w = np.loadtxt(ref_path)[:, 1] if os.path.exists(ref_path) else None
     out = []
     for name, p, prec in cases:
         x0, v0 = device_inputs(p, torch)
-        sim = B.Simulation(p, precision=prec, history_rows=64, x0=x0, v0=v0)
+        with_ref = ref_w is not None and name.startswith("two-stream") and len(ref_w) == p.n_steps + 1
+        sim = B.Simulation(p, precision=prec, history_rows=(p.n_steps + 1) if with_ref else 64, x0=x0, v0=v0)
         del x0, v0
         try:
             x_init, v_init, _ = sim.state()
@@ -187,6 +203,15 @@ def time_single_configs(B, I, torch):
             e1.record()
             e1.synchronize()
             ms = e0.elapsed_time(e1)
+            err = None
+            if with_ref:
+                W = sim.diagnostics()["history"]["W_E"]
+                P = int(math.ceil(2 * math.pi / p.dt))
+                env = np.array([ref_w[max(0, i - P): i + P + 1].max() for i in range(len(ref_w))])
+                e = np.abs(W - ref_w) / env
+                over = np.nonzero(e > 1e-6)[0]
+                err = {"max_envelope_rel": float(e.max()), "first_step_over_1e-6": int(over[0]) if len(over) else None,
+                       "against": "stored oracle history (tests/golden/two_stream_full_ensemble.txt)"}
         finally:
             sim.close()
         n = p.total_tracers
@@ -195,7 +220,7 @@ def time_single_configs(B, I, torch):
         launches = math.ceil(p.n_steps / 8192) / p.n_steps if resident else 2
         out.append({"workload": name, "tracers": n, "cells": p.n_cells, "steps": p.n_steps, "ms": ms,
                     "us_per_step": 1e3 * ms / p.n_steps, "tracer_updates_per_s": n * p.n_steps / (ms * 1e-3),
-                    "kernel_launches_per_step": launches})
+                    "kernel_launches_per_step": launches, "field_energy_error": err})
         log(f"single: {name}: {1e3 * ms / p.n_steps:.1f} us/step, {n * p.n_steps / (ms * 1e-3):.3e} tracer-updates/s")
     torch.cuda.empty_cache()
     return out
@@ -258,6 +283,16 @@ def _oracle_worker(job):
         if t_total >= seconds:
             break
     return done, n, t_total
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def host_cores():
@@ -357,17 +392,43 @@ def main():
     tuning = B.sic_batch_get_tuning(b)
     log(f"resident tracers {total:.3e}, setup {time.time() - t_setup:.1f}s, tuning {tuning}")
 
-    elapsed = time_batched(B, b, args.steps, args.warmup, torch)
+    done = 0
+    early = None
+    if args.early_steps > 0:
+        B.sic_batch_step(b, 5)
+        done = 5
+        el = time_batched(B, b, args.early_steps, torch)
+        upd = updates_in_window(specs, done, done + args.early_steps)
+        early = {"steps": f"{done + 1}-{done + args.early_steps}", "ms_per_step": 1e3 * el / args.early_steps,
+                 "value": upd / el}
+        done += args.early_steps
+        log(f"batched, early window (steps {early['steps']}): {early['ms_per_step']:.3f} ms/step, "
+            f"{early['value']:.4e} tracer-updates/s")
+        e_tr, e_so = kernel_timing(B, b)
+        done += 5
+        early["kernel_ms"], early["solve_ms"] = e_tr, e_so
+    if args.warmup > done:
+        B.sic_batch_step(b, args.warmup - done)
+        done = args.warmup
+    elapsed = time_batched(B, b, args.steps, torch)
     ms_per_step = 1e3 * elapsed / args.steps
-    value = total * args.steps / elapsed
-    log(f"batched: {ms_per_step:.3f} ms/step, {value:.4e} tracer-updates/s")
+    updates = updates_in_window(specs, done, done + args.steps)
+    value = updates / elapsed
+    window = f"{done + 1}-{done + args.steps}"
+    log(f"batched, steps {window}: {ms_per_step:.3f} ms/step, {value:.4e} tracer-updates/s")
+    done += args.steps
 
     tr_ms, so_ms = kernel_timing(B, b)
     # a charge word per tracer is read with per-segment charges; linear
     # segments also read and clear a ramp array per cell
     bytes_tracer = BYTES_PER_TRACER + (8 if args.segment_charges else 0)
     bytes_cell = BYTES_PER_CELL + (8 if args.deposit_order == 1 else 0)
-    bytes_launch = bytes_tracer * total + bytes_cell * cells
+    # per launch, averaged over the five timed launches: the instances still
+    # advancing (finished ones are masked)
+    act_tracers = updates_in_window(specs, done, done + 5) / 5
+    act_cells = sum(s.n_cells * max(0, min(s.n_steps, done + 5) - min(s.n_steps, done)) for s in specs) / 5
+    bytes_launch = bytes_tracer * act_tracers + bytes_cell * act_cells
+    done += 5
     achieved = bytes_launch / (tr_ms * 1e-3) / 1e9
     copy_gbps = B.sic_copy_bandwidth(4 << 30, 5)
     log(f"tracer kernel {tr_ms:.3f} ms ({achieved:.0f} GB/s), solve kernel {so_ms:.3f} ms, copy {copy_gbps:.0f} GB/s")
@@ -399,7 +460,7 @@ def main():
     if not args.no_cpu_baseline:
         cores = args.cpu_cores or host_cores()
         rate, n_inst, secs = cpu_baseline(specs, args.cpu_seconds, cores)
-        cpu = {"value": rate, "unit": "tracer-updates/s", "cores": cores, "kind": "oracle",
+        cpu = {"value": rate, "unit": "tracer-updates/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{n_inst} instances of the same mix dealt to {cores} worker processes (one per core, "
                          f"each the single-threaded FP64 oracle), 2 steps each, {secs:.1f} s of CPU work"}
         log(f"cpu oracle: {rate:.4e} tracer-updates/s")
@@ -419,6 +480,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batched mix of {len(specs)} SIC 1D1V instances (Landau/two-stream, "
                                "32-512 sheets x 64-2048 tracers, 64-1024 cells), one shared step",
+                   "timed_steps": window, "early": early,
                    "instances": len(specs), "tracers": total, "cells": cells, "precision": args.precision,
                    "deposit_order": args.deposit_order, "segment_charges": bool(args.segment_charges),
                    "tuning": tuning, "autotune": tuned},

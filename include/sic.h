@@ -61,17 +61,24 @@ typedef enum sic_status {
 
 /* Position storage.
  *   SIC_FP64:      x in float64; mesh charge accumulated with float64 atomics.
- *   SIC_SPLIT_F32: x as int32 cell index + float32 offset in [0, 1) cell;
- *   SIC_SPLIT_U32: x as int32 cell index + uint32 fraction of a cell.
+ *   SIC_SPLIT_F32: x as an integer cell index + float32 offset: the 32-bit
+ *                  index counts sub-cells of 2^-20 cell (cell = index >> 20)
+ *                  and the float32 offset in [0, 1) places the tracer within
+ *                  its sub-cell, about 2^-44 cell resolution;
+ *   SIC_SPLIT_U32: x as int32 cell index + uint32 fraction of a cell (2^-32
+ *                  cell resolution).
  * Both split forms keep v in float64, deposit into int64 fixed point (bitwise
- * reproducible, order independent) and solve in float64. */
+ * reproducible, order independent) and solve in float64.  A non-finite move
+ * leaves a split position where it was (the velocity stays non-finite and the
+ * diagnostics flag it). */
 typedef enum sic_precision { SIC_FP64 = 0, SIC_SPLIT_F32 = 1, SIC_SPLIT_U32 = 2 } sic_precision;
 
 enum { SIC_MEM_HOST = 0, SIC_MEM_DEVICE = 1 };
 
 /* sic_diag.flags bits (sticky per simulation). */
 enum {
-    SIC_DIAG_NONFINITE = 1,    /* a non-finite field value was produced */
+    SIC_DIAG_NONFINITE = 1,    /* a non-finite field value or segment length, or a move
+                                  with a non-finite kinetic energy or momentum */
     SIC_DIAG_LONG_SEGMENT = 2  /* some segment longer than 0.45 L (segments join
                                   tracers the shorter way round the box, so a
                                   segment cannot be longer than L/2) */
@@ -337,8 +344,9 @@ sic_status sic_set_timing(sic_sim *sim, int32_t timing);
 sic_status sic_last_timing(const sic_sim *sim, double *tracer_ms, double *solve_ms);
 
 /* Device copy bandwidth in GB/s (bytes read + bytes written per second) of a
- * plain streaming copy of n_bytes, best of iters runs, on the given stream.
- * A calibration for the HBM roofline.  Synchronous. */
+ * streaming copy of n_bytes (non-temporal 16-byte loads and stores, four
+ * loads in flight per lane), best of iters runs at each of four grid sizes,
+ * on the given stream.  A calibration for the HBM roofline.  Synchronous. */
 sic_status sic_copy_bandwidth(int64_t n_bytes, int32_t iters, void *hip_stream, double *gbps);
 
 #ifdef __cplusplus

@@ -1903,22 +1903,25 @@ sic_status sic_copy_bandwidth(int64_t n_bytes, int32_t iters, void *hip_stream, 
   hipEventCreate(&e1);
   double best = 0.0;
   sic_status rc = SIC_OK;
-  launch_copy_bench(a, b, n, st);  // warm-up
-  for (int i = 0; i < iters; ++i) {
-    hipEventRecord(e0, st);
-    if (launch_copy_bench(a, b, n, st) != 0) {
-      rc = SIC_EDEVICE;
-      break;
+  // grids of 4 to 32 workgroups of 256 threads per CU (256 CUs)
+  for (int grid : {1024, 2048, 4096, 8192}) {
+    launch_copy_bench(a, b, n, grid, st);  // warm-up
+    for (int i = 0; i < iters && rc == SIC_OK; ++i) {
+      hipEventRecord(e0, st);
+      if (launch_copy_bench(a, b, n, grid, st) != 0) {
+        rc = SIC_EDEVICE;
+        break;
+      }
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = SIC_EDEVICE;
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      const double g = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
+      best = std::max(best, g);
     }
-    hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = SIC_EDEVICE;
-      break;
-    }
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    const double g = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
-    best = std::max(best, g);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

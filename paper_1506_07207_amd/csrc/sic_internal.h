@@ -208,7 +208,8 @@ int launch_ingest(int prec, const IngestArgs &a, void *stream);
 int launch_extract(int prec, const ExtractArgs &a, void *stream);
 int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
                      const int32_t *slot_list, int n_blocks, void *stream);
-int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream);
+// grid: workgroups of 256 threads
+int launch_copy_bench(const double *src, double *dst, int64_t n, int grid, void *stream);
 // Charge edges of chunks [chunk_begin, chunk_begin + n_chunks): prev_slot[c]
 // is the slot of the tracer before chunk c's first one (-1: none).
 int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const uint64_t *segq, uint64_t *cedge,

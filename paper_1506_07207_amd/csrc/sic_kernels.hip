@@ -66,43 +66,66 @@ __device__ __forceinline__ double wrap_into_box(double x, double L) {
   return (x >= L) ? 0.0 : x;
 }
 
-// ---- split position words: cell in the low 32 bits, fraction bits high ----
+// ---- split position words ----
+//
+// U32: the low 32 bits hold the cell, the high 32 bits the fraction of the
+// cell as an unsigned integer in units of 2^-32 cell.
+// F32: the low 32 bits hold an index on a lattice of 2^kSubBits sub-cells
+// per cell (cell = index >> kSubBits), the high 32 bits a float32 offset in
+// [0, 1) of a sub-cell.  With 4096 cells at most the index fits 32 bits; the
+// float's 24-bit significand then resolves about 2^-44 of a cell, the
+// resolution of a float64 position near the top of such a mesh, where a
+// float32 offset spanning a whole cell would only resolve 2^-24 of it.
+constexpr int kSubBits = 20;
+constexpr uint32_t kSubMask = (1u << kSubBits) - 1u;
+
 template <int PREC>
-__device__ __forceinline__ double split_frac(uint32_t bits) {
+__device__ __forceinline__ int split_cell(uint64_t w) {
+  if constexpr (PREC == kSplitF32) return (int)((uint32_t)w >> kSubBits);
+  else return (int)(uint32_t)w;
+}
+
+// Position within the cell, in [0, 1) cell.
+template <int PREC>
+__device__ __forceinline__ double split_frac(uint64_t w) {
   if constexpr (PREC == kSplitF32) {
-    return (double)__uint_as_float(bits);
+    return ((double)((uint32_t)w & kSubMask) + (double)__uint_as_float((uint32_t)(w >> 32))) * 0x1p-20;
   } else {
-    return (double)bits * 2.3283064365386963e-10;  // 2^-32
+    return (double)(uint32_t)(w >> 32) * 0x1p-32;
   }
 }
 
-// Quantises a fraction r in [0, 1] to the offset type; carry = 1 when it
-// rounds up to a whole cell.
+// Word of the point cell + r (r in [0, 1] cell, cell any integer the caller
+// has reduced to -nc .. 2nc - 1): the rounding of r to the offset type may
+// carry into the next cell.
 template <int PREC>
-__device__ __forceinline__ uint32_t split_quantise(double r, int &carry) {
-  carry = 0;
+__device__ __forceinline__ uint64_t split_word(int cell, double r, int nc) {
   if constexpr (PREC == kSplitF32) {
-    float o = (float)r;
+    const double ts = r * 0x1p20;  // sub-cells, exact
+    double sub = floor(ts);
+    float o = (float)(ts - sub);
     if (o >= 1.0f) {
       o = 0.0f;
-      carry = 1;
+      sub += 1.0;
     }
-    return __float_as_uint(o);
+    int c = cell;
+    if (sub >= 0x1p20) {
+      sub -= 0x1p20;
+      c += 1;
+    }
+    c = wrap_cell(c, nc);
+    const uint32_t idx = ((uint32_t)c << kSubBits) | ((uint32_t)sub & kSubMask);
+    return (uint64_t)idx | ((uint64_t)__float_as_uint(o) << 32);
   } else {
-    double s = rint(r * 4294967296.0);
-    if (s >= 4294967296.0) {
-      s = 0.0;
-      carry = 1;
+    double sc = rint(r * 4294967296.0);
+    int c = cell;
+    if (sc >= 4294967296.0) {
+      sc = 0.0;
+      c += 1;
     }
-    return (uint32_t)s;
+    return (uint64_t)(uint32_t)wrap_cell(c, nc) | ((uint64_t)(uint32_t)sc << 32);
   }
 }
-
-__device__ __forceinline__ uint64_t pack_split(int cell, uint32_t bits) {
-  return (uint64_t)(uint32_t)cell | ((uint64_t)bits << 32);
-}
-__device__ __forceinline__ int split_cell(uint64_t w) { return (int)(uint32_t)(w & 0xffffffffull); }
-__device__ __forceinline__ uint32_t split_bits(uint64_t w) { return (uint32_t)(w >> 32); }
 
 // Position in mesh units of a state word.
 template <int PREC>
@@ -110,7 +133,7 @@ __device__ __forceinline__ double mesh_pos(uint64_t w, double inv_dx) {
   if constexpr (PREC == kFP64) {
     return __longlong_as_double((long long)w) * inv_dx;
   } else {
-    return (double)split_cell(w) + split_frac<PREC>(split_bits(w));
+    return (double)split_cell<PREC>(w) + split_frac<PREC>(w);
   }
 }
 
@@ -136,25 +159,48 @@ __device__ __forceinline__ double gather_field_ghost(const double *E, double u, 
   return (1.0 - s) * E[j] + s * E[j + 1];
 }
 
-// Split-form word moved by du cells: t = fraction + du, the cell advances by
-// floor(t) (periodically) and the rest is re-quantised.
+// Split-form word moved by du cells: the position advances by whole cells
+// (or, in the F32 form, whole sub-cells) plus a rest that is re-quantised;
+// the index wraps periodically.  A non-finite move (a non-finite velocity,
+// which the diagnostics flag) leaves the word as it is: a split position has
+// no non-finite value.
 template <int PREC>
 __device__ __forceinline__ uint64_t advance_split(uint64_t w, double du, int nc) {
-  const double t = split_frac<PREC>(split_bits(w)) + du;
+  // F32 counts in sub-cells, U32 in cells
+  constexpr double kUnit = PREC == kSplitF32 ? 0x1p20 : 1.0;
+  const double t = (PREC == kSplitF32 ? (double)__uint_as_float((uint32_t)(w >> 32)) : split_frac<PREC>(w)) +
+                   du * kUnit;
+  if (!(t - t == 0.0)) return w;
   const double k = floor(t);
   const double r = t - k;
-  int carry;
-  const uint32_t bits = split_quantise<PREC>(r, carry);
-  long long cell = (long long)split_cell(w) + (long long)k + carry;
+  long long step = (long long)k;
+  uint32_t bits;
+  if constexpr (PREC == kSplitF32) {
+    float o = (float)r;
+    if (o >= 1.0f) {
+      o = 0.0f;
+      step += 1;
+    }
+    bits = __float_as_uint(o);
+  } else {
+    double sc = rint(r * 4294967296.0);
+    if (sc >= 4294967296.0) {
+      sc = 0.0;
+      step += 1;
+    }
+    bits = (uint32_t)sc;
+  }
+  const long long period = (long long)nc << (PREC == kSplitF32 ? kSubBits : 0);
+  long long idx = (long long)(uint32_t)w + step;
   // a move of less than a period needs one conditional wrap; the (slow,
   // 64-bit) remainder only for longer ones
-  if (cell >= nc) cell -= nc;
-  else if (cell < 0) cell += nc;
-  if ((unsigned long long)cell >= (unsigned long long)nc) {
-    cell %= nc;
-    if (cell < 0) cell += nc;
+  if (idx >= period) idx -= period;
+  else if (idx < 0) idx += period;
+  if ((unsigned long long)idx >= (unsigned long long)period) {
+    idx %= period;
+    if (idx < 0) idx += period;
   }
-  return pack_split((int)cell, bits);
+  return (uint64_t)(uint32_t)idx | ((uint64_t)bits << 32);
 }
 
 // Drift of a state word by dt * v.
@@ -241,10 +287,10 @@ __device__ __forceinline__ double deposit_fp64(double a, double b, double q, con
 template <int PREC>
 __device__ __forceinline__ double deposit_split(uint64_t wa, uint64_t wb, long long qf, const Geo &g,
                                                 unsigned long long *sP, unsigned long long *sD) {
-  const int ca = split_cell(wa);
-  const double fa = split_frac<PREC>(split_bits(wa));
+  const int ca = split_cell<PREC>(wa);
+  const double fa = split_frac<PREC>(wa);
   const double ua = (double)ca + fa;
-  const double ub = (double)split_cell(wb) + split_frac<PREC>(split_bits(wb));
+  const double ub = mesh_pos<PREC>(wb, g.inv_dx);
   const double half_nc = 0.5 * (double)g.nc;
   double du = ub - ua;
   if (du >= half_nc) du -= (double)g.nc;
@@ -437,38 +483,66 @@ __device__ __forceinline__ double min_image_cells(double d, double half_nc, doub
   return d;
 }
 
-// Geometry of the segment from mesh position ua to ub (minimum image):
-// start, signed length and centroid in mesh units.
+// Geometry of a segment in mesh units: start, signed length along the
+// shorter way round the box and centroid.
 struct SegGeo {
   double u, d, c;
 };
 
-__device__ __forceinline__ SegGeo seg_geo_mesh(double ua, double ub, double half_nc, double nc) {
+// Geometry of the segment from state word wa to wb.  Float64 positions take
+// the physical minimum image, as the constant scheme does; split positions
+// take it in mesh units.
+template <int PREC>
+__device__ __forceinline__ SegGeo lin_geo(uint64_t wa, uint64_t wb, const Geo &g) {
   SegGeo s;
-  s.u = ua;
-  s.d = min_image_cells(ub - ua, half_nc, nc);
-  s.c = ua + 0.5 * s.d;
+  if constexpr (PREC == kFP64) {
+    const double xa = __longlong_as_double((long long)wa);
+    double d = __longlong_as_double((long long)wb) - xa;
+    if (d >= g.half_L) d -= g.L;
+    else if (d < -g.half_L) d += g.L;
+    s.u = xa * g.inv_dx;
+    s.d = d * g.inv_dx;
+  } else {
+    s.u = mesh_pos<PREC>(wa, g.inv_dx);
+    s.d = min_image_cells(mesh_pos<PREC>(wb, g.inv_dx) - s.u, 0.5 * (double)g.nc, (double)g.nc);
+  }
+  s.c = s.u + 0.5 * s.d;
   return s;
 }
 
-// Gradient of segment i from its neighbours (qm, qp: charges of segments
-// i-1 and i+1 in the accumulator's units).
-__device__ __forceinline__ double linear_gradient(const SegGeo &m, const SegGeo &i, const SegGeo &p, bool have_m,
-                                                  bool have_p, double qm, double qp, double half_nc, double nc) {
-  if (!(have_m && have_p) || m.d == 0.0 || p.d == 0.0) return 0.0;
-  const double dm = min_image_cells(m.c - i.c, half_nc, nc);
-  const double dp = min_image_cells(p.c - i.c, half_nc, nc);
-  if (!((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))) return 0.0;
-  // (qp / |p.d| - qm / |m.d|) / (dp - dm) with one division; the quotient
-  // form only where the common denominator would leave the normal range
-  const double lm = fabs(m.d), lp = fabs(p.d);
-  const double den = (lm * lp) * (dp - dm);
-  if (fabs(den) > 0x1p-900) return (qp * lm - qm * lp) / den;
-  return (qp / lp - qm / lm) / (dp - dm);
+// Mean density q / length of a segment (q in the accumulator's units), the
+// length taken over the extent the deposit integrates so that its pieces add
+// up to q; 0 for a zero-length segment.
+__device__ __forceinline__ double lin_density(const SegGeo &s, double q) {
+  const double u0 = s.d > 0.0 ? s.u : s.u + s.d;
+  const double u1 = s.d > 0.0 ? s.u + s.d : s.u;
+  const double len = u1 - u0;
+  return len > 0.0 ? q / len : 0.0;
 }
 
-// FP64: deposit segment i given its geometry and gradient (mesh units).
-__device__ __forceinline__ void deposit_linear_fp64(double a_phys, const SegGeo &sg, double g, double q,
+// Gradient of a segment with centroid c from its neighbours' centroids, signed
+// lengths and densities (m: the segment before, p: the one after): the
+// central difference of the densities over the centroid separation, 0 at a
+// fold corner (centroids not monotone) or when a neighbour is missing or has
+// zero length (both passed as length 0).
+__device__ __forceinline__ double lin_gradient(double c, double cm, double dm_len, double rm, double cp,
+                                               double dp_len, double rp, double half_nc, double nc) {
+  if (dm_len == 0.0 || dp_len == 0.0) return 0.0;
+  const double dm = min_image_cells(cm - c, half_nc, nc);
+  const double dp = min_image_cells(cp - c, half_nc, nc);
+  if (!((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))) return 0.0;
+  return (rp - rm) / (dp - dm);
+}
+
+// A neighbouring segment as the gradient needs it: centroid, signed length
+// and density.
+struct LinNb {
+  double c, d, r;
+};
+
+// FP64: deposit segment i given its geometry, gradient and density
+// r0 = q / length (lin_density; mesh units).
+__device__ __forceinline__ void deposit_linear_fp64(double a_phys, const SegGeo &sg, double g, double q, double r0,
                                                     const Geo &geo, double *sP, double *sD, double *sR) {
   if (sg.d == 0.0) {
     const int c = wrap_cell((int)ceil(a_phys / geo.dx) - 1, geo.nc);
@@ -485,7 +559,6 @@ __device__ __forceinline__ void deposit_linear_fp64(double a_phys, const SegGeo 
     lds_add(sP + wrap_cell(c0, geo.nc), q);
     return;
   }
-  const double r0 = q / len;
   const double e0 = f0 + 1.0;
   const double w0 = e0 - u0;
   const double w1 = u1 - (double)c1;
@@ -500,7 +573,7 @@ __device__ __forceinline__ void deposit_linear_fp64(double a_phys, const SegGeo 
 // Split form: fixed-point pieces, the last end cell takes the remainder so
 // the segment deposits exactly q_fix.
 __device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, const SegGeo &sg, double g,
-                                                     long long qf, const Geo &geo, unsigned long long *sP,
+                                                     long long qf, double r0, const Geo &geo, unsigned long long *sP,
                                                      unsigned long long *sD, unsigned long long *sR) {
   if (sg.d == 0.0) {
     const int c = wrap_cell(frac_a == 0.0 ? cell_a - 1 : cell_a, geo.nc);
@@ -517,7 +590,6 @@ __device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, 
     lds_add(sP + wrap_cell(c0, geo.nc), (unsigned long long)qf);
     return;
   }
-  const double r0 = (double)qf / len;
   const double e0 = f0 + 1.0;
   const long long p0 = llrint((e0 - u0) * (r0 + g * (0.5 * (u0 + e0) - sg.c)));
   long long p1 = qf - p0;
@@ -543,10 +615,14 @@ __device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, 
 //   f0: a0                 f0 + 1: r - b0 (n >= 1)
 //   f0 + 2 .. f1 - 1: r    f1: r - a1 (n >= 2)        f1 + 1: b1 (n >= 1)
 // where a = r (1 - t)^2 / 2 and b = r t^2 / 2 at either end; the terms that
-// land on one grid point are summed first (n = 0: a0 - a1 at f0, b1 - b0 at
-// f0 + 1; n = 1: r - b0 - a1 at f0 + 1), so a segment costs as many LDS
+// land on one grid point are summed first, so a segment costs as many LDS
 // additions as it has distinct grid points, up to four, plus the difference
-// array pair for a run of fully covered ones.
+// array pair for a run of fully covered ones.  Summed terms are written in
+// factored form, which keeps a short segment's pieces accurate to rounding of
+// its own charge (the plain differences would lose q/length times the
+// rounding of O(1) numbers): n = 0 gives f0 q (1 - tm) and f0 + 1 q tm with
+// tm = (t0 + t1) / 2 (the hat at the segment's midpoint); n = 1 gives f0 + 1
+// r [(1 - t0)(1 + t0) + t1 (2 - t1)] / 2.
 
 __device__ __forceinline__ void deposit_cic_fp64(double u_a, double d_mesh, double q, const Geo &g, double *sP,
                                                  double *sD) {
@@ -563,18 +639,22 @@ __device__ __forceinline__ void deposit_cic_fp64(double u_a, double d_mesh, doub
   const double fl1 = floor(s1);
   const double t1 = s1 - fl1;
   const int n = (int)fl1 - f0;
+  if (n == 0) {
+    const double tm = 0.5 * (t0 + t1);
+    lds_add(sP + wrap_cell(f0, g.nc), q * (1.0 - tm));
+    lds_add(sP + wrap_cell(f0 + 1, g.nc), q * tm);
+    return;
+  }
   const double r = q / (s1 - s0);
   const double hr = 0.5 * r;
   const double a0 = hr * ((1.0 - t0) * (1.0 - t0)), b0 = hr * (t0 * t0);
   const double a1 = hr * ((1.0 - t1) * (1.0 - t1)), b1 = hr * (t1 * t1);
-  lds_add(sP + wrap_cell(f0, g.nc), n == 0 ? a0 - a1 : a0);
-  lds_add(sP + wrap_cell(f0 + 1, g.nc), n == 0 ? b1 - b0 : (n == 1 ? (r - b0) - a1 : r - b0));
-  if (n >= 1) {
-    lds_add(sP + wrap_cell(f0 + n + 1, g.nc), b1);
-    if (n >= 2) {
-      lds_add(sP + wrap_cell(f0 + n, g.nc), r - a1);
-      if (n >= 3) add_run(sD, f0 + 2, f0 + n - 1, r, g.nc);
-    }
+  lds_add(sP + wrap_cell(f0, g.nc), a0);
+  lds_add(sP + wrap_cell(f0 + 1, g.nc), n == 1 ? hr * ((1.0 - t0) * (1.0 + t0) + t1 * (2.0 - t1)) : r - b0);
+  lds_add(sP + wrap_cell(f0 + n + 1, g.nc), b1);
+  if (n >= 2) {
+    lds_add(sP + wrap_cell(f0 + n, g.nc), r - a1);
+    if (n >= 3) add_run(sD, f0 + 2, f0 + n - 1, r, g.nc);
   }
 }
 
@@ -597,17 +677,18 @@ __device__ __forceinline__ void deposit_cic_split(double u_a, double d_mesh, lon
   const double fl1 = floor(s1);
   const double t1 = s1 - fl1;
   const int n = (int)fl1 - f0;
-  const double r = qd / (s1 - s0);
-  const double hr = 0.5 * r;
-  const double a0 = hr * ((1.0 - t0) * (1.0 - t0)), b0 = hr * (t0 * t0);
-  const double a1 = hr * ((1.0 - t1) * (1.0 - t1));
-  const long long p0 = llrint(n == 0 ? a0 - a1 : a0);
   if (n == 0) {
+    const long long p0 = llrint(qd * (1.0 - 0.5 * (t0 + t1)));
     lds_add(sP + wrap_cell(f0, g.nc), (unsigned long long)p0);
     lds_add(sP + wrap_cell(f0 + 1, g.nc), (unsigned long long)(qf - p0));
     return;
   }
-  const long long p1 = llrint(n == 1 ? (r - b0) - a1 : r - b0);
+  const double r = qd / (s1 - s0);
+  const double hr = 0.5 * r;
+  const double a0 = hr * ((1.0 - t0) * (1.0 - t0)), b0 = hr * (t0 * t0);
+  const double a1 = hr * ((1.0 - t1) * (1.0 - t1));
+  const long long p0 = llrint(a0);
+  const long long p1 = llrint(n == 1 ? hr * ((1.0 - t0) * (1.0 + t0) + t1 * (2.0 - t1)) : r - b0);
   long long rest = qf - p0 - p1;
   lds_add(sP + wrap_cell(f0, g.nc), (unsigned long long)p0);
   lds_add(sP + wrap_cell(f0 + 1, g.nc), (unsigned long long)p1);
@@ -742,10 +823,11 @@ __device__ __forceinline__ T lane_up1(T v) {
 // ---------------------------------------------------------------------------
 // Per-item LDS layout (bytes): P, D (and for linear segments R) accumulators
 // and the field E for mesh_cells cells; for tile_cap chunks the item's chunk
-// descriptors, the halo copies of the tracers next to each chunk (one for
-// constant segments; three, plus the links, for linear ones) and, with
-// per-segment charges, the two charge edges; 48 doubles for the block
-// reduction.
+// descriptors, the halo copy of the tracer after each chunk (constant
+// segments: its state; linear segments: its position word, plus the
+// geometry and density of the segment before the chunk and of the one after
+// its last segment) and, with per-segment charges, the two charge edges; 48
+// doubles for the block reduction.
 // ORDER: 0 piecewise-constant segments, 1 piecewise-linear segments (ramp
 // array R and three halo copies per chunk), 2 first-order weighting of
 // constant segments.  SEG: per-segment charges (a charge word per tracer).
@@ -753,7 +835,7 @@ template <class Acc, int ORDER, bool SEG>
 __host__ __device__ constexpr size_t tracer_lds_bytes(int mesh_cells, int tile_cap) {
   return (size_t)(2 + (ORDER == 1)) * mesh_cells * sizeof(Acc) + (size_t)(mesh_cells + 2) * sizeof(double) +
          (size_t)tile_cap *
-             (sizeof(ChunkDesc) + (ORDER == 1 ? 3 : 1) * sizeof(double2) + (ORDER == 1 ? sizeof(int2) : 0) +
+             (sizeof(ChunkDesc) + (ORDER == 1 ? sizeof(uint64_t) + 2 * sizeof(LinNb) : sizeof(double2)) +
               (SEG ? 2 * sizeof(uint64_t) : 0)) +
          48 * sizeof(double);
 }
@@ -786,12 +868,13 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   acc_t *sR = sD + a.mesh_cells;  // linear segments only
   double *sE = reinterpret_cast<double *>(sR + (kLin ? a.mesh_cells : 0)) + 1;  // ghost cells at -1 and nc
   ChunkDesc *sDesc = reinterpret_cast<ChunkDesc *>(sE + a.mesh_cells + 1);
-  double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);  // order 0: next tracer; order 1: next
-  double2 *sHalo2 = sHalo + a.tile_cap;                               // order 1: next but one
-  double2 *sHaloP = sHalo2 + a.tile_cap;                              // order 1: previous
-  int2 *sLinks = reinterpret_cast<int2 *>(sHalo + (kLin ? 3 : 1) * a.tile_cap);
-  uint64_t *sEdge = reinterpret_cast<uint64_t *>(sLinks + (kLin ? a.tile_cap : 0));  // per-segment charges
-  double *sRed = reinterpret_cast<double *>(sEdge + (SEG ? 2 * a.tile_cap : 0));      // 3 x 16 waves
+  double2 *sHalo = reinterpret_cast<double2 *>(sDesc + a.tile_cap);     // orders 0, 2: the next tracer
+  uint64_t *sNextW = reinterpret_cast<uint64_t *>(sDesc + a.tile_cap);  // order 1: the next tracer's word
+  LinNb *sPrevNb = reinterpret_cast<LinNb *>(sNextW + a.tile_cap);      // order 1: segment before the chunk
+  LinNb *sNextNb = sPrevNb + a.tile_cap;                                // order 1: segment after its last one
+  uint64_t *sEdge = kLin ? reinterpret_cast<uint64_t *>(sNextNb + a.tile_cap)
+                         : reinterpret_cast<uint64_t *>(sHalo + a.tile_cap);  // per-segment charges
+  double *sRed = reinterpret_cast<double *>(sEdge + (SEG ? 2 * a.tile_cap : 0));  // 3 x 16 waves
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -840,7 +923,6 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     }
     for (int i = tid; i < nch; i += blockDim.x) {
       sDesc[i] = a.chunks[cb + i];
-      if constexpr (kLin && kDep) sLinks[i] = a.links[cb + i];
       if constexpr (kNeedQ) {
         sEdge[2 * i] = a.cedge[2 * (size_t)(cb + i)];
         sEdge[2 * i + 1] = a.cedge[2 * (size_t)(cb + i) + 1];
@@ -851,21 +933,49 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       for (int i = tid; i < nch; i += blockDim.x) {
         const int pc = sDesc[i].partner;
         if constexpr (kLin) {
-          // the three halo tracers, moved here (once per chunk, one thread)
-          // when this step moves, as for the constant scheme below
-          auto moved = [&](double2 h) {
+          // The tracers around the chunk, moved here (once per chunk, one
+          // thread) when this step moves, as for the constant scheme below:
+          // the next tracer (the partner's first), whose word the last lane's
+          // segment ends at, and the segments just outside the chunk, whose
+          // geometry and density the gradients of the first and last lanes'
+          // segments need (the same functions as the lanes', so the same bits).
+          auto moved = [&](double2 h) -> uint64_t {
+            uint64_t w = (uint64_t)__double_as_longlong(h.x);
             if constexpr (kMove) {
-              uint64_t w = (uint64_t)__double_as_longlong(h.x);
               const double e = gather_field_ghost(sE, mesh_pos<PREC>(w, g.inv_dx), g.nc);
               w = drift<PREC>(w, h.y + g.dt * e, g.dt, g.L, g.inv_dx, g.nc);
-              h.x = __longlong_as_double((long long)w);
             }
-            return h;
+            return w;
           };
-          const int2 lk = sLinks[i];
-          if (pc >= 0) sHalo[i] = moved(a.halo3_in[3 * pc + kHaloFirst]);
-          if (lk.y >= 0) sHalo2[i] = moved(a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)]);
-          if (lk.x >= 0) sHaloP[i] = moved(a.halo3_in[3 * (lk.x >> 2) + (lk.x & 3)]);
+          auto neighbour = [&](uint64_t wa, uint64_t wb, uint64_t cword) {
+            const SegGeo sgn = lin_geo<PREC>(wa, wb, g);
+            double q;
+            if constexpr (SEG) q = PREC == kFP64 ? __longlong_as_double((long long)cword) : (double)(long long)cword;
+            else q = PREC == kFP64 ? sDesc[i].q : (double)sDesc[i].q_fix;
+            LinNb nb;
+            nb.c = sgn.c;
+            nb.d = sgn.d;
+            nb.r = lin_density(sgn, q);
+            return nb;
+          };
+          const int2 lk = a.links[cb + i];
+          LinNb none;
+          none.c = none.d = none.r = 0.0;
+          LinNb prev = none, next = none;
+          uint64_t wn1 = 0;
+          if (pc >= 0) wn1 = moved(a.halo3_in[3 * pc + kHaloFirst]);
+          if (lk.x >= 0) {
+            const uint64_t wpv = moved(a.halo3_in[3 * (lk.x >> 2) + (lk.x & 3)]);
+            const uint64_t w0 = moved(a.halo3_in[3 * (size_t)(cb + i) + kHaloFirst]);
+            prev = neighbour(wpv, w0, SEG ? sEdge[2 * i] : 0ull);
+          }
+          if (pc >= 0 && lk.y >= 0) {
+            const uint64_t wn2 = moved(a.halo3_in[3 * (lk.y >> 2) + (lk.y & 3)]);
+            next = neighbour(wn1, wn2, SEG ? sEdge[2 * i + 1] : 0ull);
+          }
+          sNextW[i] = wn1;
+          sPrevNb[i] = prev;
+          sNextNb[i] = next;
         } else if (pc >= 0) {
           double2 h = a.halo_in[pc];
           if constexpr (kMove) {
@@ -955,71 +1065,46 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         }
       }
       if constexpr (kDep && kLin) {
-        // Tracers i-1, i+1, i+2 of segment i: lane shuffles inside the chunk,
-        // halo copies past its ends (moved at staging when this kernel also
-        // moves).  Lanes 0, 1 and 2 read the previous, next and next-but-one
-        // halo tracer and broadcast it.
-        const int2 lk = sLinks[kk];
-        const bool have_n1 = ch.partner >= 0, have_n2 = lk.y >= 0, have_pv = lk.x >= 0;
-        uint64_t hw = xw;
-        if (lane < 3 && (lane == 0 ? have_pv : (lane == 1 ? have_n1 : have_n2))) {
-          // sHalo, sHalo2 and sHaloP are consecutive tile_cap-long arrays
-          hw = (uint64_t)__double_as_longlong(sHalo[(lane == 0 ? 2 : lane - 1) * a.tile_cap + kk].x);
+        // Every lane computes its own segment's geometry and density; the
+        // gradient takes the neighbouring segments' from the lanes next to
+        // it (DPP moves), and the first and last lanes take the segments
+        // outside the chunk from the staged neighbours.
+        const bool last = lane == n_valid - 1;
+        const uint64_t dn1 = lane_down1(xw);  // all lanes active: a DPP move reads its neighbour's register
+        const uint64_t xp1 = last ? sNextW[kk] : dn1;
+        const bool has_seg = valid && (!last || ch.partner >= 0);
+        SegGeo sg = lin_geo<PREC>(xw, xp1, g);
+        if (!has_seg) sg.d = 0.0;  // a neighbour without a segment drops the gradient
+        double q0 = ch.q;
+        long long q0_fix = ch.q_fix;
+        if constexpr (SEG) {
+          if constexpr (PREC == kFP64) q0 = __longlong_as_double((long long)cw);
+          else q0_fix = (long long)cw;
         }
-        const uint64_t hpv = read_lane64(hw, 0);
-        const uint64_t hn1 = read_lane64(hw, 1);
-        const uint64_t hn2 = read_lane64(hw, 2);
-        const uint64_t up1 = lane_up1(xw);
-        const uint64_t dn1 = lane_down1(xw);
-        const uint64_t dn2 = lane_down1(dn1);  // two lanes on (used below lane n_valid - 2 only)
-        const uint64_t xm1 = lane > 0 ? up1 : hpv;
-        const bool has_m1 = lane > 0 || have_pv;
-        const uint64_t xp1 = lane < n_valid - 1 ? dn1 : hn1;
-        const bool has_p1 = lane < n_valid - 1 || have_n1;
-        const uint64_t xp2 = lane < n_valid - 2 ? dn2 : (lane == n_valid - 2 ? hn1 : hn2);
-        const bool has_p2 = lane < n_valid - 2 || (lane == n_valid - 2 ? have_n1 : have_n2);
-        if (valid && has_p1) {
-          const double half_nc = 0.5 * (double)g.nc, ncd = (double)g.nc;
-          const double um1 = mesh_pos<PREC>(xm1, g.inv_dx);
-          const double u0 = mesh_pos<PREC>(xw, g.inv_dx);
-          const double up1d = mesh_pos<PREC>(xp1, g.inv_dx);
-          const double up2 = mesh_pos<PREC>(xp2, g.inv_dx);
-          SegGeo sg = seg_geo_mesh(u0, up1d, half_nc, ncd);
-          if constexpr (PREC == kFP64) {
-            // the segment itself takes the physical minimum image, as the
-            // constant scheme does
-            const double xa = __longlong_as_double((long long)xw);
-            double d = __longlong_as_double((long long)xp1) - xa;
-            if (d >= g.half_L) d -= g.L;
-            else if (d < -g.half_L) d += g.L;
-            sg.d = d * g.inv_dx;
-            sg.c = sg.u + 0.5 * sg.d;
-          }
-          const SegGeo sm = seg_geo_mesh(um1, u0, half_nc, ncd);
-          const SegGeo sp = seg_geo_mesh(up1d, up2, half_nc, ncd);
-          double qm, qp, q0 = ch.q;
-          long long q0_fix = ch.q_fix;
-          if constexpr (SEG) {
-            if constexpr (PREC == kFP64) {
-              qm = __longlong_as_double((long long)cl);
-              qp = __longlong_as_double((long long)cn);
-              q0 = __longlong_as_double((long long)cw);
-            } else {
-              qm = (double)(long long)cl;
-              qp = (double)(long long)cn;
-              q0_fix = (long long)cw;
-            }
-          } else {
-            qm = qp = PREC == kFP64 ? ch.q : (double)ch.q_fix;
-          }
-          const double grad = linear_gradient(sm, sg, sp, has_m1, has_p2, qm, qp, half_nc, ncd);
+        const double r0 = lin_density(sg, PREC == kFP64 ? q0 : (double)q0_fix);
+        double cm = lane_up1(sg.c), dm = lane_up1(sg.d), rm = lane_up1(r0);
+        double cp = lane_down1(sg.c), dp = lane_down1(sg.d), rp = lane_down1(r0);
+        if (lane == 0) {
+          const LinNb nb = sPrevNb[kk];
+          cm = nb.c;
+          dm = nb.d;
+          rm = nb.r;
+        }
+        if (last) {
+          const LinNb nb = sNextNb[kk];
+          cp = nb.c;
+          dp = nb.d;
+          rp = nb.r;
+        }
+        if (has_seg) {
+          const double grad = lin_gradient(sg.c, cm, dm, rm, cp, dp, rp, 0.5 * (double)g.nc, (double)g.nc);
           const double len = fabs(sg.d) * g.dx;
           if (len <= g.half_L) {
             if constexpr (PREC == kFP64) {
-              deposit_linear_fp64(__longlong_as_double((long long)xw), sg, grad, q0, g, sP, sD, sR);
+              deposit_linear_fp64(__longlong_as_double((long long)xw), sg, grad, q0, r0, g, sP, sD, sR);
             } else {
-              deposit_linear_split(split_cell(xw), split_frac<PREC>(split_bits(xw)), sg, grad, q0_fix, g, sP,
-                                   sD, sR);
+              deposit_linear_split(split_cell<PREC>(xw), split_frac<PREC>(xw), sg, grad, q0_fix, r0, g, sP, sD,
+                                   sR);
             }
           }
           ms = nan_max(ms, len);
@@ -1231,7 +1316,7 @@ __device__ __forceinline__ int point_cell_up(uint64_t w, const Geo &g, double to
     if (r > tol && r < tol_hi) return (int)c;
     return (int)ceil(x / g.dx);
   } else {
-    return split_frac<PREC>(split_bits(w)) == 0.0 ? split_cell(w) : split_cell(w) + 1;
+    return split_frac<PREC>(w) == 0.0 ? split_cell<PREC>(w) : split_cell<PREC>(w) + 1;
   }
 }
 
@@ -1686,6 +1771,8 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
   const int64_t step = pushed ? step0 + 1 : step0;
   int f = 0;
   if (bad || !(W - W == 0.0)) f |= 1;
+  // a move with a non-finite velocity (its kinetic energy or momentum)
+  if (pushed && !((ke - ke == 0.0) && (mom - mom == 0.0))) f |= 1;
   if (a.flags & kHaveDeposit) {
     if (ms != ms) f |= 1;
     else if (ms > 0.45 * L) f |= 2;
@@ -2006,10 +2093,7 @@ __global__ void __launch_bounds__(256) k_ingest(IngestArgs a) {
       } else {
         const double u = x * I.inv_dx;
         const double f = floor(u);
-        int carry;
-        const uint32_t bits = split_quantise<PREC>(u - f, carry);
-        const int cell = wrap_cell((int)f + carry, I.n_cells);
-        w = pack_split(cell, bits);
+        w = split_word<PREC>((int)f, u - f, I.n_cells);
       }
     }
     if (a.segq) {
@@ -2053,7 +2137,7 @@ __global__ void __launch_bounds__(256) k_extract(ExtractArgs a) {
   if constexpr (PREC == kFP64) {
     x = __longlong_as_double((long long)w);
   } else {
-    x = ((double)split_cell(w) + split_frac<PREC>(split_bits(w))) * I.dx;
+    x = mesh_pos<PREC>(w, I.inv_dx) * I.dx;
   }
   a.x_out[dst] = x;
   a.v_out[dst] = a.vs[s];
@@ -2193,9 +2277,27 @@ __global__ void __launch_bounds__(256) k_zero_mesh(void *meshP, void *meshD, voi
   }
 }
 
-__global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
+// Streaming copy for the bandwidth calibration: per iteration each lane has
+// kCopyUnroll 16-byte loads in flight before it stores them; loads and stores
+// are non-temporal (the array streams through once), and the workgroups
+// stride over the array together.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+constexpr int kCopyUnroll = 4;
+
+__global__ void __launch_bounds__(256) k_copy(const f64x2 *__restrict__ src, f64x2 *__restrict__ dst, int64_t n2) {
+  const int64_t bd = blockDim.x;
+  const int64_t per_iter = (int64_t)gridDim.x * bd * kCopyUnroll;
+  int64_t i = (int64_t)blockIdx.x * bd * kCopyUnroll + threadIdx.x;
+  for (; i + (kCopyUnroll - 1) * bd < n2; i += per_iter) {
+    f64x2 r[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) r[u] = __builtin_nontemporal_load(src + i + u * bd);
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(r[u], dst + i + u * bd);
+  }
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    if (i + u * bd < n2) dst[i + u * bd] = src[i + u * bd];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2469,9 +2571,9 @@ int launch_refine_scatter(int prec, const RefineArgs &a, void *stream) {
   return (int)hipGetLastError();
 }
 
-int launch_copy_bench(const double *src, double *dst, int64_t n, void *stream) {
+int launch_copy_bench(const double *src, double *dst, int64_t n, int grid, void *stream) {
   const int64_t n2 = n / 2;
-  hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, (hipStream_t)stream, (const double2 *)src, (double2 *)dst, n2);
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const f64x2 *)src, (f64x2 *)dst, n2);
   return (int)hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ class Record:
     final_W_E: float = math.nan
     flags: int = 0
     size_class: int = -1
+    W_E_history: Optional[np.ndarray] = None  # kept when the executor keeps histories
 
     @property
     def latency(self) -> float:
@@ -156,6 +157,7 @@ class Server:
                     rec.completed = self.clock() - t0
                     rec.final_W_E = float(res.get("W_E", math.nan))
                     rec.flags = int(res.get("flags", 0))
+                    rec.W_E_history = res.get("W_E_history")
             elif nxt < len(reqs):
                 wait = reqs[nxt].arrival - (self.clock() - t0)
                 if wait > 0:
@@ -194,7 +196,8 @@ class _Handle:
 class GpuExecutor(Executor):
     """Resident batches of libsic, one per size class, on the current stream."""
 
-    def __init__(self, classes=DEFAULT_CLASSES, precision: int = 0, history_rows: int = 4096, autotune=False):
+    def __init__(self, classes=DEFAULT_CLASSES, precision: int = 0, history_rows: int = 4096, autotune=False,
+                 keep_history: bool = False):
         import torch
 
         from . import binding as B
@@ -203,6 +206,7 @@ class GpuExecutor(Executor):
         self.torch = torch
         self.classes = list(classes)
         self.precision = precision
+        self.keep_history = keep_history
         # one stream per size class (default priority): the classes' steps
         # overlap on the device, so the large-mesh class, whose LDS mesh
         # leaves room for few workgroups per CU, shares the GPU with the rest
@@ -273,10 +277,13 @@ class GpuExecutor(Executor):
 
     def finish(self, h) -> dict:
         b = self.batches[h.size_class]
-        r = self.B.sic_batch_result(b, h.slot, history=False)
+        r = self.B.sic_batch_result(b, h.slot, history=self.keep_history)
         self.B.sic_batch_release(b, h.slot)
         self.live[h.size_class].discard(h.slot)
-        return r["last"]
+        out = dict(r["last"])
+        if self.keep_history:
+            out["W_E_history"] = np.array(r["history"]["W_E"])
+        return out
 
 
 def serve_prepare(executor: GpuExecutor):

@@ -3,6 +3,7 @@ single steps of the full two-stream configuration and of a large served job,
 sampled instances of the 4096-instance mixed batch in the launch shape the
 benchmark times, and a full-length two-stream run at reduced tracer count."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -10,7 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_1506_07207_amd import binding as B
 from paper_1506_07207_amd import inputs as I
-from tests.parity import envelope_rel, periodic_diff, rel_inf
+from tests.parity import envelope, envelope_rel, horizon, periodic_diff, perturbed_positions, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +24,7 @@ def _one_step(p, prec):
     return x, v, d
 
 
-@pytest.mark.parametrize("prec", [B.SIC_FP64, B.SIC_SPLIT_U32])
+@pytest.mark.parametrize("prec", [B.SIC_FP64, B.SIC_SPLIT_U32, B.SIC_SPLIT_F32])
 def test_two_stream_full_size_single_step(prec):
     p = I.two_stream()  # 512 sheets x 4096 tracers, 1024 cells
     print(f"case two_stream full size prec={prec}", flush=True)
@@ -35,7 +36,10 @@ def test_two_stream_full_size_single_step(prec):
         assert abs(d["last"]["W_E"] - ref["hist"][1, 2]) < 1e-10 * ref["hist"][1, 2]
         assert rel_inf(d["E"], ref["E"]) < 1e-10
     else:
-        assert np.max(periodic_diff(x, ref["x"], p.L)) < 2.0 ** -30 * dx
+        # quantisation: 2^-32 (U32) or about 2^-44 (F32) of a cell, plus the
+        # oracle's own float64 rounding of a position for F32
+        q = 2.0 ** -30 if prec == B.SIC_SPLIT_U32 else 2.0 ** -40
+        assert np.max(periodic_diff(x, ref["x"], p.L)) < q * dx
         assert abs(d["last"]["W_E"] - ref["hist"][1, 2]) < 1e-6 * ref["hist"][1, 2]
     rho_o = ref["Q"] / dx - ref["Q"].sum() / p.L
     assert np.max(np.abs(d["rho"] - rho_o)) < 1e-10
@@ -46,37 +50,91 @@ def _first_over(err, tol):
     return int(idx[0]) if len(idx) else None
 
 
-def test_two_stream_full_length_reduced_tracers():
-    """2000 steps of the two-stream configuration (64 sheets x 1024 tracers).
+FORMS = ((B.SIC_FP64, "fp64", 1e-10), (B.SIC_SPLIT_U32, "split u32", 1e-6), (B.SIC_SPLIT_F32, "split f32", 1e-6))
 
-    After saturation (t ~ 20) the phase-space vortex amplifies any
-    difference exponentially: even the FP64 GPU path, which differs from the
-    oracle only in the order of roundings, departs from it.  So the run-long
-    comparison holds each tolerance through the linear and early nonlinear
-    phase (t <= 50) and reports the step where it is first exceeded; the
-    oracle-resynchronised single steps below hold it at every point of the
-    run."""
-    p = I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=2000)
-    print("case two_stream 64x1024, 2000 steps", flush=True)
-    ref = O.run_problem(p)
-    Wr = ref["hist"][:, 2]
-    P = int(math.ceil(2 * math.pi / p.dt))
-    env = np.array([np.max(Wr[max(0, i - P): i + P + 1]) for i in range(len(Wr))])
+
+def _gpu_errors(p, W_ref):
+    env = envelope(W_ref, p.dt)
     errs = {}
-    for prec in (B.SIC_FP64, B.SIC_SPLIT_U32, B.SIC_SPLIT_F32):
+    for prec, _, _ in FORMS:
         with B.Simulation(p, precision=prec) as s:
             s.step(p.n_steps)
-            errs[prec] = np.abs(s.diagnostics()["history"]["W_E"] - Wr) / env
-    window = int(round(50.0 / p.dt))
-    for prec, tol in ((B.SIC_FP64, 1e-10), (B.SIC_SPLIT_U32, 1e-6), (B.SIC_SPLIT_F32, 1e-6)):
-        e = errs[prec]
-        print(f"prec={prec}: max error up to t=50 {e[:window + 1].max():.3e}, whole run {e.max():.3e}, "
-              f"first step over {tol:g}: {_first_over(e, tol)}", flush=True)
-    assert errs[B.SIC_FP64][:window + 1].max() < 1e-10
-    assert errs[B.SIC_SPLIT_U32][:window + 1].max() < 1e-6
+            W = s.diagnostics()["history"]["W_E"]
+        errs[prec] = np.abs(W - W_ref) / env
+    return env, errs
 
 
-@pytest.mark.parametrize("prec,tol", [(B.SIC_FP64, 1e-10), (B.SIC_SPLIT_U32, 1e-6)])
+def _check_horizons(errs, spread_ulp, spread_u32, label):
+    """After saturation the vortex amplifies any difference exponentially,
+    so a finite-precision run can follow the oracle only while small
+    differences do not yet grow.  That regime is read off the oracle itself:
+    an ensemble of oracle runs whose initial positions move at the scale of
+    a form's rounding (one ulp of a float64 position for float64 and for the
+    F32 split form, about 2^-44 of a cell; 2^-33 of a cell for the U32 split
+    form) spreads by rounding-sized amounts until the differences start to
+    grow; the horizon is the first step where the spread exceeds ten times
+    its size at step 0.  Each form is held to its tolerance up to its
+    horizon.  The F32 form stays within its tolerance over the whole run
+    (its result is bitwise reproducible, so this is a fixed fact of the
+    configuration, not a sample), and is held to that."""
+    n = len(spread_ulp)
+    h_ulp = horizon(spread_ulp, 10.0 * max(spread_ulp[0], 1e-16))
+    h_u32 = horizon(spread_u32, 10.0 * max(spread_u32[0], 1e-16))
+    horizons = {B.SIC_FP64: h_ulp, B.SIC_SPLIT_F32: n, B.SIC_SPLIT_U32: h_u32}
+    for prec, name, tol in FORMS:
+        e, h = errs[prec], horizons[prec]
+        print(f"{label} {name}: horizon {h} of {n - 1} steps, max error up to it {e[:h].max():.3e}, "
+              f"whole run {e.max():.3e}, first step over {tol:g}: {_first_over(e, tol)}", flush=True)
+    for k in range(0, n, 100):
+        print(f"  step {k}: spread ulp {spread_ulp[k]:.2e} u32 {spread_u32[k]:.2e}; error " +
+              " ".join(f"{name} {errs[prec][k]:.2e}" for prec, name, _ in FORMS), flush=True)
+    for prec, name, tol in FORMS:
+        h = horizons[prec]
+        assert h > 0.25 * n, (name, h)  # the predictable phase covers the linear growth and saturation
+        assert errs[prec][:h].max() < tol, (name, h, errs[prec][:h].max())
+
+
+def test_two_stream_full_size_full_run():
+    """The full two-stream configuration (512 sheets x 4096 tracers, 1024
+    cells, 2000 steps) in all three forms against the oracle's history, and
+    against the predictability horizons of the oracle's own perturbation
+    ensembles (stored, written by tests/golden/make_two_stream_ensemble.py)."""
+    p = I.two_stream()
+    print("case two_stream full size, 2000 steps", flush=True)
+    data = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "two_stream_full_ensemble.txt"))
+    assert data.shape == (p.n_steps + 1, 4)
+    W_ref = data[:, 1]
+    env, errs = _gpu_errors(p, W_ref)
+    _check_horizons(errs, data[:, 2] / env, data[:, 3] / env, "two-stream 512x4096")
+
+
+def test_two_stream_full_length_reduced_tracers():
+    """2000 steps of the two-stream configuration at 64 sheets x 1024
+    tracers: fewer tracers per cell make the nonlinear phase more chaotic
+    than at full size.  The oracle ensembles are computed here (threads:
+    the oracle releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    p = I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=2000)
+    dx = p.L / p.n_cells
+    print("case two_stream 64x1024, 2000 steps", flush=True)
+    members = [("base", 0), ("ulp", 1), ("ulp", 2), ("ulp", 3), ("u32", 4), ("u32", 5)]
+
+    def run(m):
+        kind, seed = m
+        x0 = p.x0 if kind == "base" else perturbed_positions(p.x0, p.L, kind, seed, dx)
+        return O.run(p.L, p.n_cells, p.dt, p.n_tracers, p.q, p.closed, x0, p.v0, p.n_steps)["hist"][:, 2]
+
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        Ws = list(ex.map(run, members))
+    W_ref = Ws[0]
+    env, errs = _gpu_errors(p, W_ref)
+    spread = {k: np.max([np.abs(W - W_ref) for (kk, _), W in zip(members, Ws) if kk == k], axis=0) / env
+              for k in ("ulp", "u32")}
+    _check_horizons(errs, spread["ulp"], spread["u32"], "two-stream 64x1024")
+
+
+@pytest.mark.parametrize("prec,tol", [(B.SIC_FP64, 1e-10), (B.SIC_SPLIT_U32, 1e-6), (B.SIC_SPLIT_F32, 1e-6)])
 def test_two_stream_resynchronised_steps_through_the_run(prec, tol):
     """At steps 0, 400, ..., 2000 of the two-stream run (64 x 1024), the GPU
     is loaded with the oracle's state and takes one step; its field energy
@@ -84,7 +142,7 @@ def test_two_stream_resynchronised_steps_through_the_run(prec, tol):
     including deep in the nonlinear phase."""
     p = I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=2000)
     dx = p.L / p.n_cells
-    pos_tol = 1e-12 * p.L if prec == B.SIC_FP64 else 2.0 ** -30 * dx
+    pos_tol = {B.SIC_FP64: 1e-12 * p.L, B.SIC_SPLIT_U32: 2.0 ** -30 * dx, B.SIC_SPLIT_F32: 2.0 ** -40 * dx}[prec]
     ref = O.run_problem(p, 0)
     x, v, step = ref["x"], ref["v"], 0
     with B.Simulation(p, precision=prec) as s:
@@ -146,17 +204,7 @@ def test_mixed_batch_sampled_instances(order, seg, prec, tol):
             err = np.max(np.abs(h["W_E"] - ref["hist"][:, 2]) / np.max(ref["hist"][:, 2]))
             print(f"  instance {i}: W_E rel err {err:.2e}", flush=True)
             assert err < tol, (i, err)
-            if order != 2:
-                assert rel_inf(r["E"], ref["E"]) < tol
-            else:
-                # W_1 weighting: the oracle's trapezoid pieces carry position
-                # rounding into its charge; Gauss's law carries a charge
-                # difference into the field with gain at most L
-                dx = p.L / p.n_cells
-                rho_o = ref["Q"] / dx - ref["Q"].sum() / p.L
-                err_rho = np.max(np.abs(r["rho"] - rho_o))
-                assert err_rho < 1e-10 * max(1.0, np.max(np.abs(ref["Q"] / dx))), (i, err_rho)
-                assert np.max(np.abs(r["E"] - ref["E"])) <= 1e-10 * np.max(np.abs(ref["E"])) + p.L * err_rho, i
+            assert rel_inf(r["E"], ref["E"]) < tol, (i, rel_inf(r["E"], ref["E"]))
     finally:
         B.sic_batch_destroy(b)
 
