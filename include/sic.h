@@ -224,6 +224,23 @@ sic_status sic_get_state(sic_sim *sim, double *x, double *v_half, int64_t *step,
  * deposits and solves first).  Synchronous. */
 sic_status sic_set_state(sic_sim *sim, int64_t step, const double *x, const double *v_half, int32_t mem_kind);
 
+/* Largest simulation (tracers) whose host inputs sic_set_state_noalloc stages. */
+#define SIC_NOALLOC_MAX_TRACERS (1 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sic_set_state
+ * without any allocation.  Host inputs (SIC_MEM_HOST) are staged through a
+ * fixed device array of 16 * SIC_NOALLOC_MAX_TRACERS bytes (16 MiB) that the
+ * library holds on each GPU it runs on until the process ends, instead of a
+ * buffer allocated for the call; device inputs are read in place.  With host
+ * inputs a simulation of more than SIC_NOALLOC_MAX_TRACERS tracers gets
+ * SIC_EINVAL and nothing changes.  The array is shared by every call on that
+ * GPU and keeps the last call's contents: calls that overlap on one GPU (from
+ * several host threads) race on it and must be serialised by the caller.
+ * Otherwise exactly sic_set_state (synchronous). */
+sic_status sic_set_state_noalloc(sic_sim *sim, int64_t step, const double *x, const double *v_half,
+                                 int32_t mem_kind);
+
 void sic_destroy(sic_sim *sim);
 const char *sic_status_str(sic_status s);
 /* Message of the last failing call on sim; with sim == NULL, of the last

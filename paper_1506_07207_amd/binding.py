@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libsic.so")
 SIC_ABI_VERSION = 2
 SIC_BATCH_SEGMENT_CHARGES = 1
 SIC_MAX_CELLS = 4096
+SIC_NOALLOC_MAX_TRACERS = 1 << 20
 SIC_FP64, SIC_SPLIT_F32, SIC_SPLIT_U32 = 0, 1, 2
 SIC_MEM_HOST, SIC_MEM_DEVICE = 0, 1
 SIC_DIAG_NONFINITE, SIC_DIAG_LONG_SEGMENT = 1, 2
@@ -80,6 +81,7 @@ _SIGS = {
     "sic_diagnostics": (_I32, [_P, _P, _P, _P, _P, _P]),
     "sic_get_state": (_I32, [_P, _P, _P, _P, _I32]),
     "sic_set_state": (_I32, [_P, _I64, _P, _P, _I32]),
+    "sic_set_state_noalloc": (_I32, [_P, _I64, _P, _P, _I32]),
     "sic_destroy": (None, [_P]),
     "sic_last_error": (ctypes.c_char_p, [_P]),
     "sic_set_tuning": (_I32, [_P, _P]),
@@ -287,6 +289,13 @@ def sic_set_state(h, step: int, x, v_half):
     px, kx, kx_ = _as_f64(x)
     pv, kv, kv_ = _as_f64(v_half)
     _check(lib.sic_set_state(h, int(step), px, pv, kx), "sic_set_state", h)
+
+
+def sic_set_state_noalloc(h, step: int, x, v_half):
+    lib = load()
+    px, kx, kx_ = _as_f64(x)
+    pv, kv, kv_ = _as_f64(v_half)
+    _check(lib.sic_set_state_noalloc(h, int(step), px, pv, kx), "sic_set_state_noalloc", h)
 
 
 def sic_refine(h, l_max: float) -> int:

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -118,6 +119,7 @@ struct SlotHost {
 struct Pool {
   int prec = 0;
   int order = 0;  // deposit order: 0 piecewise-constant, 1 piecewise-linear, 2 first-order weighting
+  int device = 0;    // HIP device current at creation
   bool seg = false;  // per-segment charges
   bool batch = false;
   hipStream_t stream = nullptr;  // caller's stream
@@ -194,6 +196,32 @@ sic_status fail(Pool *p, sic_status s, const std::string &msg) {
   return s;
 }
 
+// Staging memory of the entry points that allocate nothing: one fixed array
+// per GPU (each device holds its own copy of this module-scope array), 16
+// bytes per tracer for SIC_NOALLOC_MAX_TRACERS tracers.  In host code the
+// name stands for a host-side shadow, not a device address: kernels and
+// copies get the address hipGetSymbolAddress returns for the device, looked
+// up once per device when a pool is created there.
+static __device__ __align__(256) double scratch[2 * (size_t)SIC_NOALLOC_MAX_TRACERS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+hipError_t scratch_address(int device, double **out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
 #define HIPCHK(p, expr)                                                                          \
   do {                                                                                           \
     hipError_t e_ = (expr);                                                                      \
@@ -254,6 +282,7 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
   p->order = order;
   p->seg = seg;
   p->batch = batch;
+  if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
   p->stream = (hipStream_t)stream;
   p->slot_cap = slot_cap;
   p->max_cells = max_cells;
@@ -298,6 +327,13 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
   ALLOC(p->inst, (size_t)slot_cap);
   ALLOC(p->slot_items, (size_t)slot_cap);
   ALLOC(p->partials, (size_t)p->item_cap);
+  {
+    // the no-allocation entry points' staging array on this device, looked
+    // up here once per device (a failure is reported by those entry points,
+    // which look it up again)
+    double *sp = nullptr;
+    (void)scratch_address(p->device, &sp);
+  }
   {
     const size_t mc = (size_t)slot_cap * max_cells;
     long long *mp = nullptr, *md = nullptr;
@@ -1461,8 +1497,10 @@ sic_status pool_load_state(Pool *p, int64_t step, const int32_t *n_tracers, cons
   return st;
 }
 
+// fixed_stage: device memory of at least 2 n_tracers doubles for staging host
+// inputs (the no-allocation entry point's array); nullptr: allocated here.
 sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, const double *v,
-                          int32_t mem_kind) {
+                          int32_t mem_kind, double *fixed_stage = nullptr) {
   if (slot < 0 || slot >= p->slot_cap || !p->slots[slot].live) return fail(p, SIC_EINVAL, "slot not live");
   if (!x || !v || step < 0) return fail(p, SIC_EINVAL, "bad state arguments");
   SlotHost &sh = p->slots[slot];
@@ -1472,14 +1510,18 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
   sic_status st = read_inst(p, slot, &I);
   if (st != SIC_OK) return st;
   I.step = step;
-  double *stage = nullptr;
+  double *stage = nullptr;  // allocated here (freed below)
   const double *dx = x, *dv = v;
   if (mem_kind == SIC_MEM_HOST) {
-    HIPCHK(p, hipMalloc((void **)&stage, sizeof(double) * 2 * (size_t)std::max<int64_t>(sh.n_tracers, 1)));
-    hipMemcpyAsync(stage, x, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyHostToDevice, p->stream);
-    hipMemcpyAsync(stage + sh.n_tracers, v, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyHostToDevice, p->stream);
-    dx = stage;
-    dv = stage + sh.n_tracers;
+    double *buf = fixed_stage;
+    if (!buf) {
+      HIPCHK(p, hipMalloc((void **)&stage, sizeof(double) * 2 * (size_t)std::max<int64_t>(sh.n_tracers, 1)));
+      buf = stage;
+    }
+    hipMemcpyAsync(buf, x, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyHostToDevice, p->stream);
+    hipMemcpyAsync(buf + sh.n_tracers, v, sizeof(double) * (size_t)sh.n_tracers, hipMemcpyHostToDevice, p->stream);
+    dx = buf;
+    dv = buf + sh.n_tracers;
   }
   hipError_t e = hipMemcpyAsync(p->inst + slot, &I, sizeof(I), hipMemcpyHostToDevice, p->stream);
   // positions and velocities only: the layout and the charges stay
@@ -1681,6 +1723,27 @@ sic_status sic_get_state(sic_sim *sim, double *x, double *v_half, int64_t *step,
 sic_status sic_set_state(sic_sim *sim, int64_t step, const double *x, const double *v_half, int32_t mem_kind) {
   if (!sim) return SIC_EINVAL;
   return pool_set_state(sim->pool, 0, step, x, v_half, mem_kind);
+}
+
+sic_status sic_set_state_noalloc(sic_sim *sim, int64_t step, const double *x, const double *v_half,
+                                 int32_t mem_kind) {
+  if (!sim) return SIC_EINVAL;
+  Pool *p = sim->pool;
+  double *stage = nullptr;
+  if (mem_kind == SIC_MEM_HOST) {
+    if (p->slots[0].n_tracers > (int64_t)SIC_NOALLOC_MAX_TRACERS)
+      return fail(p, SIC_EINVAL,
+                  "sic_set_state_noalloc: host inputs of more than SIC_NOALLOC_MAX_TRACERS tracers (use sic_set_state "
+                  "or device inputs)");
+    int cur = 0;
+    HIPCHK(p, hipGetDevice(&cur));
+    if (cur != p->device) HIPCHK(p, hipSetDevice(p->device));
+    const hipError_t e = scratch_address(p->device, &stage);
+    if (cur != p->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess)
+      return fail(p, SIC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  return pool_set_state(p, 0, step, x, v_half, mem_kind, stage);
 }
 
 sic_status sic_refine(sic_sim *sim, double l_max, int64_t *inserted) {
