@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-simulation set-ups")
+    ap.add_argument("--no-refine", action="store_true", help="skip the refinement run")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="CPU work of the oracle baseline (core-seconds)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="worker processes for the oracle (0: the host share)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape with the autotuner first")
@@ -224,6 +225,46 @@ def time_single_configs(B, I, torch):
         log(f"single: {name}: {1e3 * ms / p.n_steps:.1f} us/step, {n * p.n_steps / (ms * 1e-3):.3e} tracer-updates/s")
     torch.cuda.empty_cache()
     return out
+
+
+def time_refinement(B, I, torch, steps=700, tail=50):
+    """The refinement experiment of section 2.6 (two cold beams, 10 tracers
+    per cell per stream, 100 cells, dt 0.1) with refinement at one cell after
+    every move, all ``steps`` in one sic_step call (the passes run on the
+    device); then the same final state stepped without refinement, for the
+    cost of a refining step against a plain one at the same tracer count."""
+    p = I.refinement_two_stream(n_steps=steps)
+    dx = p.L / p.n_cells
+    cap = 4_000_000
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    with B.Simulation(p, l_max=dx, max_tracers=cap, history_rows=steps + 8) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps - tail)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.step(tail)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        nt, total = s.layout()
+        x, v, step = s.state()
+        c = s.charges()
+    with B.Simulation(p, seg_charges=p.seg_charges, max_tracers=total, history_rows=64) as s2:
+        s2.load_state(step, nt, x, v, c)
+        s2.step(1)
+        e0, e1 = ev(), ev()
+        e0.record()
+        s2.step(tail)
+        e1.record()
+        e1.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+    torch.cuda.empty_cache()
+    refining_us = 1e6 * (t2 - t1) / tail
+    plain_us = 1e3 * plain_ms / tail
+    return {"workload": f"section 2.6 two-stream refinement run, l_max = 1 cell, {steps} steps in one call",
+            "steps": steps, "tracers_start": p.total_tracers, "tracers_end": int(total),
+            "seconds": t2 - t0, "us_per_step_last_refining": refining_us,
+            "us_per_step_plain_same_state": plain_us, "refining_over_plain": refining_us / plain_us}
 
 
 DEPOSIT_BYTES_PER_TRACER = 8   # the position word, read once
@@ -441,6 +482,13 @@ def main():
 
     single = None if args.no_single else time_single_configs(B, I, torch)
 
+    refine = None
+    if not args.no_refine:
+        refine = time_refinement(B, I, torch)
+        log(f"refinement: {refine['seconds']:.3f} s for {refine['steps']} steps ({refine['tracers_start']} -> "
+            f"{refine['tracers_end']} tracers); last steps {refine['us_per_step_last_refining']:.1f} us refining vs "
+            f"{refine['us_per_step_plain_same_state']:.1f} us plain")
+
     plain = None
     if not args.no_plain:
         rng = np.random.default_rng(7)
@@ -492,6 +540,7 @@ def main():
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
         "deposit": deposit,
         "single": single,
+        "refinement": refine,
         "plain": plain,
         "serving": serve,
         "cpu_baseline": cpu,

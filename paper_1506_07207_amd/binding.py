@@ -540,8 +540,11 @@ class Simulation:
                           max_tracers=max_tracers)
 
     def step(self, n):
-        sic_step(self.h, n)
-        self._refresh_count()
+        try:
+            sic_step(self.h, n)
+        finally:
+            # refinement may have grown the sheets, also when a later pass failed
+            self._refresh_count()
 
     def _refresh_count(self):
         """Tracer total after refinement may have grown the sheets."""

@@ -160,6 +160,16 @@ struct Pool {
   double *ref_v = nullptr;
   uint64_t *ref_c = nullptr;
   int64_t ref_stage_cap = 0;
+  // device-side refinement of a single simulation (allocated on first use)
+  bool dev_refine = false;       // steps are refining on the device (host layout mirror stale)
+  bool dr_items = false;         // slot 0's work items are laid out for its whole reservation
+  int32_t *dr_nt = nullptr;      // per sheet: tracers now
+  int32_t *dr_closed = nullptr;  // per sheet
+  double *dr_q = nullptr;        // per sheet
+  int64_t *dr_work = nullptr;    // plan scratch, 3 n_sheets + 3
+  int32_t *dr_state = nullptr;   // RefineState words
+  int64_t *dr_in_off = nullptr;  // per chunk of the reservation: first staging index
+  int32_t dr_sheets = 0, dr_chunks = 0;
 
   std::vector<SlotHost> slots;
   ChunkAllocator alloc;       // tracer chunks
@@ -170,7 +180,8 @@ struct Pool {
   sic_tuning tune{};  // requested (0 = automatic)
   int block = kDefaultBlock, grid = kDefaultGrid, tile = kMinTile;
   int solve_grid = 1;  // solve workgroups of a whole-pool step: live slot indices, rounded up
-  std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;  // (steps, parity, grid, solve grid)
+  // (steps, parity, grid, solve grid, device refinement: the launches then skip an inactive slot)
+  std::map<std::tuple<int64_t, int, int, int, int>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_objs;
   bool timing = false;
   double t_tracer = 0.0, t_solve = 0.0;
@@ -262,7 +273,8 @@ void pool_free(Pool *p) {
                   p->links,     p->chunks,   p->items,    p->n_items,  p->inst,      p->slot_items,
                   p->partials,  p->meshP,    p->meshD,    p->meshR,    p->meshE,     p->meshRho,
                   p->hist,      p->done,     p->slot_ids, p->segq,     p->cedge,     p->edge_prev,
-                  p->ref_cnt,   p->ref_mask, p->ref_off,  p->ref_w,    p->ref_v,     p->ref_c};
+                  p->ref_cnt,   p->ref_mask, p->ref_off,  p->ref_w,    p->ref_v,     p->ref_c,
+                  p->dr_nt,     p->dr_closed, p->dr_q,    p->dr_work,  p->dr_state,  p->dr_in_off};
   for (void *b : bufs)
     if (b) hipFree(b);
   if (p->cap) hipStreamDestroy(p->cap);
@@ -461,6 +473,7 @@ sic_status upload_item_count(Pool *p) {
 // Lays out the work items of one slot in the item arena and uploads them.
 sic_status place_slot_items(Pool *p, int32_t slot) {
   SlotHost &s = p->slots[slot];
+  p->dr_items = false;
   const int tile = slot_tile(p, s.n_chunks);
   p->tile = tile;
   const int32_t n = (s.n_chunks + tile - 1) / tile;
@@ -686,7 +699,9 @@ TracerArgs tracer_args(Pool *p, int mode, int slot) {
   a.cedge = p->cedge;
   a.mesh_cells = p->max_cells;
   a.tile_cap = p->tile;
-  a.respect_active = (p->batch && !one) ? 1 : 0;
+  // batches skip finished slots; a single simulation refining on the device
+  // is made inactive when a pass would exceed its capacity
+  a.respect_active = ((p->batch || p->dev_refine) && !one) ? 1 : 0;
   return a;
 }
 
@@ -705,7 +720,7 @@ SolveArgs solve_args(Pool *p, int flags, int slot) {
   a.hist = p->hist;
   a.done = p->done;
   a.flags = flags;
-  a.respect_active = (p->batch && slot < 0) ? 1 : 0;
+  a.respect_active = ((p->batch || p->dev_refine) && slot < 0) ? 1 : 0;
   return a;
 }
 
@@ -740,7 +755,7 @@ sic_status enqueue_fused(Pool *p, hipStream_t st) {
 }
 
 sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
-  auto key = std::make_tuple(k, p->parity, p->grid, p->solve_grid);
+  auto key = std::make_tuple(k, p->parity, p->grid, p->solve_grid, p->dev_refine ? 1 : 0);
   auto it = p->graphs.find(key);
   if (it != p->graphs.end()) {
     *out = it->second;
@@ -1570,6 +1585,235 @@ sic_status sim_push(Pool *p) {
   return SIC_OK;
 }
 
+// ---- refinement on the device (single simulation) ----
+//
+// Every step: the fused step and its solve, then a marking pass, the plan
+// (flat staging offsets, new sheet sizes, capacity), the scatter into the
+// flat staging, the new layout (descriptors, links, charge edges, work
+// items), the re-ingest, and a deposit and solve of the refined state - each
+// launch reading the counts the previous ones left on the device, the
+// launches sized for the simulation's reservation, and the ones after the
+// plan doing nothing when no segment was split.  No host round trip per
+// step: the host layout is brought up to date once at the end.
+
+// Work items for the whole reservation (tile fixed for it), the first
+// ceil(n_chunks / tile) of them live; the rest are written by the device as
+// the simulation grows.
+sic_status place_slot_items_reserved(Pool *p, int32_t slot) {
+  SlotHost &s = p->slots[slot];
+  sic_status st = clear_slot_items(p, slot);
+  if (st != SIC_OK) return st;
+  const int tile = slot_tile(p, s.n_chunks_res);
+  p->tile = tile;
+  const int32_t cap = (s.n_chunks_res + tile - 1) / tile;
+  const int32_t now = (s.n_chunks + tile - 1) / tile;
+  const int64_t ib = p->item_alloc.alloc(cap);
+  if (ib < 0) return fail(p, SIC_EBUSY, "work-item arena full");
+  std::vector<Item> its((size_t)cap);
+  for (int32_t k = 0; k < cap; ++k) {
+    its[k].inst = k < now ? slot : -1;
+    its[k].chunk_begin = s.chunk_begin + k * tile;
+    its[k].chunk_end = s.chunk_begin + std::min(s.n_chunks, (k + 1) * tile);
+    its[k].pad = 0;
+  }
+  s.item_begin = (int32_t)ib;
+  s.n_items = cap;  // the range held (released as a whole)
+  p->slot_items_h[slot] = make_int2((int32_t)ib, cap);  // grids cover the reservation
+  const int2 live = make_int2((int32_t)ib, now);
+  HIPCHK(p, hipMemcpyAsync(p->items + ib, its.data(), sizeof(Item) * (size_t)cap, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->slot_items + slot, &live, sizeof(int2), hipMemcpyHostToDevice, p->stream));
+  st = upload_item_count(p);  // the host high-water mark (grid) covers the reservation
+  if (st != SIC_OK) return st;
+  const int32_t walk = (int32_t)ib + now;  // the kernels walk the live items only
+  HIPCHK(p, hipMemcpyAsync(p->n_items, &walk, sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  p->dr_items = true;
+  return SIC_OK;
+}
+
+sic_status dev_refine_begin(Pool *p) {
+  SlotHost &sh = p->slots[0];
+  sic_status st = ensure_refine_scratch(p, sh.max_tracers);
+  if (st != SIC_OK) return st;
+  const int32_t S = (int32_t)sh.n_tracers_s.size();
+  if (p->dr_sheets < S || p->dr_chunks < sh.n_chunks_res) {
+    for (void *b : {(void *)p->dr_nt, (void *)p->dr_closed, (void *)p->dr_q, (void *)p->dr_work, (void *)p->dr_state,
+                    (void *)p->dr_in_off})
+      if (b) hipFree(b);
+    p->dr_nt = p->dr_closed = p->dr_state = nullptr;
+    p->dr_q = nullptr;
+    p->dr_work = p->dr_in_off = nullptr;
+    p->dr_sheets = p->dr_chunks = 0;
+    HIPCHK(p, dalloc(&p->dr_nt, (size_t)S));
+    HIPCHK(p, dalloc(&p->dr_closed, (size_t)S));
+    HIPCHK(p, dalloc(&p->dr_q, (size_t)S));
+    HIPCHK(p, dalloc(&p->dr_work, 3 * (size_t)S + 3));
+    HIPCHK(p, dalloc(&p->dr_state, (size_t)kRefWords));
+    HIPCHK(p, dalloc(&p->dr_in_off, (size_t)sh.n_chunks_res));
+    p->dr_sheets = S;
+    p->dr_chunks = sh.n_chunks_res;
+  }
+  int32_t stw[kRefWords] = {};
+  stw[kRefChunks] = sh.n_chunks;
+  HIPCHK(p, hipMemcpyAsync(p->dr_nt, sh.n_tracers_s.data(), sizeof(int32_t) * (size_t)S, hipMemcpyHostToDevice,
+                           p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->dr_closed, sh.closed_s.data(), sizeof(int32_t) * (size_t)S, hipMemcpyHostToDevice,
+                           p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->dr_q, sh.q_s.data(), sizeof(double) * (size_t)S, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->dr_state, stw, sizeof(stw), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (!p->dr_items) {  // kept from an earlier call unless the host laid the slot out since
+    const int tile0 = p->tile, grid0 = p->grid;
+    st = place_slot_items_reserved(p, 0);
+    if (st != SIC_OK) return st;
+    if (p->tile != tile0 || p->grid != grid0) destroy_graphs(p);
+  }
+  p->dev_refine = true;
+  return SIC_OK;
+}
+
+// The host mirror of the layout after device refinement: the sheets' sizes
+// come back and the layout is rebuilt as the host builds it (the same
+// content; uploaded again, which also sizes the host's chunk offsets); the
+// work items stay laid out for the reservation, so the next refining call
+// reuses them and its captured step.  Returns SIC_ENOMEM when a pass was
+// refused for capacity.
+sic_status dev_refine_end(Pool *p) {
+  SlotHost &sh = p->slots[0];
+  p->dev_refine = false;
+  std::vector<int32_t> nt(sh.n_tracers_s.size());
+  int32_t stw[kRefWords];
+  HIPCHK(p, hipMemcpyAsync(nt.data(), p->dr_nt, sizeof(int32_t) * nt.size(), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipMemcpyAsync(stw, p->dr_state, sizeof(stw), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  int64_t n_tr = 0;
+  for (int32_t t : nt) n_tr += t;
+  Layout L;
+  build_layout(0, sh.chunk_begin, nt, sh.closed_s, sh.q_s, sh.q_scale, p->prec != kFP64, &L);
+  sh.n_tracers = n_tr;
+  sh.n_tracers_s = nt;
+  sh.chunk_in_off = L.in_off;
+  sh.n_chunks = (int32_t)L.cd.size();
+  hipError_t e = upload_layout(p, sh, sh.chunk_begin, L);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("layout upload: ") + hipGetErrorString(e));
+  sic_status st = SIC_OK;
+  if (stw[kRefHalt] != 0) {
+    // the pass that did not fit inserted nothing; the simulation stays at
+    // that step, active again for the caller
+    InstDesc I;
+    st = read_inst(p, 0, &I);
+    if (st != SIC_OK) return st;
+    I.active = 1;
+    HIPCHK(p, hipMemcpyAsync(p->inst, &I, sizeof(I), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    return fail(p, SIC_ENOMEM, "refinement exceeds the tracer capacity");
+  }
+  return SIC_OK;
+}
+
+// One refinement pass of slot 0 on the device, after its fused step.
+sic_status dev_refine_pass(Pool *p, double l_max) {
+  SlotHost &sh = p->slots[0];
+  RefineArgs ra;
+  ra.chunks = p->chunks;
+  ra.inst = p->inst;
+  ra.xs = p->xs;
+  ra.vs = p->vs;
+  ra.segq = p->segq;
+  ra.chunk_begin = sh.chunk_begin;
+  ra.n_chunks = sh.n_chunks_res;
+  ra.l_max = l_max;
+  ra.cnt = p->ref_cnt;
+  ra.mask = p->ref_mask;
+  ra.out_off = p->ref_off;
+  ra.w_out = p->ref_w;
+  ra.v_out = p->ref_v;
+  ra.c_out = p->ref_c;
+  ra.state = p->dr_state;
+  RefinePlanArgs pa;
+  pa.chunks = p->chunks;
+  pa.links = p->order == 1 ? p->links : nullptr;
+  pa.edge_prev = p->edge_prev;
+  pa.in_off = p->dr_in_off;
+  pa.items = p->items;
+  pa.slot_items = p->slot_items;
+  pa.n_items = p->n_items;
+  pa.inst = p->inst;
+  pa.cnt = p->ref_cnt;
+  pa.out_off = p->ref_off;
+  pa.nt = p->dr_nt;
+  pa.closed = p->dr_closed;
+  pa.q = p->dr_q;
+  pa.work = p->dr_work;
+  pa.state = p->dr_state;
+  pa.max_tracers = sh.max_tracers;
+  pa.q_scale = sh.q_scale;
+  pa.n_sheets = (int32_t)sh.n_tracers_s.size();
+  pa.chunk_begin = sh.chunk_begin;
+  pa.chunk_cap = sh.n_chunks_res;
+  pa.tile = p->tile;
+  pa.slot = 0;
+  pa.item_begin = sh.item_begin;
+  pa.order = p->order;
+  pa.fixed = p->prec != kFP64 ? 1 : 0;
+  LAUNCHCHK(p, launch_refine_mark(p->prec, ra, p->stream));
+  LAUNCHCHK(p, launch_refine_plan(pa, p->stream));
+  LAUNCHCHK(p, launch_refine_scatter(p->prec, ra, p->stream));
+  LAUNCHCHK(p, launch_refine_layout(pa, p->stream));
+  IngestArgs ia;
+  ia.x_in = nullptr;
+  ia.w_in = p->ref_w;
+  ia.v_in = p->ref_v;
+  ia.c_in = nullptr;
+  ia.cw_in = p->ref_c;
+  ia.segq = p->segq;
+  ia.q_scale = sh.q_scale;
+  ia.chunk_in_off = p->dr_in_off;
+  ia.chunk_begin = sh.chunk_begin;
+  ia.n_chunks = sh.n_chunks_res;
+  ia.chunks = p->chunks;
+  ia.inst = p->inst;
+  ia.xs = p->xs;
+  ia.vs = p->vs;
+  ia.halo = p->halo[p->parity];
+  ia.halo3 = p->halo3[p->parity];
+  ia.state = p->dr_state;
+  LAUNCHCHK(p, launch_ingest(p->prec, ia, p->stream));
+  LAUNCHCHK(p, launch_charge_edges(p->chunks, p->edge_prev, p->segq, p->cedge, sh.chunk_begin, sh.n_chunks_res,
+                                   p->stream, p->dr_state));
+  // the refined state's charge and field (only when a segment was split)
+  TracerArgs ta = tracer_args(p, kDeposit, 0);
+  ta.gate = p->dr_state + kRefInserted;
+  const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
+  LAUNCHCHK(p, launch_tracers(p->prec, kDeposit, p->order, p->seg, ta, grid_for(p, 0), p->block, lds, p->stream));
+  SolveArgs sa = solve_args(p, kHaveDeposit, 0);
+  sa.gate = p->dr_state + kRefInserted;
+  LAUNCHCHK(p, launch_solve(p->prec, sa, 1, p->max_cells, p->stream));
+  return SIC_OK;
+}
+
+sic_status sim_step_refining(Pool *p, int64_t n) {
+  SlotHost &sh = p->slots[0];
+  InstDesc I0;
+  sic_status st = read_inst(p, 0, &I0);
+  if (st == SIC_OK) st = dev_refine_begin(p);
+  const int parity0 = p->parity;
+  for (int64_t i = 0; i < n && st == SIC_OK; ++i) {
+    st = run_fused(p, 1);
+    if (st == SIC_OK) st = dev_refine_pass(p, sh.l_max);
+  }
+  if (!p->dev_refine) return st;
+  sic_status st2 = dev_refine_end(p);
+  // after a refused pass the remaining steps did nothing (the slot was
+  // inactive): the halo buffers alternate only for the steps that ran
+  InstDesc I1;
+  const sic_status st3 = read_inst(p, 0, &I1);
+  if (st3 == SIC_OK) p->parity = parity0 ^ (int)((I1.step - I0.step) & 1);
+  if (st != SIC_OK) return st;
+  return st2 != SIC_OK ? st2 : st3;
+}
+
 sic_status sim_step(Pool *p, int64_t n) {
   if (n < 0) return fail(p, SIC_EINVAL, "n_steps < 0");
   SlotHost &sh = p->slots[0];
@@ -1581,12 +1825,15 @@ sic_status sim_step(Pool *p, int64_t n) {
     // refinement after every move: the fused step deposits the moved
     // tracers; when a segment is split the refined state is deposited and
     // solved again, so the step's field and row are those of the refined
-    // sheets
-    for (int64_t i = 0; i < n && st == SIC_OK; ++i) {
-      st = run_fused(p, 1);
-      if (st == SIC_OK) st = pool_refine(p, 0, sh.l_max, nullptr);
+    // sheets (all on the device; the timing mode keeps the host passes)
+    if (p->timing) {
+      for (int64_t i = 0; i < n && st == SIC_OK; ++i) {
+        st = run_fused(p, 1);
+        if (st == SIC_OK) st = pool_refine(p, 0, sh.l_max, nullptr);
+      }
+      return st;
     }
-    return st;
+    return sim_step_refining(p, n);
   }
   if (p->order == 0 && !p->timing && sh.n_chunks <= resident_max_chunks()) return run_resident(p, n);
   return run_fused(p, n);

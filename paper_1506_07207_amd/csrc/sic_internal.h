@@ -6,8 +6,10 @@
 // empty), so a wavefront never straddles two sheets.  State is two arrays of
 // 8-byte words per tracer slot:
 //   word 0: x (float64)                      - SIC_FP64
-//           cell (int32, low) | offset (high) - split forms (offset is a
-//           float32 in [0,1) or a uint32 fraction of a cell)
+//           index (low 32 bits) | offset (high) - split forms: U32 the cell
+//           and a uint32 fraction of it; F32 an index of 2^-20-cell
+//           sub-cells (cell = index >> 20) and a float32 offset in [0, 1)
+//           of the sub-cell
 //   word 1: v (float64)
 // Every chunk also keeps a copy of its first tracer's state in a "halo"
 // array.  A step that moves tracers and deposits their new positions in the
@@ -124,6 +126,7 @@ struct TracerArgs {
   int32_t mesh_cells;      // LDS capacity in cells (max n_cells of the pool)
   int32_t tile_cap;        // LDS capacity in chunks per work item
   int32_t respect_active;  // skip slots with active == 0
+  const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
 };
 
 struct SolveArgs {
@@ -141,6 +144,7 @@ struct SolveArgs {
   int32_t flags;
   int32_t respect_active;
   int32_t order;             // deposit order of the pool (0, 1 or 2); R exists only for 1
+  const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
 };
 
 struct IngestArgs {
@@ -160,6 +164,8 @@ struct IngestArgs {
   double *vs;
   double2 *halo;
   double2 *halo3;  // order 1 (NULL otherwise)
+  const int32_t *state = nullptr;  // device refinement: skip unless state[kRefInserted] > 0, chunk
+                                   // count state[kRefChunks] (the launch covers the capacity)
 };
 
 struct ExtractArgs {
@@ -195,6 +201,46 @@ struct RefineArgs {
   uint64_t *w_out;
   double *v_out;
   uint64_t *c_out;
+  const int32_t *state = nullptr;  // device refinement: chunk count state[kRefChunks]; the marking pass
+                                   // skips after a halt, the scatter unless state[kRefInserted] > 0
+};
+
+// Refinement done entirely on the device (one simulation, steps in a row):
+// int32 words of its state.  kRefChunks: chunks of the slot now;
+// kRefInserted: tracers the last pass inserted (0: nothing to re-lay out);
+// kRefHalt: set when a pass would exceed the capacity (sticky; the slot is
+// made inactive, so the following steps do nothing); kRefNextChunks: chunks
+// after the pending re-layout.
+enum RefineState : int { kRefChunks = 0, kRefInserted = 1, kRefHalt = 2, kRefNextChunks = 3, kRefWords = 8 };
+
+// The re-layout of one simulation after a refinement pass, planned and
+// written on the device (the counterpart of the host's layout building).
+struct RefinePlanArgs {
+  ChunkDesc *chunks;       // pool descriptors; the slot's range is rewritten
+  int2 *links;             // order 1 (NULL otherwise)
+  int64_t *edge_prev;      // per chunk: slot of the tracer before its first one
+  int64_t *in_off;         // per chunk of the range: first index in the flat staging
+  Item *items;             // the slot's item range (room for the capacity)
+  int2 *slot_items;        // per slot: (first item, item count)
+  int32_t *n_items;        // item count the tracer kernel walks
+  InstDesc *inst;
+  const int32_t *cnt;      // per chunk of the range: segments to split
+  int64_t *out_off;        // per chunk of the range: first index in the flat staging
+  int32_t *nt;             // per sheet: tracers now
+  const int32_t *closed;   // per sheet
+  const double *q;         // per sheet: charge kept in the descriptors
+  int64_t *work;           // 3 n_sheets + 3 entries (per sheet: new count, new first chunk, flat start)
+  int32_t *state;          // RefineState words
+  int64_t max_tracers;
+  double q_scale;
+  int32_t n_sheets;
+  int32_t chunk_begin;
+  int32_t chunk_cap;       // chunks reserved for the slot
+  int32_t tile;            // chunks per work item
+  int32_t slot;
+  int32_t item_begin;
+  int32_t order;
+  int32_t fixed;           // split forms: descriptors carry fixed-point charges
 };
 
 // Launchers (sic_kernels.hip).  All return hipError_t as int.
@@ -213,7 +259,7 @@ int launch_copy_bench(const double *src, double *dst, int64_t n, int grid, void 
 // Charge edges of chunks [chunk_begin, chunk_begin + n_chunks): prev_slot[c]
 // is the slot of the tracer before chunk c's first one (-1: none).
 int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const uint64_t *segq, uint64_t *cedge,
-                        int32_t chunk_begin, int32_t n_chunks, void *stream);
+                        int32_t chunk_begin, int32_t n_chunks, void *stream, const int32_t *state = nullptr);
 // A small simulation's n_steps fused steps (push, deposit, solve) in one
 // launch of one workgroup; chunks [chunk_begin, chunk_begin + n_chunks) of
 // slot 0, constant segments.  a.halo_out receives the first-tracer halos of
@@ -221,7 +267,13 @@ int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const
 int resident_max_chunks();
 int launch_resident(int prec, bool seg, const TracerArgs &a, const SolveArgs &sa, int chunk_begin, int n_chunks,
                     int n_cells, int64_t n_steps, void *stream);
+// With a.state the launches cover a.n_chunks chunks (the capacity) and read
+// the count from the device.
 int launch_refine_mark(int prec, const RefineArgs &a, void *stream);
 int launch_refine_scatter(int prec, const RefineArgs &a, void *stream);
+// Device re-layout: the plan (one workgroup) and the descriptor/item writer
+// (covers chunk_cap chunks).
+int launch_refine_plan(const RefinePlanArgs &a, void *stream);
+int launch_refine_layout(const RefinePlanArgs &a, void *stream);
 
 }  // namespace sic

@@ -876,6 +876,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
                          : reinterpret_cast<uint64_t *>(sHalo + a.tile_cap);  // per-segment charges
   double *sRed = reinterpret_cast<double *>(sEdge + (SEG ? 2 * a.tile_cap : 0));  // 3 x 16 waves
 
+  if (a.gate != nullptr && *a.gate <= 0) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -905,6 +906,35 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     const int cb = item.chunk_begin;
     const int nch = item.chunk_end - item.chunk_begin;
 
+    // Loads and stores are unconditional (a chunk always has 64 slots; the
+    // padding slots of a sheet's last chunk are read and written back
+    // unchanged), so the only branches around memory operations are uniform.
+    // The state is streamed once per step: non-temporal loads and stores
+    // keep it from displacing the meshes and tables in the caches.
+    auto load_state = [&](int kk, uint64_t &xw, double &v, uint64_t &cw) {
+      // past the item's last chunk every lane reads the item's first slot: the
+      // loads are still issued, so the count of loads in flight is the same at
+      // every stage and the wait before a stage leaves the later ones in flight
+      const size_t s = kk < nch ? (size_t)(cb + kk) * kChunk + lane : (size_t)cb * kChunk;
+      xw = __builtin_nontemporal_load(a.xs + s);
+      if constexpr (kField) v = __builtin_nontemporal_load(a.vs + s);  // a deposit alone needs no velocity
+      if constexpr (kNeedQ) cw = a.segq[s];
+    };
+    // kPrefetch chunks in flight per wavefront, in fixed registers (the
+    // loop is fully unrolled over them).  The first ones are issued before
+    // the item's tables are staged: they need only the item's chunk range,
+    // so their latency overlaps the staging's.
+    uint64_t xr[kPrefetch], cr_[kPrefetch];
+    double vr[kPrefetch];
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      xr[j] = cr_[j] = 0;
+      vr[j] = 0.0;
+      load_state(wave + j * nwaves, xr[j], vr[j], cr_[j]);
+      // issue in stage order, as the loop does: the wait before a stage's
+      // first use then leaves the later stages' loads in flight
+      __builtin_amdgcn_sched_barrier(0);
+    }
     // Stage the item's tables in LDS: one pass of global reads per item
     // instead of dependent reads per chunk.
     for (int i = tid; i < g.nc; i += blockDim.x) {
@@ -923,6 +953,11 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     }
     for (int i = tid; i < nch; i += blockDim.x) {
       sDesc[i] = a.chunks[cb + i];
+      // the next chunk's halo, read with the descriptor: it is the partner
+      // of every chunk but a sheet's last (checked below)
+      if constexpr (kDep && !kLin) {
+        if (i + 1 < nch) sHalo[i] = a.halo_in[cb + i + 1];
+      }
       if constexpr (kNeedQ) {
         sEdge[2 * i] = a.cedge[2 * (size_t)(cb + i)];
         sEdge[2 * i + 1] = a.cedge[2 * (size_t)(cb + i) + 1];
@@ -977,7 +1012,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           sPrevNb[i] = prev;
           sNextNb[i] = next;
         } else if (pc >= 0) {
-          double2 h = a.halo_in[pc];
+          double2 h = (pc == cb + i + 1 && i + 1 < nch) ? sHalo[i] : a.halo_in[pc];
           if constexpr (kMove) {
             // the partner's move, from its state before this step: done here
             // once per chunk by one thread rather than by a whole wavefront
@@ -998,20 +1033,6 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     // the next two chunks is in flight while the current one is processed
     // (moving a register whose load is pending would force a wait).
     double ke = 0.0, mom = 0.0, ms = 0.0;
-    // Loads and stores are unconditional (a chunk always has 64 slots; the
-    // padding slots of a sheet's last chunk are read and written back
-    // unchanged), so the only branches around memory operations are uniform.
-    // The state is streamed once per step: non-temporal loads and stores
-    // keep it from displacing the meshes and tables in the caches.
-    auto load_state = [&](int kk, uint64_t &xw, double &v, uint64_t &cw) {
-      // past the item's last chunk every lane reads the item's first slot: the
-      // loads are still issued, so the count of loads in flight is the same at
-      // every stage and the wait before a stage leaves the later ones in flight
-      const size_t s = kk < nch ? (size_t)(cb + kk) * kChunk + lane : (size_t)cb * kChunk;
-      xw = __builtin_nontemporal_load(a.xs + s);
-      if constexpr (kField) v = __builtin_nontemporal_load(a.vs + s);  // a deposit alone needs no velocity
-      if constexpr (kNeedQ) cw = a.segq[s];
-    };
     auto process = [&](int kk, uint64_t xw, double v, uint64_t cw) {
       const ChunkDesc ch = sDesc[kk];
       const int n_valid = __builtin_amdgcn_readfirstlane(ch.n_valid);
@@ -1161,19 +1182,6 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         }
       }
     };
-    // kPrefetch chunks in flight per wavefront, in fixed registers (the
-    // loop is fully unrolled over them).
-    uint64_t xr[kPrefetch], cr_[kPrefetch];
-    double vr[kPrefetch];
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
-      xr[j] = cr_[j] = 0;
-      vr[j] = 0.0;
-      load_state(wave + j * nwaves, xr[j], vr[j], cr_[j]);
-      // issue in stage order, as the loop does: the wait before a stage's
-      // first use then leaves the later stages' loads in flight
-      __builtin_amdgcn_sched_barrier(0);
-    }
     for (int k = wave; k < nch; k += kPrefetch * nwaves) {
 #pragma unroll
       for (int j = 0; j < kPrefetch; ++j) {
@@ -1327,6 +1335,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SEG ?
 k_deposit_faces(TracerArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
   extern __shared__ __align__(16) unsigned char smem[];
+  if (a.gate != nullptr && *a.gate <= 0) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1817,6 +1826,7 @@ template <int PREC, int CELLS>
 __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
   __shared__ double sWd[4];
+  if (a.gate != nullptr && *a.gate <= 0) return;
   const int slot = a.slot_list ? a.slot_list[blockIdx.x] : (int)blockIdx.x;
   InstDesc *Ip = a.inst + slot;
   if (!Ip->live) return;
@@ -2073,6 +2083,7 @@ __global__ void __launch_bounds__(NT) k_resident(TracerArgs a, SolveArgs sa, int
 template <int PREC>
 __global__ void __launch_bounds__(256) k_ingest(IngestArgs a) {
   const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a.state != nullptr && (a.state[kRefInserted] <= 0 || cl >= a.state[kRefChunks])) return;
   if (cl >= a.n_chunks) return;
   const int lane = threadIdx.x & 63;
   const int c = a.chunk_begin + cl;
@@ -2149,8 +2160,9 @@ __global__ void __launch_bounds__(256) k_extract(ExtractArgs a) {
 // its partner tracer.
 __global__ void __launch_bounds__(256) k_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot,
                                                       const uint64_t *segq, uint64_t *cedge, int32_t chunk_begin,
-                                                      int32_t n_chunks) {
+                                                      int32_t n_chunks, const int32_t *state) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (state != nullptr && (state[kRefInserted] <= 0 || i >= state[kRefChunks])) return;
   if (i >= n_chunks) return;
   const int c = chunk_begin + i;
   const int64_t pv = prev_slot[c];
@@ -2196,6 +2208,7 @@ __device__ __forceinline__ bool refine_segment(const RefineArgs &a, const ChunkD
 template <int PREC>
 __global__ void __launch_bounds__(256) k_refine_mark(RefineArgs a) {
   const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a.state != nullptr && (a.state[kRefHalt] != 0 || cl >= a.state[kRefChunks])) return;
   if (cl >= a.n_chunks) return;  // uniform per wavefront
   const int lane = threadIdx.x & 63;
   const int c = a.chunk_begin + cl;
@@ -2219,6 +2232,7 @@ __global__ void __launch_bounds__(256) k_refine_mark(RefineArgs a) {
 template <int PREC>
 __global__ void __launch_bounds__(256) k_refine_scatter(RefineArgs a) {
   const int cl = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a.state != nullptr && (a.state[kRefInserted] <= 0 || cl >= a.state[kRefChunks])) return;
   if (cl >= a.n_chunks) return;  // uniform per wavefront
   const int lane = threadIdx.x & 63;
   const int c = a.chunk_begin + cl;
@@ -2259,6 +2273,170 @@ __global__ void __launch_bounds__(256) k_refine_scatter(RefineArgs a) {
   a.w_out[out] = w;
   a.v_out[out] = v;
   a.c_out[out] = c0;
+}
+
+// Device re-layout after a marking pass (one simulation; the host's layout
+// building done on the device, so that refining steps need no round trip).
+// The plan, one workgroup: the flat staging offset of every chunk (the old
+// tracers plus the inserted ones, sheet-major), each sheet's new tracer
+// count, its first chunk in the new layout and its first staging index, and
+// the capacity check.  A pass that would exceed the capacity inserts nothing
+// and halts the simulation (inactive; the host reports it).
+__global__ void __launch_bounds__(1024) k_refine_plan(RefinePlanArgs a) {
+  __shared__ long long sW[16];
+  __shared__ long long sTot[2];
+  __shared__ int sOver;
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  int32_t *st = a.state;
+  if (st[kRefHalt] != 0) {
+    if (tid == 0) st[kRefInserted] = 0;
+    return;
+  }
+  if (tid == 0) sOver = 0;
+  const int n = st[kRefChunks];
+  long long carry = 0, inserted = 0;
+  for (int base = 0; base < n; base += nth) {
+    const int c = base + tid;
+    long long k = 0, v = 0;
+    if (c < n) {
+      k = a.cnt[c];
+      v = (long long)a.chunks[a.chunk_begin + c].n_valid + k;
+    }
+    const long long iv = block_incl_scan(v, sW);
+    if (c < n) a.out_off[c] = carry + iv - v;
+    if (tid == nth - 1) sTot[0] = iv;
+    const long long ik = block_incl_scan(k, sW);
+    if (tid == nth - 1) sTot[1] = ik;
+    __syncthreads();
+    carry += sTot[0];
+    inserted += sTot[1];
+    __syncthreads();
+  }
+  const long long total_new = carry;
+  const int S = a.n_sheets;
+  int64_t *newnt = a.work;
+  int64_t *first2 = a.work + S;  // S + 1 entries
+  int64_t *flat0 = a.work + 2 * S + 1;
+  long long old_first = 0, new_first = 0;
+  for (int base = 0; base < S; base += nth) {
+    const int s = base + tid;
+    long long och = 0, nch = 0, nn = 0, o0 = 0;
+    if (s < S) och = ((long long)a.nt[s] + kChunk - 1) / kChunk;
+    const long long io = block_incl_scan(och, sW);
+    if (s < S) {
+      const long long f0 = old_first + io - och, f1 = old_first + io;  // old chunks of sheet s
+      o0 = a.out_off[f0];
+      const long long o1 = f1 < n ? a.out_off[f1] : total_new;
+      nn = o1 - o0;
+      nch = (nn + kChunk - 1) / kChunk;
+      if (nn > 0x7fffffffll) sOver = 1;
+    }
+    const long long in2 = block_incl_scan(nch, sW);
+    if (s < S) {
+      newnt[s] = nn;
+      first2[s] = new_first + in2 - nch;
+      flat0[s] = o0;
+    }
+    if (tid == nth - 1) {
+      sTot[0] = io;
+      sTot[1] = in2;
+    }
+    __syncthreads();
+    old_first += sTot[0];
+    new_first += sTot[1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    first2[S] = new_first;
+    const bool over = sOver != 0 || total_new > a.max_tracers || new_first > a.chunk_cap;
+    if (over) {
+      st[kRefHalt] = 1;
+      st[kRefInserted] = 0;
+      a.inst[a.slot].active = 0;
+    } else {
+      st[kRefInserted] = (int32_t)(inserted < 0x7fffffffll ? inserted : 0x7fffffffll);
+      st[kRefNextChunks] = (int32_t)new_first;
+    }
+  }
+}
+
+// Writes the planned layout: per new chunk its descriptor (sheet charge,
+// fixed-point charge, valid count, partner chunk, open-sheet start), its
+// first staging index, the slot of the tracer before it (charge edges) and,
+// for piecewise-linear segments, its links; the slot's work items (runs of
+// tile chunks); the new counts.  Mirrors the host's layout building.
+__global__ void __launch_bounds__(256) k_refine_layout(RefinePlanArgs a) {
+  int32_t *st = a.state;
+  if (st[kRefInserted] <= 0) return;
+  const int S = a.n_sheets;
+  const int64_t *newnt = a.work;
+  const int64_t *first2 = a.work + S;
+  const int64_t *flat0 = a.work + 2 * S + 1;
+  const int n2 = st[kRefNextChunks];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  auto n_valid_of = [](long long n, long long k) { return (int32_t)min((long long)kChunk, n - k * kChunk); };
+  if (c < n2) {
+    int lo = 0, hi = S - 1;  // the sheet holding new chunk c: last s with first2[s] <= c
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first2[mid] <= c) lo = mid;
+      else hi = mid - 1;
+    }
+    const int s = lo;
+    const long long k = c - first2[s];
+    const long long n = newnt[s];
+    const long long nch = (n + kChunk - 1) / kChunk;
+    const int32_t first = a.chunk_begin + (int32_t)first2[s];
+    const bool cl = a.closed[s] != 0;
+    ChunkDesc d;
+    d.q = a.q[s];
+    d.q_fix = a.fixed ? (int64_t)llrint(a.q[s] * a.q_scale) : 0;
+    d.n_valid = n_valid_of(n, k);
+    d.inst = a.slot;
+    d.flags = (k == 0 && !cl) ? kChunkOpenStart : 0;
+    d.partner = (k + 1 < nch) ? (int32_t)(first + k + 1) : (cl ? first : -1);
+    a.chunks[first + k] = d;
+    a.in_off[c] = flat0[s] + k * kChunk;
+    if (a.edge_prev) {
+      int64_t pv = -1;
+      if (k > 0) pv = (int64_t)(first + k - 1) * kChunk + (kChunk - 1);
+      else if (cl) pv = (int64_t)(first + nch - 1) * kChunk + (n - (nch - 1) * kChunk - 1);
+      a.edge_prev[first + k] = pv;
+    }
+    if (a.links) {
+      int2 lk = make_int2(-1, -1);
+      if (!cl || n >= 3) {
+        if (k > 0) lk.x = (int32_t)(((first + k - 1) << 2) | kHaloLast);
+        else if (cl) lk.x = (int32_t)(((first + nch - 1) << 2) | kHaloLast);
+        if (d.partner >= 0) {
+          const long long pk = d.partner - first;
+          if (n_valid_of(n, pk) >= 2) {
+            lk.y = (d.partner << 2) | kHaloSecond;
+          } else {
+            const int32_t pp = (pk + 1 < nch) ? (int32_t)(first + pk + 1) : (cl ? first : -1);
+            if (pp >= 0) lk.y = (pp << 2) | kHaloFirst;
+          }
+        }
+      }
+      a.links[first + k] = lk;
+    }
+  }
+  const int n_items = (n2 + a.tile - 1) / a.tile;
+  if (c < n_items) {
+    Item it;
+    it.inst = a.slot;
+    it.chunk_begin = a.chunk_begin + c * a.tile;
+    it.chunk_end = a.chunk_begin + min(n2, (c + 1) * a.tile);
+    it.pad = 0;
+    a.items[a.item_begin + c] = it;
+  }
+  for (int s = c; s < S; s += gridDim.x * blockDim.x) a.nt[s] = (int32_t)newnt[s];
+  if (c == 0) {
+    st[kRefChunks] = n2;
+    a.slot_items[a.slot].y = n_items;
+    *a.n_items = a.item_begin + n_items;
+  }
 }
 
 template <int PREC>
@@ -2538,10 +2716,10 @@ int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const Inst
 }
 
 int launch_charge_edges(const ChunkDesc *chunks, const int64_t *prev_slot, const uint64_t *segq, uint64_t *cedge,
-                        int32_t chunk_begin, int32_t n_chunks, void *stream) {
+                        int32_t chunk_begin, int32_t n_chunks, void *stream, const int32_t *state) {
   if (n_chunks <= 0) return 0;
   hipLaunchKernelGGL(k_charge_edges, dim3((n_chunks + 255) / 256), dim3(256), 0, (hipStream_t)stream, chunks,
-                     prev_slot, segq, cedge, chunk_begin, n_chunks);
+                     prev_slot, segq, cedge, chunk_begin, n_chunks, state);
   return (int)hipGetLastError();
 }
 
@@ -2568,6 +2746,17 @@ int launch_refine_scatter(int prec, const RefineArgs &a, void *stream) {
     case kSplitU32: hipLaunchKernelGGL(k_refine_scatter<kSplitU32>, dim3(grid), dim3(256), 0, st, a); break;
     default: return (int)hipErrorInvalidValue;
   }
+  return (int)hipGetLastError();
+}
+
+int launch_refine_plan(const RefinePlanArgs &a, void *stream) {
+  hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_refine_layout(const RefinePlanArgs &a, void *stream) {
+  const int grid = std::max(1, (a.chunk_cap + 255) / 256);
+  hipLaunchKernelGGL(k_refine_layout, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -167,6 +167,76 @@ def test_refinement_run_matches_oracle():
     assert np.max(np.abs(h["total_charge"] - ref["hist"][:, 5])) < 1e-12 * ref["hist"][0, 5]
 
 
+def test_refinement_run_in_one_call_matches_oracle():
+    """The same run as one sic_step call: refinement runs on the device after
+    every move, with no host round trip between steps, and ends with the
+    oracle's sheets, field-energy history and total charge."""
+    p = I.refinement_two_stream(n_steps=340)
+    dx = p.L / p.n_cells
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, l_max=dx,
+                    capacity=200_000)
+    print(f"case refinement run in one call, oracle final count {ref['count'][-1]}", flush=True)
+    with B.Simulation(p, l_max=dx, max_tracers=200_000) as s:
+        s.step(p.n_steps)
+        h = s.diagnostics()["history"]
+        nt, tot = s.layout()
+        x, v, step = s.state()
+        c = s.charges()
+    assert step == p.n_steps and tot == ref["count"][-1]
+    assert np.array_equal(nt, ref["n_tracers"])
+    err = envelope_rel(h["W_E"], ref["hist"][:, 2], p.dt)
+    print(f"refinement run in one call: envelope error {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert np.max(np.abs(h["total_charge"] - ref["hist"][:, 5])) < 1e-12 * ref["hist"][0, 5]
+    assert np.array_equal(c, ref["c"])  # halved charges, exact in float64
+    assert np.max(periodic_diff(x, ref["x"], p.L)) < 1e-9 * p.L
+
+
+@pytest.mark.parametrize("prec", [B.SIC_FP64, B.SIC_SPLIT_U32])
+def test_refinement_in_one_call_equals_step_by_step(prec):
+    """Stepping 300 steps in one call (device refinement) and one step per
+    call give the same insertions and, in the split form, the same bits."""
+    p = I.refinement_two_stream(n_steps=300)
+    dx = p.L / p.n_cells
+    outs = []
+    for per_call in (p.n_steps, 1):
+        with B.Simulation(p, precision=prec, l_max=dx, max_tracers=200_000) as s:
+            for _ in range(p.n_steps // per_call):
+                s.step(per_call)
+            x, v, _ = s.state()
+            outs.append((s.layout()[0], x, v, s.charges(), s.diagnostics()["history"]["W_E"]))
+    (nt1, x1, v1, c1, W1), (nt2, x2, v2, c2, W2) = outs
+    assert np.array_equal(nt1, nt2) and np.array_equal(c1, c2)
+    if prec == B.SIC_FP64:
+        assert np.max(periodic_diff(x1, x2, p.L)) < 1e-10 * p.L
+        assert np.max(np.abs(W1 - W2) / np.max(W2)) < 1e-10
+    else:
+        assert np.array_equal(x1, x2) and np.array_equal(v1, v2) and np.array_equal(W1, W2)
+
+
+def test_refinement_over_capacity_during_steps_stops_there():
+    """A run whose refinement outgrows its capacity stops at the step whose
+    pass would not fit: that pass inserts nothing, sic_step reports
+    SIC_ENOMEM, and the simulation keeps the tracers of the last pass that
+    fitted, as the oracle's count history gives them."""
+    p = I.refinement_two_stream(n_steps=340)
+    dx = p.L / p.n_cells
+    ref = O.run_seg(p.L, p.n_cells, p.dt, p.n_tracers, p.closed, p.seg_charges, p.x0, p.v0, p.n_steps, l_max=dx,
+                    capacity=200_000)
+    cap = int(ref["count"][0] + (ref["count"][-1] - ref["count"][0]) // 2)
+    m = int(np.nonzero(ref["count"] > cap)[0][0])  # the first step whose pass does not fit
+    with B.Simulation(p, l_max=dx, max_tracers=cap) as s:
+        with pytest.raises(B.SicError) as e:
+            s.step(p.n_steps)
+        assert e.value.status == 2
+        x, v, step = s.state()
+        _, tot = s.layout()
+        assert step == m and tot == ref["count"][m - 1]
+        # the simulation is usable afterwards: a step without refinement room fails the same way
+        with pytest.raises(B.SicError):
+            s.step(1)
+
+
 def _envelope_errors(W, Wr, dt):
     P = int(math.ceil(2 * math.pi / dt))
     env = np.array([np.max(Wr[max(0, i - P): i + P + 1]) for i in range(len(Wr))])
