@@ -1712,8 +1712,9 @@ sic_status dev_refine_end(Pool *p) {
   return SIC_OK;
 }
 
-// One refinement pass of slot 0 on the device, after its fused step.
-sic_status dev_refine_pass(Pool *p, double l_max) {
+// One refinement pass of slot 0 on the device, after its fused step, on
+// stream st.
+sic_status dev_refine_pass(Pool *p, double l_max, hipStream_t st) {
   SlotHost &sh = p->slots[0];
   RefineArgs ra;
   ra.chunks = p->chunks;
@@ -1757,10 +1758,10 @@ sic_status dev_refine_pass(Pool *p, double l_max) {
   pa.item_begin = sh.item_begin;
   pa.order = p->order;
   pa.fixed = p->prec != kFP64 ? 1 : 0;
-  LAUNCHCHK(p, launch_refine_mark(p->prec, ra, p->stream));
-  LAUNCHCHK(p, launch_refine_plan(pa, p->stream));
-  LAUNCHCHK(p, launch_refine_scatter(p->prec, ra, p->stream));
-  LAUNCHCHK(p, launch_refine_layout(pa, p->stream));
+  LAUNCHCHK(p, launch_refine_mark(p->prec, ra, st));
+  LAUNCHCHK(p, launch_refine_plan(pa, st));
+  LAUNCHCHK(p, launch_refine_scatter(p->prec, ra, st));
+  LAUNCHCHK(p, launch_refine_layout(pa, st));
   IngestArgs ia;
   ia.x_in = nullptr;
   ia.w_in = p->ref_w;
@@ -1779,17 +1780,53 @@ sic_status dev_refine_pass(Pool *p, double l_max) {
   ia.halo = p->halo[p->parity];
   ia.halo3 = p->halo3[p->parity];
   ia.state = p->dr_state;
-  LAUNCHCHK(p, launch_ingest(p->prec, ia, p->stream));
+  LAUNCHCHK(p, launch_ingest(p->prec, ia, st));
   LAUNCHCHK(p, launch_charge_edges(p->chunks, p->edge_prev, p->segq, p->cedge, sh.chunk_begin, sh.n_chunks_res,
-                                   p->stream, p->dr_state));
+                                   st, p->dr_state));
   // the refined state's charge and field (only when a segment was split)
   TracerArgs ta = tracer_args(p, kDeposit, 0);
   ta.gate = p->dr_state + kRefInserted;
   const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
-  LAUNCHCHK(p, launch_tracers(p->prec, kDeposit, p->order, p->seg, ta, grid_for(p, 0), p->block, lds, p->stream));
+  LAUNCHCHK(p, launch_tracers(p->prec, kDeposit, p->order, p->seg, ta, grid_for(p, 0), p->block, lds, st));
   SolveArgs sa = solve_args(p, kHaveDeposit, 0);
   sa.gate = p->dr_state + kRefInserted;
-  LAUNCHCHK(p, launch_solve(p->prec, sa, 1, p->max_cells, p->stream));
+  LAUNCHCHK(p, launch_solve(p->prec, sa, 1, p->max_cells, st));
+  return SIC_OK;
+}
+
+// Graphs of k refining steps (fused step, solve, refinement pass), keyed
+// apart from the plain step graphs.
+sic_status get_refine_graph(Pool *p, int64_t k, double l_max, hipGraphExec_t *out) {
+  auto key = std::make_tuple(k, p->parity, p->grid, p->solve_grid, 2);
+  auto it = p->graphs.find(key);
+  if (it != p->graphs.end()) {
+    *out = it->second;
+    return SIC_OK;
+  }
+  const int parity0 = p->parity;
+  HIPCHK(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+  sic_status s = SIC_OK;
+  for (int64_t i = 0; i < k && s == SIC_OK; ++i) {
+    s = enqueue_fused(p, p->cap);
+    if (s == SIC_OK) s = dev_refine_pass(p, l_max, p->cap);
+  }
+  p->parity = parity0;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap, &g);
+  if (s != SIC_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(p, SIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  p->graph_objs.push_back(g);
+  p->graphs[key] = ex;
+  *out = ex;
   return SIC_OK;
 }
 
@@ -1799,9 +1836,15 @@ sic_status sim_step_refining(Pool *p, int64_t n) {
   sic_status st = read_inst(p, 0, &I0);
   if (st == SIC_OK) st = dev_refine_begin(p);
   const int parity0 = p->parity;
-  for (int64_t i = 0; i < n && st == SIC_OK; ++i) {
-    st = run_fused(p, 1);
-    if (st == SIC_OK) st = dev_refine_pass(p, sh.l_max);
+  while (n > 0 && st == SIC_OK) {
+    const int64_t k = std::min<int64_t>(n, kGraphSteps);
+    hipGraphExec_t ex;
+    st = get_refine_graph(p, k, sh.l_max, &ex);
+    if (st != SIC_OK) break;
+    const hipError_t e = hipGraphLaunch(ex, p->stream);
+    if (e != hipSuccess) st = fail(p, SIC_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    if (k & 1) p->parity ^= 1;
+    n -= k;
   }
   if (!p->dev_refine) return st;
   sic_status st2 = dev_refine_end(p);

@@ -2295,24 +2295,27 @@ __global__ void __launch_bounds__(1024) k_refine_plan(RefinePlanArgs a) {
   }
   if (tid == 0) sOver = 0;
   const int n = st[kRefChunks];
-  long long carry = 0, inserted = 0;
-  for (int base = 0; base < n; base += nth) {
-    const int c = base + tid;
-    long long k = 0, v = 0;
-    if (c < n) {
-      k = a.cnt[c];
-      v = (long long)a.chunks[a.chunk_begin + c].n_valid + k;
-    }
-    const long long iv = block_incl_scan(v, sW);
-    if (c < n) a.out_off[c] = carry + iv - v;
-    if (tid == nth - 1) sTot[0] = iv;
-    const long long ik = block_incl_scan(k, sW);
-    if (tid == nth - 1) sTot[1] = ik;
-    __syncthreads();
-    carry += sTot[0];
-    inserted += sTot[1];
-    __syncthreads();
+  // each thread sums a contiguous run of chunks, one block scan places the
+  // runs, then each thread writes its run's offsets
+  const int per = (n + nth - 1) / nth;
+  const int c0 = min(n, tid * per), c1 = min(n, c0 + per);
+  long long sv = 0, sk = 0;
+  for (int c = c0; c < c1; ++c) {
+    const long long k = a.cnt[c];
+    sv += (long long)a.chunks[a.chunk_begin + c].n_valid + k;
+    sk += k;
   }
+  const long long iv = block_incl_scan(sv, sW);
+  if (tid == nth - 1) sTot[0] = iv;
+  const long long ik = block_incl_scan(sk, sW);
+  if (tid == nth - 1) sTot[1] = ik;
+  long long run = iv - sv;
+  for (int c = c0; c < c1; ++c) {
+    a.out_off[c] = run;
+    run += (long long)a.chunks[a.chunk_begin + c].n_valid + a.cnt[c];
+  }
+  __syncthreads();
+  const long long carry = sTot[0], inserted = sTot[1];
   const long long total_new = carry;
   const int S = a.n_sheets;
   int64_t *newnt = a.work;
