@@ -38,10 +38,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(precision, instances):
+def profiled_traffic(precision, instances, tuning):
     """HBM bytes per tracer-kernel launch from the committed rocprofv3 counter
-    summary, valid only for the profiled workload and only while the kernel
-    source is the one that was profiled (None otherwise)."""
+    summary, valid only for the profiled workload, launch shape and window,
+    and only while the kernel source is the one that was profiled (None
+    otherwise)."""
     import hashlib
 
     if precision != "fp64" or instances != 4096:
@@ -54,6 +55,9 @@ def profiled_traffic(precision, instances):
     except OSError:
         return None
     if kv.get("kernel_source_sha256_16") != digest:
+        return None
+    shape = f"{tuning['tile_chunks']},{tuning['block_threads']},{tuning['grid_blocks']}"
+    if kv.get("launch_shape") != shape:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -80,7 +84,8 @@ def parse():
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement run")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="CPU work of the oracle baseline (core-seconds)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="worker processes for the oracle (0: the host share)")
-    ap.add_argument("--autotune", action="store_true", help="pick the launch shape with the autotuner first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time the default launch shape instead of the autotuner's pick")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
@@ -513,6 +518,9 @@ def main():
                          f"each the single-threaded FP64 oracle), 2 steps each, {secs:.1f} s of CPU work"}
         log(f"cpu oracle: {rate:.4e} tracer-updates/s")
 
+    traffic = None
+    if args.deposit_order == 0 and not args.segment_charges:
+        traffic = profiled_traffic(args.precision, args.instances, tuning)
     out = {
         "metric": METRIC,
         "value": value,
@@ -533,9 +541,7 @@ def main():
                    "deposit_order": args.deposit_order, "segment_charges": bool(args.segment_charges),
                    "tuning": tuning, "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": (profiled_traffic(args.precision, args.instances)
-                                                                    if args.deposit_order == 0 and not args.segment_charges
-                                                                    else None),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_tracers (move + deposit)", "kernel_ms": tr_ms, "solve_ms": so_ms,
                      "algorithmic_bytes": bytes_launch, "copy_gbps": copy_gbps},
         "deposit": deposit,

@@ -43,22 +43,26 @@ def _traffic_file(tmp_path, digest, value):
     return hashlib.sha256(b"// kernel source\n").hexdigest()[:16]
 
 
-def test_traffic_reported_only_for_the_profiled_source(tmp_path, monkeypatch):
+def test_traffic_reported_only_for_the_profiled_source_and_shape(tmp_path, monkeypatch):
     digest = _traffic_file(tmp_path, "0" * 16, 0)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.profiled_traffic("fp64", 4096) is None  # stale: another source was profiled
+    shape = {"tile_chunks": 256, "block_threads": 512, "grid_blocks": 131072}
+    assert bench.profiled_traffic("fp64", 4096, shape) is None  # stale: another source was profiled
     (tmp_path / "profiles" / "k_tracers_fp64_mixed4096_traffic.md").write_text(
-        "    kernel_source_sha256_16=%s\n    traffic_bytes_per_launch=123456789\n" % digest)
-    assert bench.profiled_traffic("fp64", 4096) == 123456789.0
-    # only for the workload and precision that were profiled
-    assert bench.profiled_traffic("split_u32", 4096) is None
-    assert bench.profiled_traffic("fp64", 512) is None
+        "    kernel_source_sha256_16=%s\n    launch_shape=256,512,131072\n"
+        "    traffic_bytes_per_launch=123456789\n" % digest)
+    assert bench.profiled_traffic("fp64", 4096, shape) == 123456789.0
+    # only for the workload, precision and launch shape that were profiled
+    assert bench.profiled_traffic("split_u32", 4096, shape) is None
+    assert bench.profiled_traffic("fp64", 512, shape) is None
+    assert bench.profiled_traffic("fp64", 4096, dict(shape, tile_chunks=128)) is None
 
 
 def test_committed_traffic_summary_is_machine_readable():
     path = os.path.join(ROOT, "profiles", "k_tracers_fp64_mixed4096_traffic.md")
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and " " not in line.strip())
     assert len(kv["kernel_source_sha256_16"]) == 16
+    assert len(kv["launch_shape"].split(",")) == 3
     assert float(kv["traffic_bytes_per_launch"]) > 0
 
 
