@@ -210,8 +210,9 @@ sic_status sic_load_state(sic_sim *sim, int64_t step, const int32_t *n_tracers, 
  * the newest row.  rho_out / E_out (NULL or n_cells doubles, host memory)
  * receive the charge density n_j - nbar and the field of the newest solve.
  * history_out (NULL or *history_len rows) receives the oldest-first rows still
- * in the ring; *history_len is set to the number of rows written (or, when
- * history_out is NULL, to the number available). */
+ * in the ring, from the step the simulation started at or its state was last
+ * set or loaded at; *history_len is set to the number of rows written (or,
+ * when history_out is NULL, to the number available). */
 sic_status sic_diagnostics(sic_sim *sim, sic_diag *out, double *rho_out, double *E_out, sic_diag *history_out,
                            int64_t *history_len);
 

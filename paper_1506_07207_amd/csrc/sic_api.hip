@@ -110,6 +110,9 @@ struct SlotHost {
   std::vector<int64_t> chunk_in_off;
   int64_t *d_in_off = nullptr;
   int state = kStale;
+  // the step the diagnostics history starts at: 0, or the step a state was
+  // set or loaded at (rows before it were never written by this simulation)
+  int64_t hist_from = 0;
   bool pending_push = false, pending_dep = false;
   bool reported = false;
 };
@@ -1094,6 +1097,7 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   sh.q_scale = q_scale;
   sh.l_max = cfg->l_max;
   sh.max_tracers = reserve_tr;
+  sh.hist_from = 0;
   sh.chunk_begin = (int32_t)cb;
   sh.n_chunks = (int32_t)n_ch;
   sh.n_chunks_res = (int32_t)n_res;
@@ -1358,7 +1362,7 @@ sic_status pool_diagnostics(Pool *p, int32_t slot, sic_diag *out, double *rho_ou
   if (st != SIC_OK) return st;
   const int64_t step = I.step;
   const int64_t cap = I.hist_cap;
-  const int64_t avail = std::min<int64_t>(step + 1, cap);
+  const int64_t avail = std::min<int64_t>(step + 1 - std::min(step, p->slots[slot].hist_from), cap);
   const DiagRow *H = p->hist + I.hist_off;
   if (out) {
     DiagRow r;
@@ -1509,6 +1513,7 @@ sic_status pool_load_state(Pool *p, int64_t step, const int32_t *n_tracers, cons
   }
   sic_status st = pool_relayout(p, 0, nt, dx, nullptr, dv, dc, nullptr, step, false);
   if (stage) hipFree(stage);
+  if (st == SIC_OK) sh.hist_from = step;
   return st;
 }
 
@@ -1548,6 +1553,7 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
   if (e != hipSuccess || e2 != hipSuccess || le != 0) return fail(p, SIC_EDEVICE, "set_state failed");
   sh.state = kStale;
   sh.pending_push = sh.pending_dep = false;
+  sh.hist_from = step;
   return SIC_OK;
 }
 

@@ -36,6 +36,9 @@ def test_set_state_noalloc_matches_set_state(prec):
         a = _state_after(p, prec, 30, x, v, noalloc=True)
         b = _state_after(p, prec, 30, x, v, noalloc=False)
         assert a[2] == b[2] == 30 and a[5] == b[5] == 35
+        # the history starts at the step the state was set at
+        for r in (a, b):
+            assert list(r[6]["history"]["step"]) == list(range(30, 36))
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         if prec == B.SIC_FP64:
             # float64 atomics may add in another order over the five steps
