@@ -171,11 +171,25 @@ sic_status sic_push(sic_sim *sim);
 /* n_steps full steps.  Each step moves the tracers with the current field,
  * deposits the new positions and solves the new field, so on return the field
  * is current for the new step.  If the field is stale it is brought up to date
- * first.  Steps run as captured HIP graphs; a small simulation (constant
- * segments, at most 32 chunks of 64 tracer slots) runs them in one launch of
- * a single workgroup instead (same arithmetic).  Async; with refinement on
- * (l_max > 0) each step also runs sic_refine, which synchronises. */
+ * first.  Steps run as captured HIP graphs of a tracer launch and a solve
+ * launch each (SIC_PATH_FUSED); a small simulation (constant segments, at
+ * most 32 chunks of 64 tracer slots) runs them in one launch of a single
+ * workgroup instead (SIC_PATH_RESIDENT; same arithmetic, and the same bits in
+ * the split forms).  Timing mode (sic_set_timing) always takes the fused
+ * path.  Async; with refinement on (l_max > 0) each step is followed by a
+ * refinement pass on the device (SIC_PATH_REFINING: graphs of steps and
+ * passes; the host reads the layout back when it needs it). */
 sic_status sic_step(sic_sim *sim, int64_t n_steps);
+
+enum {
+    SIC_PATH_NONE = -1,
+    SIC_PATH_FUSED = 0,
+    SIC_PATH_RESIDENT = 1,
+    SIC_PATH_REFINING = 2
+};
+/* The launch path of the last sic_step call on sim (SIC_PATH_NONE before
+ * any). */
+sic_status sic_last_step_path(const sic_sim *sim, int32_t *path);
 
 /* One refinement pass (section 2.6) over the current positions: every segment
  * longer than l_max (minimum-image length) gets a tracer at its centre, with
@@ -256,12 +270,16 @@ int32_t sic_abi_version(void);
  *   grid_blocks:   workgroups of the tracer kernels, which loop over the
  *                  work items (any count is valid); 0 = automatic: one work
  *                  item per workgroup (batches: the item count rounded up to
- *                  a power of two, at least 4096). */
+ *                  a power of two, at least 4096);
+ *   fused_only:    single simulations: nonzero keeps sic_step on the fused
+ *                  launches where it would take the resident one; 0 =
+ *                  automatic (batches ignore it).
+ * sic_get_tuning reports the shape in effect (fused_only as set). */
 typedef struct sic_tuning {
     int32_t tile_chunks;
     int32_t block_threads;
     int32_t grid_blocks;
-    int32_t reserved;
+    int32_t fused_only;
 } sic_tuning;
 
 sic_status sic_set_tuning(sic_sim *sim, const sic_tuning *t);

@@ -28,6 +28,7 @@ SIC_NOALLOC_MAX_TRACERS = 1 << 20
 SIC_FP64, SIC_SPLIT_F32, SIC_SPLIT_U32 = 0, 1, 2
 SIC_MEM_HOST, SIC_MEM_DEVICE = 0, 1
 SIC_DIAG_NONFINITE, SIC_DIAG_LONG_SEGMENT = 1, 2
+SIC_PATH_NONE, SIC_PATH_FUSED, SIC_PATH_RESIDENT, SIC_PATH_REFINING = -1, 0, 1, 2
 STATUS = {0: "SIC_OK", 1: "SIC_EINVAL", 2: "SIC_ENOMEM", 3: "SIC_EDEVICE", 4: "SIC_ESTATE", 5: "SIC_EBUSY",
           6: "SIC_ENOTSUP"}
 PRECISIONS = {"fp64": SIC_FP64, "split_f32": SIC_SPLIT_F32, "split_u32": SIC_SPLIT_U32}
@@ -58,7 +59,7 @@ class sic_diag(ctypes.Structure):
 
 class sic_tuning(ctypes.Structure):
     _fields_ = [("tile_chunks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("fused_only", ctypes.c_int32)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ _SIGS = {
     "sic_get_tuning": (_I32, [_P, _P]),
     "sic_set_timing": (_I32, [_P, _I32]),
     "sic_last_timing": (_I32, [_P, _P, _P]),
+    "sic_last_step_path": (_I32, [_P, _P]),
     "sic_batch_create": (_I32, [_I64, _I32, _I32, _I32, _I32, _I32, _I64, _P, _P]),
     "sic_batch_admit": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _I32, _I64, _P]),
     "sic_batch_get_charges": (_I32, [_P, _I32, _P, _I32]),
@@ -342,19 +344,26 @@ def sic_last_error(h) -> str:
     return (load().sic_last_error(h) or b"").decode()
 
 
-def sic_set_tuning(h, tile_chunks=0, block_threads=0, grid_blocks=0):
-    t = sic_tuning(int(tile_chunks), int(block_threads), int(grid_blocks), 0)
+def sic_set_tuning(h, tile_chunks=0, block_threads=0, grid_blocks=0, fused_only=0):
+    t = sic_tuning(int(tile_chunks), int(block_threads), int(grid_blocks), int(fused_only))
     _check(load().sic_set_tuning(h, ctypes.byref(t)), "sic_set_tuning", h)
 
 
 def sic_get_tuning(h) -> dict:
     t = sic_tuning()
     _check(load().sic_get_tuning(h, ctypes.byref(t)), "sic_get_tuning", h)
-    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks)
+    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks,
+                fused_only=t.fused_only)
 
 
 def sic_set_timing(h, on: bool):
     _check(load().sic_set_timing(h, 1 if on else 0), "sic_set_timing", h)
+
+
+def sic_last_step_path(h) -> int:
+    p = ctypes.c_int32(0)
+    _check(load().sic_last_step_path(h, ctypes.byref(p)), "sic_last_step_path", h)
+    return p.value
 
 
 def sic_last_timing(h):
@@ -488,14 +497,16 @@ def sic_batch_set_tuning(b, tile_chunks=0, block_threads=0, grid_blocks=0):
 def sic_batch_get_tuning(b) -> dict:
     t = sic_tuning()
     _check(load().sic_batch_get_tuning(b, ctypes.byref(t)), "sic_batch_get_tuning", b, batch=True)
-    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks)
+    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks,
+                fused_only=t.fused_only)
 
 
 def sic_autotune(h, steps_per_trial: int = 3):
     t = sic_tuning()
     ms = ctypes.c_double(0)
     _check(load().sic_autotune(h, int(steps_per_trial), ctypes.byref(t), ctypes.byref(ms)), "sic_autotune", h)
-    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks), ms.value
+    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks,
+                fused_only=t.fused_only), ms.value
 
 
 def sic_batch_autotune(b, steps_per_trial: int = 3):
@@ -503,7 +514,8 @@ def sic_batch_autotune(b, steps_per_trial: int = 3):
     ms = ctypes.c_double(0)
     _check(load().sic_batch_autotune(b, int(steps_per_trial), ctypes.byref(t), ctypes.byref(ms)),
            "sic_batch_autotune", b, batch=True)
-    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks), ms.value
+    return dict(tile_chunks=t.tile_chunks, block_threads=t.block_threads, grid_blocks=t.grid_blocks,
+                fused_only=t.fused_only), ms.value
 
 
 def sic_batch_set_timing(b, on: bool):

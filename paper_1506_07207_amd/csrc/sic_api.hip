@@ -188,6 +188,7 @@ struct Pool {
   std::vector<hipGraph_t> graph_objs;
   bool timing = false;
   double t_tracer = 0.0, t_solve = 0.0;
+  int last_path = SIC_PATH_NONE;  // launch path of the last single-simulation step call
   std::string err;
 };
 
@@ -639,7 +640,7 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
     for (int b : blocks) {
       if (t > 0 && t * kChunk < b) continue;  // every wave gets at least one chunk
       for (int g : grids) {
-        sic_tuning cand{t, b, g, 0};
+        sic_tuning cand{t, b, g, saved.fused_only};
         p->tune = cand;
         destroy_graphs(p);
         apply_launch_shape(p);
@@ -671,7 +672,7 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
     best_out->tile_chunks = p->tile;
     best_out->block_threads = p->block;
     best_out->grid_blocks = p->grid;
-    best_out->reserved = 0;
+    best_out->fused_only = p->tune.fused_only;
   }
   if (best_ms_out) *best_ms_out = best_ms;
   return SIC_OK;
@@ -1875,6 +1876,7 @@ sic_status sim_step(Pool *p, int64_t n) {
     // tracers; when a segment is split the refined state is deposited and
     // solved again, so the step's field and row are those of the refined
     // sheets (all on the device; the timing mode keeps the host passes)
+    p->last_path = SIC_PATH_REFINING;
     if (p->timing) {
       for (int64_t i = 0; i < n && st == SIC_OK; ++i) {
         st = run_fused(p, 1);
@@ -1884,7 +1886,11 @@ sic_status sim_step(Pool *p, int64_t n) {
     }
     return sim_step_refining(p, n);
   }
-  if (p->order == 0 && !p->timing && sh.n_chunks <= resident_max_chunks()) return run_resident(p, n);
+  if (p->order == 0 && !p->timing && !p->tune.fused_only && sh.n_chunks <= resident_max_chunks()) {
+    p->last_path = SIC_PATH_RESIDENT;
+    return run_resident(p, n);
+  }
+  p->last_path = SIC_PATH_FUSED;
   return run_fused(p, n);
 }
 
@@ -2084,13 +2090,19 @@ sic_status sic_get_tuning(const sic_sim *sim, sic_tuning *t) {
   t->tile_chunks = sim->pool->tile;
   t->block_threads = sim->pool->block;
   t->grid_blocks = sim->pool->grid;
-  t->reserved = 0;
+  t->fused_only = sim->pool->tune.fused_only;
   return SIC_OK;
 }
 
 sic_status sic_set_timing(sic_sim *sim, int32_t timing) {
   if (!sim) return SIC_EINVAL;
   sim->pool->timing = timing != 0;
+  return SIC_OK;
+}
+
+sic_status sic_last_step_path(const sic_sim *sim, int32_t *path) {
+  if (!sim || !path) return SIC_EINVAL;
+  *path = sim->pool->last_path;
   return SIC_OK;
 }
 
@@ -2211,7 +2223,7 @@ sic_status sic_batch_get_tuning(const sic_batch *b, sic_tuning *t) {
   t->tile_chunks = b->pool->tile;
   t->block_threads = b->pool->block;
   t->grid_blocks = b->pool->grid;
-  t->reserved = 0;
+  t->fused_only = 0;
   return SIC_OK;
 }
 

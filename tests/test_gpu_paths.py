@@ -1,0 +1,54 @@
+"""Launch paths of a single simulation's steps: the resident launch of a
+small simulation gives the fused launches' bits in the split forms and the
+same run to rounding in FP64; sic_last_step_path reports the path taken and
+fused_only forces the fused launches."""
+import numpy as np
+import pytest
+
+from paper_1506_07207_amd import binding as B
+from paper_1506_07207_amd import inputs as I
+from tests.parity import periodic_diff
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(p, prec, steps, fused_only):
+    with B.Simulation(p, precision=prec) as s:
+        assert B.sic_last_step_path(s.h) == B.SIC_PATH_NONE
+        B.sic_set_tuning(s.h, fused_only=fused_only)
+        assert B.sic_get_tuning(s.h)["fused_only"] == fused_only
+        s.step(steps)
+        path = B.sic_last_step_path(s.h)
+        x, v, st = s.state()
+        d = s.diagnostics()
+    return path, x, v, st, d
+
+
+@pytest.mark.parametrize("prec", [B.SIC_SPLIT_U32, B.SIC_SPLIT_F32, B.SIC_FP64])
+def test_resident_and_fused_paths_agree(prec):
+    # 8 sheets of 250 tracers: 32 chunks, the largest resident simulation
+    p = I.landau(n_sheets=8, n_tracers=250, n_cells=64, alpha=0.05)
+    print(f"case resident vs fused prec={prec}", flush=True)
+    r = _run(p, prec, 80, 0)
+    f = _run(p, prec, 80, 1)
+    assert r[0] == B.SIC_PATH_RESIDENT and f[0] == B.SIC_PATH_FUSED
+    assert r[3] == f[3] == 80
+    if prec == B.SIC_FP64:
+        assert np.max(periodic_diff(r[1], f[1], p.L)) < 1e-11 * p.L
+        np.testing.assert_allclose(r[4]["history"]["W_E"], f[4]["history"]["W_E"], rtol=1e-10)
+    else:
+        assert np.array_equal(r[1], f[1]) and np.array_equal(r[2], f[2])
+        assert np.array_equal(r[4]["history"]["W_E"], f[4]["history"]["W_E"])
+
+
+def test_larger_simulation_takes_the_fused_path():
+    p = I.landau(n_sheets=64, n_tracers=256, n_cells=64)
+    path, *_ = _run(p, B.SIC_FP64, 3, 0)
+    assert path == B.SIC_PATH_FUSED
+
+
+def test_refining_simulation_reports_its_path():
+    p = I.two_stream(n_sheets=8, n_tracers=64, n_cells=64, n_steps=5)
+    with B.Simulation(p, l_max=p.L / 16, max_tracers=16 * p.total_tracers) as s:
+        s.step(3)
+        assert B.sic_last_step_path(s.h) == B.SIC_PATH_REFINING
