@@ -369,9 +369,10 @@ sic_status sic_batch_last_timing(const sic_batch *b, double *tracer_ms, double *
  * the handle's own resident simulations, with HIP events around each kernel,
  * then restores the simulations to their state before the call (the trial
  * steps leave no trace; the device briefly holds a second copy of the state)
- * and applies the fastest shape.  best / best_ms (may be NULL) receive it and
- * its time per step.  Synchronous; SIC_ENOMEM if the state copy does not
- * fit. */
+ * and applies the fastest shape; the shape in effect is timed first and kept
+ * unless another is more than 2 % faster.  best / best_ms (may be NULL)
+ * receive the shape applied and its time per step.  Synchronous; SIC_ENOMEM
+ * if the state copy does not fit. */
 sic_status sic_autotune(sic_sim *sim, int32_t steps_per_trial, sic_tuning *best, double *best_ms);
 sic_status sic_batch_autotune(sic_batch *b, int32_t steps_per_trial, sic_tuning *best, double *best_ms);
 

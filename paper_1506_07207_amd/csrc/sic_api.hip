@@ -39,6 +39,7 @@ constexpr int kMaxGrid = 1 << 20;        // largest default grid (the kernels lo
 constexpr int kDefaultBlock = 256;       // single simulations
 constexpr int kDefaultBatchBlock = 512;  // batches
 constexpr int kDefaultBatchTile = 256;   // chunks per batch work item (16k tracers per LDS mesh merge)
+constexpr int kLinearBatchTile = 192;    // piecewise-linear segments: three workgroups per CU in LDS
 // (batch defaults: the autotuner's choice on the 4096-instance mixed batch)
 constexpr int kMinTile = 4;             // chunks per work item, lower bound
 constexpr int kMaxTile = 256;
@@ -408,7 +409,7 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
 int slot_tile(const Pool *p, int64_t n_chunks) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
   const int wave_min = p->block / kChunk;
-  if (p->batch) return std::max(kDefaultBatchTile, wave_min);
+  if (p->batch) return std::max(p->order == 1 ? kLinearBatchTile : kDefaultBatchTile, wave_min);
   const int64_t per = (n_chunks + 2047) / 2048;
   const int64_t mesh_min = (4 * (int64_t)p->max_cells + kChunk - 1) / kChunk;
   const int64_t want = std::max(per, std::min(mesh_min, n_chunks / 128));
@@ -634,9 +635,25 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
   const int tiles[] = {0, 16, 32, 64, 128, 256};  // 0: the default item size
   const int blocks[] = {256, 512, 1024};
   const int grids[] = {0, 1024, 2048, 4096};  // 0: one work item per workgroup
+  // the shape in effect is timed first, and a candidate replaces it only when
+  // it is faster by more than the trials' noise
+  constexpr double kMargin = 0.98;
   sic_tuning best = saved;
-  double best_ms = 1e300;
+  double best_ms = 1e300, best_key = 1e300;  // measured time; time compared (the margin applied)
+  {
+    p->tune = saved;
+    destroy_graphs(p);
+    apply_launch_shape(p);
+    st = relayout_items(p);
+    if (st == SIC_OK) st = run_fused(p, 1);
+    if (st == SIC_OK) st = run_fused(p, steps);
+    if (st == SIC_OK) {
+      best_ms = p->t_tracer + p->t_solve;
+      best_key = kMargin * best_ms;
+    }
+  }
   for (int t : tiles) {
+    if (st != SIC_OK) break;
     for (int b : blocks) {
       if (t > 0 && t * kChunk < b) continue;  // every wave gets at least one chunk
       for (int g : grids) {
@@ -649,8 +666,8 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
         if (st == SIC_OK) st = run_fused(p, steps);
         if (st != SIC_OK) break;
         const double ms = p->t_tracer + p->t_solve;
-        if (ms < best_ms) {
-          best_ms = ms;
+        if (ms < best_key) {
+          best_ms = best_key = ms;
           best = cand;
         }
       }
