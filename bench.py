@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="length of the served stream in requests (0: --serve-seconds of arrivals)")
     ap.add_argument("--plain-serve-requests", type=int, default=100)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -374,12 +376,14 @@ def serving(B, S, I, value, args, torch):
     sample = list(I.request_stream(4000, 1.0, seed=20251204))
     mean_work = float(np.mean([r.spec.tracers * r.spec.n_steps for r in sample]))
     rate = args.serve_load * value / mean_work
-    n = max(20, int(rate * args.serve_seconds))
+    n = args.serve_requests if args.serve_requests > 0 else max(20, int(rate * args.serve_seconds))
     reqs = S.poisson_stream(n, rate)
     log(f"serving {n} requests at {rate:.1f}/s (mean {mean_work:.3e} tracer-updates per request)")
     ex = S.GpuExecutor()
     try:
-        rep = S.Server(ex, chunk_steps=32).run(reqs, warmup_fraction=0.2, prepare=S.serve_prepare(ex))
+        # the first 10 % of the stream, while the batch fills, is not counted
+        rep = S.Server(ex, chunk_steps=32).run(reqs, warmup_fraction=0.1, prepare=S.serve_prepare(ex),
+                                               progress=lambda d, t: log(f"served {d}/{t}"))
     finally:
         ex.close()
     torch.cuda.empty_cache()
@@ -505,7 +509,7 @@ def main():
         log(f"plain: {rate:.4e} tracer-updates/s over {len(sub)} instances")
 
     serve = None
-    if args.serve_seconds > 0:
+    if args.serve_seconds > 0 or args.serve_requests > 0:
         from paper_1506_07207_amd import serve as S
         serve = serving(B, S, I, value, args, torch)
 

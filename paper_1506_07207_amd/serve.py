@@ -115,8 +115,12 @@ class Server:
         self.clock = clock
         self.sleep = sleep
 
-    def run(self, requests: Iterable, warmup_fraction: float = 0.1, prepare: Optional[Callable] = None) -> Report:
+    def run(self, requests: Iterable, warmup_fraction: float = 0.1, prepare: Optional[Callable] = None,
+            progress: Optional[Callable[[int, int], None]] = None) -> Report:
+        """Serves the stream in real time; progress(done, total), if given,
+        is called each time another tenth of the requests has completed."""
         reqs = sorted(requests, key=lambda r: r.arrival)
+        done, step_report = 0, max(1, len(reqs) // 10)
         records = {r.rid: Record(r.rid, r.arrival, r.spec.tracers, r.spec.n_steps) for r in reqs}
         waiting = collections.deque()
         passed: Dict[int, int] = collections.defaultdict(int)
@@ -158,6 +162,9 @@ class Server:
                     rec.final_W_E = float(res.get("W_E", math.nan))
                     rec.flags = int(res.get("flags", 0))
                     rec.W_E_history = res.get("W_E_history")
+                    done += 1
+                    if progress is not None and done % step_report == 0:
+                        progress(done, len(reqs))
             elif nxt < len(reqs):
                 wait = reqs[nxt].arrival - (self.clock() - t0)
                 if wait > 0:
