@@ -527,11 +527,13 @@ __device__ __forceinline__ double lin_density(const SegGeo &s, double q) {
 // zero length (both passed as length 0).
 __device__ __forceinline__ double lin_gradient(double c, double cm, double dm_len, double rm, double cp,
                                                double dp_len, double rp, double half_nc, double nc) {
-  if (dm_len == 0.0 || dp_len == 0.0) return 0.0;
+  // without branches: a wavefront's lanes mostly take the quotient, and the
+  // others select 0 (their divisor replaced by 1)
   const double dm = min_image_cells(cm - c, half_nc, nc);
   const double dp = min_image_cells(cp - c, half_nc, nc);
-  if (!((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0))) return 0.0;
-  return (rp - rm) / (dp - dm);
+  const bool ok = dm_len != 0.0 && dp_len != 0.0 && ((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0));
+  const double q = (rp - rm) / (ok ? dp - dm : 1.0);
+  return ok ? q : 0.0;
 }
 
 // A neighbouring segment as the gradient needs it: centroid, signed length
@@ -555,18 +557,19 @@ __device__ __forceinline__ void deposit_linear_fp64(double a_phys, const SegGeo 
   const double f0 = floor(u0);
   const int c0 = (int)f0;
   const int c1 = (int)ceil(u1) - 1;
-  if (!(len > 0.0) || c1 <= c0) {
-    lds_add(sP + wrap_cell(c0, geo.nc), q);
-    return;
-  }
+  // a segment inside one cell puts q there; a longer one its first piece
+  // (one atomic for both kinds, so a wavefront that holds both issues one)
+  const bool multi = (len > 0.0) && c1 > c0;
   const double e0 = f0 + 1.0;
   const double w0 = e0 - u0;
-  const double w1 = u1 - (double)c1;
-  lds_add(sP + wrap_cell(c0, geo.nc), w0 * (r0 + g * (0.5 * (u0 + e0) - sg.c)));
-  lds_add(sP + wrap_cell(c1, geo.nc), w1 * (r0 + g * (0.5 * ((double)c1 + u1) - sg.c)));
-  if (c1 - c0 >= 2) {
-    const double A = r0 + g * ((double)(c0 + 1) + 0.5 - sg.c);
-    add_ramp(sD, sR, c0 + 1, c1 - 1, A, g, geo.nc);
+  lds_add(sP + wrap_cell(c0, geo.nc), multi ? w0 * (r0 + g * (0.5 * (u0 + e0) - sg.c)) : q);
+  if (multi) {
+    const double w1 = u1 - (double)c1;
+    lds_add(sP + wrap_cell(c1, geo.nc), w1 * (r0 + g * (0.5 * ((double)c1 + u1) - sg.c)));
+    if (c1 - c0 >= 2) {
+      const double A = r0 + g * ((double)(c0 + 1) + 0.5 - sg.c);
+      add_ramp(sD, sR, c0 + 1, c1 - 1, A, g, geo.nc);
+    }
   }
 }
 
@@ -586,22 +589,23 @@ __device__ __forceinline__ void deposit_linear_split(int cell_a, double frac_a, 
   const double f0 = floor(u0);
   const int c0 = (int)f0;
   const int c1 = (int)ceil(u1) - 1;
-  if (!(len > 0.0) || c1 <= c0) {
-    lds_add(sP + wrap_cell(c0, geo.nc), (unsigned long long)qf);
-    return;
-  }
+  // a segment inside one cell puts qf there; a longer one its first piece
+  // (one atomic for both kinds)
+  const bool multi = (len > 0.0) && c1 > c0;
   const double e0 = f0 + 1.0;
-  const long long p0 = llrint((e0 - u0) * (r0 + g * (0.5 * (u0 + e0) - sg.c)));
-  long long p1 = qf - p0;
-  if (c1 - c0 >= 2) {
-    const long long n = c1 - c0 - 1;
-    const long long A = llrint(r0 + g * ((double)(c0 + 1) + 0.5 - sg.c));
-    const long long B = llrint(g);
-    add_ramp(sD, sR, c0 + 1, c1 - 1, (unsigned long long)A, (unsigned long long)B, geo.nc);
-    p1 -= n * A + B * (n * (n - 1) / 2);
-  }
+  const long long p0 = multi ? llrint((e0 - u0) * (r0 + g * (0.5 * (u0 + e0) - sg.c))) : qf;
   lds_add(sP + wrap_cell(c0, geo.nc), (unsigned long long)p0);
-  lds_add(sP + wrap_cell(c1, geo.nc), (unsigned long long)p1);
+  if (multi) {
+    long long p1 = qf - p0;
+    if (c1 - c0 >= 2) {
+      const long long n = c1 - c0 - 1;
+      const long long A = llrint(r0 + g * ((double)(c0 + 1) + 0.5 - sg.c));
+      const long long B = llrint(g);
+      add_ramp(sD, sR, c0 + 1, c1 - 1, (unsigned long long)A, (unsigned long long)B, geo.nc);
+      p1 -= n * A + B * (n * (n - 1) / 2);
+    }
+    lds_add(sP + wrap_cell(c1, geo.nc), (unsigned long long)p1);
+  }
 }
 
 // ---- first-order weighting of segments (section 2.4) ----
@@ -631,30 +635,27 @@ __device__ __forceinline__ void deposit_cic_fp64(double u_a, double d_mesh, doub
   const double fl0 = floor(s0);
   const double t0 = s0 - fl0;
   const int f0 = (int)fl0;
-  if (!(s1 > s0)) {  // a point: its hat weights
-    lds_add(sP + wrap_cell(f0, g.nc), q * (1.0 - t0));
-    lds_add(sP + wrap_cell(f0 + 1, g.nc), q * t0);
-    return;
-  }
   const double fl1 = floor(s1);
   const double t1 = s1 - fl1;
-  const int n = (int)fl1 - f0;
-  if (n == 0) {
-    const double tm = 0.5 * (t0 + t1);
-    lds_add(sP + wrap_cell(f0, g.nc), q * (1.0 - tm));
-    lds_add(sP + wrap_cell(f0 + 1, g.nc), q * tm);
-    return;
-  }
-  const double r = q / (s1 - s0);
+  const int n = (int)fl1 - f0;  // 0 for a point (s1 = s0: t1 = t0, so tm = t0)
+  // grid points f0 and f0 + 1 take one addition each in every case; the
+  // density (a division) is computed when some lane of the wavefront needs it
+  const bool longseg = n >= 1;
+  double r = 0.0;
+  if (__builtin_amdgcn_ballot_w64(longseg) != 0) r = q / (longseg ? s1 - s0 : 1.0);
   const double hr = 0.5 * r;
+  const double tm = 0.5 * (t0 + t1);
   const double a0 = hr * ((1.0 - t0) * (1.0 - t0)), b0 = hr * (t0 * t0);
-  const double a1 = hr * ((1.0 - t1) * (1.0 - t1)), b1 = hr * (t1 * t1);
-  lds_add(sP + wrap_cell(f0, g.nc), a0);
-  lds_add(sP + wrap_cell(f0 + 1, g.nc), n == 1 ? hr * ((1.0 - t0) * (1.0 + t0) + t1 * (2.0 - t1)) : r - b0);
-  lds_add(sP + wrap_cell(f0 + n + 1, g.nc), b1);
-  if (n >= 2) {
-    lds_add(sP + wrap_cell(f0 + n, g.nc), r - a1);
-    if (n >= 3) add_run(sD, f0 + 2, f0 + n - 1, r, g.nc);
+  lds_add(sP + wrap_cell(f0, g.nc), longseg ? a0 : q * (1.0 - tm));
+  lds_add(sP + wrap_cell(f0 + 1, g.nc),
+          longseg ? (n == 1 ? hr * ((1.0 - t0) * (1.0 + t0) + t1 * (2.0 - t1)) : r - b0) : q * tm);
+  if (longseg) {
+    const double a1 = hr * ((1.0 - t1) * (1.0 - t1)), b1 = hr * (t1 * t1);
+    lds_add(sP + wrap_cell(f0 + n + 1, g.nc), b1);
+    if (n >= 2) {
+      lds_add(sP + wrap_cell(f0 + n, g.nc), r - a1);
+      if (n >= 3) add_run(sD, f0 + 2, f0 + n - 1, r, g.nc);
+    }
   }
 }
 
