@@ -172,20 +172,24 @@ sic_status sic_push(sic_sim *sim);
  * deposits the new positions and solves the new field, so on return the field
  * is current for the new step.  If the field is stale it is brought up to date
  * first.  Steps run as captured HIP graphs of a tracer launch and a solve
- * launch each (SIC_PATH_FUSED); a small simulation (constant segments, at
- * most 32 chunks of 64 tracer slots) runs them in one launch of a single
- * workgroup instead (SIC_PATH_RESIDENT; same arithmetic, and the same bits in
- * the split forms).  Timing mode (sic_set_timing) always takes the fused
- * path.  Async; with refinement on (l_max > 0) each step is followed by a
- * refinement pass on the device (SIC_PATH_REFINING: graphs of steps and
- * passes; the host reads the layout back when it needs it). */
+ * launch each (SIC_PATH_FUSED).  With constant segments a simulation's
+ * tracer launches solve the previous step's charge themselves, in every
+ * workgroup, and one solve launch closes each graph of up to 32 steps
+ * (SIC_PATH_SOLVE_FIRST); a small simulation (at most 32 chunks of 64 tracer
+ * slots) runs its steps in one launch of a single workgroup
+ * (SIC_PATH_RESIDENT).  All give the bits of the fused path in the split
+ * forms.  Timing mode (sic_set_timing) always takes the fused path.  Async;
+ * with refinement on (l_max > 0) each step is followed by a refinement pass
+ * on the device (SIC_PATH_REFINING: graphs of steps and passes; the host
+ * reads the layout back when it needs it). */
 sic_status sic_step(sic_sim *sim, int64_t n_steps);
 
 enum {
     SIC_PATH_NONE = -1,
     SIC_PATH_FUSED = 0,
     SIC_PATH_RESIDENT = 1,
-    SIC_PATH_REFINING = 2
+    SIC_PATH_REFINING = 2,
+    SIC_PATH_SOLVE_FIRST = 3
 };
 /* The launch path of the last sic_step call on sim (SIC_PATH_NONE before
  * any). */
@@ -272,8 +276,8 @@ int32_t sic_abi_version(void);
  *                  item per workgroup (batches: the item count rounded up to
  *                  a power of two, at least 4096);
  *   fused_only:    single simulations: nonzero keeps sic_step on the fused
- *                  launches where it would take the resident one; 0 =
- *                  automatic (batches ignore it).
+ *                  launch pairs where it would take the resident or
+ *                  solve-first path; 0 = automatic (batches ignore it).
  * sic_get_tuning reports the shape in effect (fused_only as set). */
 typedef struct sic_tuning {
     int32_t tile_chunks;

@@ -28,7 +28,7 @@ SIC_NOALLOC_MAX_TRACERS = 1 << 20
 SIC_FP64, SIC_SPLIT_F32, SIC_SPLIT_U32 = 0, 1, 2
 SIC_MEM_HOST, SIC_MEM_DEVICE = 0, 1
 SIC_DIAG_NONFINITE, SIC_DIAG_LONG_SEGMENT = 1, 2
-SIC_PATH_NONE, SIC_PATH_FUSED, SIC_PATH_RESIDENT, SIC_PATH_REFINING = -1, 0, 1, 2
+SIC_PATH_NONE, SIC_PATH_FUSED, SIC_PATH_RESIDENT, SIC_PATH_REFINING, SIC_PATH_SOLVE_FIRST = -1, 0, 1, 2, 3
 STATUS = {0: "SIC_OK", 1: "SIC_EINVAL", 2: "SIC_ENOMEM", 3: "SIC_EDEVICE", 4: "SIC_ESTATE", 5: "SIC_EBUSY",
           6: "SIC_ENOTSUP"}
 PRECISIONS = {"fp64": SIC_FP64, "split_f32": SIC_SPLIT_F32, "split_u32": SIC_SPLIT_U32}

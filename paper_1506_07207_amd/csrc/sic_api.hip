@@ -174,6 +174,11 @@ struct Pool {
   int32_t *dr_state = nullptr;   // RefineState words
   int64_t *dr_in_off = nullptr;  // per chunk of the reservation: first staging index
   int32_t dr_sheets = 0, dr_chunks = 0;
+  // solve-first steps of a single simulation (allocated on first use): two
+  // more accumulator pairs (the pool's own is the third) and a second set of
+  // work-item partials
+  void *sf_mesh = nullptr;     // P1, D1, P2, D2: max_cells words each
+  Partial *sf_part = nullptr;  // item_cap
 
   std::vector<SlotHost> slots;
   ChunkAllocator alloc;       // tracer chunks
@@ -279,7 +284,8 @@ void pool_free(Pool *p) {
                   p->partials,  p->meshP,    p->meshD,    p->meshR,    p->meshE,     p->meshRho,
                   p->hist,      p->done,     p->slot_ids, p->segq,     p->cedge,     p->edge_prev,
                   p->ref_cnt,   p->ref_mask, p->ref_off,  p->ref_w,    p->ref_v,     p->ref_c,
-                  p->dr_nt,     p->dr_closed, p->dr_q,    p->dr_work,  p->dr_state,  p->dr_in_off};
+                  p->dr_nt,     p->dr_closed, p->dr_q,    p->dr_work,  p->dr_state,  p->dr_in_off,
+                  p->sf_mesh,   p->sf_part};
   for (void *b : bufs)
     if (b) hipFree(b);
   if (p->cap) hipStreamDestroy(p->cap);
@@ -806,6 +812,104 @@ sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
   return SIC_OK;
 }
 
+// Solve-first steps: a single simulation with constant segments (not timed,
+// not refining on the device) runs k steps as k tracer launches whose
+// second and later ones solve the previous step's charge in every workgroup
+// (launch_tracers_sf), then one solve launch for the last step.  The charge
+// rotates through three accumulator pairs A0 (the pool's own), A1, A2 and
+// the partials through two buffers: launch i (1-based) merges into
+// A[(i - 1) mod 3] and writes partials (i - 1) mod 2, reads A[(i - 2) mod 3]
+// and partials (i - 2) mod 2, and clears A[i mod 3], which launch i - 1 read
+// and launch i + 1 merges into after this one has ended.  The closing solve
+// clears what it reads and a zero launch the pair launch k read, so every
+// pair is clear again, as the other paths expect.  The bits are those of the
+// tracer/solve launch pairs: the same solve code, the same sums in the same
+// order.
+bool sf_ready(Pool *p) {
+  if (p->batch || p->order != 0 || p->timing || p->dev_refine || p->tune.fused_only || p->block < kSolveThreads)
+    return false;
+  if (!p->sf_mesh) {
+    const size_t bytes = sizeof(double) * 4 * (size_t)p->max_cells;
+    if (hipMalloc(&p->sf_mesh, bytes) != hipSuccess) {
+      p->sf_mesh = nullptr;
+      return false;
+    }
+    if (hipMemsetAsync(p->sf_mesh, 0, bytes, p->stream) != hipSuccess) return false;
+  }
+  if (!p->sf_part) {
+    if (hipMalloc((void **)&p->sf_part, sizeof(Partial) * (size_t)p->item_cap) != hipSuccess) {
+      p->sf_part = nullptr;
+      return false;
+    }
+  }
+  return true;
+}
+
+sic_status enqueue_sf(Pool *p, int64_t k, hipStream_t st) {
+  double *m = static_cast<double *>(p->sf_mesh);
+  const size_t mc = (size_t)p->max_cells;
+  void *AP[3] = {p->meshP, m, m + 2 * mc};
+  void *AD[3] = {p->meshD, m + mc, m + 3 * mc};
+  Partial *PB[2] = {p->partials, p->sf_part};
+  const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
+  for (int64_t i = 1; i <= k; ++i) {
+    TracerArgs a = tracer_args(p, kPush | kDeposit, -1);
+    a.meshP = AP[(i - 1) % 3];
+    a.meshD = AD[(i - 1) % 3];
+    a.partials = PB[(i - 1) % 2];
+    if (i == 1) {
+      LAUNCHCHK(p, launch_tracers(p->prec, kPush | kDeposit, p->order, p->seg, a, grid_for(p, -1), p->block, lds, st));
+    } else {
+      a.sf_P = AP[(i - 2) % 3];
+      a.sf_D = AD[(i - 2) % 3];
+      a.sf_zP = AP[i % 3];
+      a.sf_zD = AD[i % 3];
+      a.sf_partials = PB[(i - 2) % 2];
+      a.sf = solve_args(p, kHavePush | kHaveDeposit, -1);
+      LAUNCHCHK(p, launch_tracers_sf(p->prec, p->seg, a, grid_for(p, -1), p->block, lds, p->max_cells, st));
+    }
+    p->parity ^= 1;
+  }
+  SolveArgs sa = solve_args(p, kHavePush | kHaveDeposit, -1);
+  sa.meshP = AP[(k - 1) % 3];
+  sa.meshD = AD[(k - 1) % 3];
+  sa.partials = PB[(k - 1) % 2];
+  LAUNCHCHK(p, launch_solve(p->prec, sa, p->solve_grid, p->max_cells, st));
+  if (k >= 2)
+    LAUNCHCHK(p, launch_zero_mesh(p->prec, AP[(k - 2) % 3], AD[(k - 2) % 3], nullptr, p->inst, p->slot_ids, 1, st));
+  return SIC_OK;
+}
+
+sic_status get_sf_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
+  auto key = std::make_tuple(k, p->parity, p->grid, p->solve_grid, 3);
+  auto it = p->graphs.find(key);
+  if (it != p->graphs.end()) {
+    *out = it->second;
+    return SIC_OK;
+  }
+  const int parity0 = p->parity;
+  HIPCHK(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+  sic_status s = enqueue_sf(p, k, p->cap);
+  p->parity = parity0;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap, &g);
+  if (s != SIC_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(p, SIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  p->graph_objs.push_back(g);
+  p->graphs[key] = ex;
+  *out = ex;
+  return SIC_OK;
+}
+
 sic_status run_fused(Pool *p, int64_t n) {
   if (n <= 0) return SIC_OK;
   if (p->timing) {
@@ -841,10 +945,11 @@ sic_status run_fused(Pool *p, int64_t n) {
     p->t_solve = ts / (double)n;
     return SIC_OK;
   }
+  const bool sf = sf_ready(p);
   while (n > 0) {
     const int64_t k = std::min<int64_t>(n, kGraphSteps);
     hipGraphExec_t ex;
-    sic_status s = get_graph(p, k, &ex);
+    sic_status s = sf ? get_sf_graph(p, k, &ex) : get_graph(p, k, &ex);
     if (s != SIC_OK) return s;
     HIPCHK(p, hipGraphLaunch(ex, p->stream));
     if (k & 1) p->parity ^= 1;
@@ -1907,7 +2012,7 @@ sic_status sim_step(Pool *p, int64_t n) {
     p->last_path = SIC_PATH_RESIDENT;
     return run_resident(p, n);
   }
-  p->last_path = SIC_PATH_FUSED;
+  p->last_path = sf_ready(p) ? SIC_PATH_SOLVE_FIRST : SIC_PATH_FUSED;
   return run_fused(p, n);
 }
 

@@ -104,6 +104,24 @@ struct alignas(64) DiagRow {
 // sheet too short to have a gradient).
 enum HaloWhich : int { kHaloFirst = 0, kHaloSecond = 1, kHaloLast = 2 };
 
+struct SolveArgs {
+  InstDesc *inst;
+  const int2 *slot_items;    // per slot: (first item, item count) in the item list
+  const int32_t *slot_list;  // NULL: slot = blockIdx.x
+  const Partial *partials;
+  void *meshP;
+  void *meshD;
+  void *meshR;               // order 1 only
+  double *meshE;
+  double *meshRho;           // n_j - nbar of the newest solve
+  DiagRow *hist;
+  int32_t *done;             // per slot: set to 1 when a batch run finishes
+  int32_t flags;
+  int32_t respect_active;
+  int32_t order;             // deposit order of the pool (0, 1 or 2); R exists only for 1
+  const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
+};
+
 struct TracerArgs {
   const Item *items;
   const int32_t *n_items;  // device-side item count
@@ -127,24 +145,14 @@ struct TracerArgs {
   int32_t tile_cap;        // LDS capacity in chunks per work item
   int32_t respect_active;  // skip slots with active == 0
   const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
-};
-
-struct SolveArgs {
-  InstDesc *inst;
-  const int2 *slot_items;    // per slot: (first item, item count) in the item list
-  const int32_t *slot_list;  // NULL: slot = blockIdx.x
-  const Partial *partials;
-  void *meshP;
-  void *meshD;
-  void *meshR;               // order 1 only
-  double *meshE;
-  double *meshRho;           // n_j - nbar of the newest solve
-  DiagRow *hist;
-  int32_t *done;             // per slot: set to 1 when a batch run finishes
-  int32_t flags;
-  int32_t respect_active;
-  int32_t order;             // deposit order of the pool (0, 1 or 2); R exists only for 1
-  const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
+  // Solve-first launches of a single simulation (launch_tracers_sf): every
+  // workgroup solves the previous step's charge for the field it pushes
+  // with, instead of reading meshE; the first also writes what a solve
+  // launch would (the diagnostics row, the step, the field and density).
+  const void *sf_P = nullptr, *sf_D = nullptr;  // the previous step's accumulators
+  void *sf_zP = nullptr, *sf_zD = nullptr;      // accumulators to clear, a slice per workgroup
+  const Partial *sf_partials = nullptr;         // the previous launch's work-item partials
+  SolveArgs sf{};                               // what the first workgroup's solve writes to
 };
 
 struct IngestArgs {
@@ -246,6 +254,10 @@ struct RefinePlanArgs {
 // Launchers (sic_kernels.hip).  All return hipError_t as int.
 int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a, int grid, int block,
                    size_t lds_bytes, void *stream);
+// A fused step (push + deposit, constant segments) of a single simulation in
+// solve-first form (TracerArgs sf_*); max_cells sizes the solve.
+int launch_tracers_sf(int prec, bool seg, const TracerArgs &a, int grid, int block, size_t lds_bytes,
+                      int max_cells, void *stream);
 int set_tracer_lds_limit(int prec, int order, bool seg, size_t lds_bytes);
 size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_cap);
 // max_cells: the largest mesh of the slots the launch may solve.

@@ -820,6 +820,287 @@ __device__ __forceinline__ T lane_up1(T v) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Field solve
+// ---------------------------------------------------------------------------
+namespace {
+
+// Inclusive scan over the 256-thread block of one value per thread, in a
+// fixed order.  sWave holds 4 entries.
+template <class T>
+__device__ __forceinline__ T block_incl_scan(T v, T *sWave) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  v = wave_incl_scan(v, [](T x, T y) { return x + y; });
+  if (lane == 63) sWave[wave] = v;
+  __syncthreads();
+  T base = (T)0;
+  for (int w = 0; w < wave; ++w) base += sWave[w];
+  __syncthreads();
+  return v + base;
+}
+
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T *sWave) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sWave[wave] = v;
+  __syncthreads();
+  const T r = sWave[0] + sWave[1] + sWave[2] + sWave[3];
+  __syncthreads();
+  return r;
+}
+
+
+}  // namespace
+
+// The solve of one slot by one workgroup of kSolveThreads threads: charge
+// per cell from the P/D (and R) accumulators, which it clears; mean removal,
+// Gauss's law, cell-centre field, field energy; the diagnostics row and the
+// step count.  ke, mom, ms are the slot's kinetic-energy, momentum and
+// max-segment sums of the step.  The accumulators may be the slot's global
+// mesh (k_solve) or a workgroup's LDS copy (k_resident); with sE the field is
+// also left in LDS.
+// The slot's constants the solve needs, read once by its caller.
+struct SlotConst {
+  int nc;
+  double L, dx, dt, q_unit;
+  int64_t mesh_off, hist_off, hist_cap;
+};
+
+__device__ __forceinline__ SlotConst slot_const(const InstDesc &I) {
+  SlotConst k;
+  k.nc = I.n_cells;
+  k.L = I.L;
+  k.dx = I.dx;
+  k.dt = I.dt;
+  k.q_unit = I.q_unit;
+  k.mesh_off = I.mesh_off;
+  k.hist_off = I.hist_off;
+  k.hist_cap = I.hist_cap;
+  return k;
+}
+
+// The slot's point (P) and difference (D) accumulators of this thread's
+// cells, read and cleared: the first half of the solve, apart so that a
+// caller can have these loads in flight with others.
+template <int PREC, int CELLS, class Acc, class T>
+__device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD, T (&pv)[CELLS], T (&dv)[CELLS]) {
+  const int nc = kc.nc;
+  const int per = (nc + kSolveThreads - 1) / kSolveThreads;
+  const int j0 = threadIdx.x * per;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) {
+    pv[k] = (T)0;
+    dv[k] = (T)0;
+    const int j = j0 + k;
+    if (k < per && j < nc) {
+      pv[k] = (T)gP[j];
+      dv[k] = (T)gD[j];
+      gP[j] = (Acc)0;
+      gD[j] = (Acc)0;
+    }
+  }
+}
+
+// step0 and flags0 are the slot's step and sticky flags before this solve;
+// pv, dv this thread's accumulators from solve_take; returns the flags after
+// it (the same value in every thread).  With write_field false the field and
+// density are left in sE only (the resident kernel writes them to global
+// memory on its last step); with writer false nothing at all is written to
+// global memory (the workgroups of a launch that each solve the same charge
+// for their own use, all but one).
+template <int PREC, int CELLS, class Acc, class T>
+__device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const SlotConst &kc, int64_t step0,
+                                          int flags0, const T (&pv)[CELLS], const T (&dv)[CELLS], Acc *gRamp,
+                                          double ke, double mom, double ms, double *sE, bool write_field,
+                                          bool writer = true) {
+  using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+  static_assert(std::is_same<acc_t, T>::value, "accumulator type");
+  // The cells are partitioned over kSolveThreads threads; a wider workgroup
+  // (the resident kernel's) runs the same code, its other threads holding no
+  // cells and adding zeros, so the result has the same bits.
+  __shared__ double sWd[16];
+  __shared__ long long sWi[16];
+  __shared__ double sLastF[kSolveThreads];
+  InstDesc *Ip = a.inst + slot;
+  const int tid = threadIdx.x;
+  const int nc = kc.nc;
+  const double L = kc.L, dx = kc.dx, dt = kc.dt;
+  const double q_unit = kc.q_unit;
+
+  // 2. charge per cell: Q_j = P_j + sum_{m <= j} D_m
+  const int per = (nc + kSolveThreads - 1) / kSolveThreads;
+  const int j0 = tid * per;
+  double *gE = a.meshE + kc.mesh_off;
+  double *gR = a.meshRho + kc.mesh_off;
+  acc_t dsum = (acc_t)0;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) dsum += dv[k];
+  auto scan = [&](acc_t v) -> acc_t {
+    if constexpr (PREC == kFP64) return block_incl_scan(v, sWd);
+    else return block_incl_scan(v, sWi);
+  };
+  const acc_t dbase = scan(dsum) - dsum;
+  // Linear ramps of piecewise-linear segments: the charge adds the second
+  // prefix sum of R (zero for piecewise-constant segments).
+  acc_t r2[CELLS];
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) r2[k] = (acc_t)0;
+  if (gRamp != nullptr) {  // only piecewise-linear segments have ramps
+    acc_t rsum = (acc_t)0;
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      const int j = j0 + k;
+      if (k < per && j < nc) {
+        r2[k] = (acc_t)gRamp[j];
+        gRamp[j] = (Acc)0;
+      }
+      rsum += r2[k];
+    }
+    const acc_t base1 = scan(rsum) - rsum;
+    acc_t run1 = base1, s1sum = (acc_t)0;
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      run1 += r2[k];
+      r2[k] = run1;
+      if ((k < per) && (j0 + k < nc)) s1sum += run1;
+    }
+    const acc_t base2 = scan(s1sum) - s1sum;
+    acc_t run2 = base2;
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      if ((k < per) && (j0 + k < nc)) run2 += r2[k];
+      r2[k] = run2;
+    }
+  }
+  double Q[CELLS];
+  acc_t qsum_acc = (acc_t)0;
+  {
+    acc_t run = dbase;
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      run += dv[k];
+      const acc_t qa = pv[k] + run + r2[k];
+      const bool in = (k < per) && (j0 + k < nc);
+      if constexpr (PREC == kFP64) Q[k] = in ? qa : 0.0;
+      else Q[k] = in ? (double)qa * q_unit : 0.0;
+      if (in) qsum_acc += qa;
+    }
+  }
+  double Qtot;
+  if constexpr (PREC == kFP64) Qtot = block_sum(qsum_acc, sWd);
+  else Qtot = (double)block_sum(qsum_acc, sWi) * q_unit;
+
+  // 3. Gauss's law on faces: F_{j+1/2} = F_{j-1/2} + (Q_j - Qtot/nc),
+  //    F shifted to zero mean; E_j = (F_{j-1/2} + F_{j+1/2}) / 2.
+  const double qmean = Qtot / (double)nc;
+  double F[CELLS];
+  double rsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) {
+    const bool in = (k < per) && (j0 + k < nc);
+    const double r = in ? (Q[k] - qmean) : 0.0;
+    rsum += r;
+    F[k] = r;
+  }
+  const double fbase = block_incl_scan(rsum, sWd) - rsum;
+  double fsum = 0.0;
+  {
+    double run = fbase;
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      const bool in = (k < per) && (j0 + k < nc);
+      run += F[k];
+      F[k] = in ? run : 0.0;
+      if (in) fsum += F[k];
+    }
+  }
+  const double fmean = block_sum(fsum, sWd) / (double)nc;
+  double lastF = 0.0;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) {
+    if ((k < per) && (j0 + k < nc)) {
+      F[k] -= fmean;
+      lastF = F[k];
+    }
+  }
+  if (tid < kSolveThreads) sLastF[tid] = lastF;
+  __syncthreads();
+  double prevF = (tid == 0) ? sLastF[(nc - 1) / per] : (tid < kSolveThreads ? sLastF[tid - 1] : 0.0);
+  double w2 = 0.0;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) {
+    const int j = j0 + k;
+    if ((k < per) && (j < nc)) {
+      const double e = 0.5 * (prevF + F[k]);
+      prevF = F[k];
+      if (sE) sE[j] = e;
+      if (write_field) {
+        gE[j] = e;
+        gR[j] = (Q[k] - qmean) / dx;
+      }
+      w2 += e * e;
+      finite = finite && (e - e == 0.0);
+    }
+  }
+  // the field energy and the count of non-finite values, in one pass
+  w2 = wave_sum(w2);
+  int nbad = wave_sum(finite ? 0 : 1);
+  if ((tid & 63) == 0) {
+    sWd[tid >> 6] = w2;
+    sWi[tid >> 6] = nbad;
+  }
+  __syncthreads();
+  const double W = 0.5 * dx * (sWd[0] + sWd[1] + sWd[2] + sWd[3]);
+  const int bad = (int)(sWi[0] + sWi[1] + sWi[2] + sWi[3]);
+  __syncthreads();
+
+  // 4. diagnostics and step bookkeeping
+  const bool pushed = (a.flags & kHavePush) != 0;
+  const int64_t step = pushed ? step0 + 1 : step0;
+  int f = 0;
+  if (bad || !(W - W == 0.0)) f |= 1;
+  // a move with a non-finite velocity (its kinetic energy or momentum)
+  if (pushed && !((ke - ke == 0.0) && (mom - mom == 0.0))) f |= 1;
+  if (a.flags & kHaveDeposit) {
+    if (ms != ms) f |= 1;
+    else if (ms > 0.45 * L) f |= 2;
+  }
+  const int flags = flags0 | f;
+  if (tid == 0 && writer) {
+    Ip->flags = flags;
+    const int64_t cap = kc.hist_cap;
+    DiagRow *H = a.hist + kc.hist_off;
+    DiagRow r;
+    r.step = step;
+    r.t = (double)step * dt;
+    r.W_E = W;
+    r.KE = __longlong_as_double(0x7ff8000000000000ll);
+    r.momentum = r.KE;
+    r.total_charge = Qtot;
+    r.max_segment = (a.flags & kHaveDeposit) ? ms : r.KE;
+    r.flags = flags;
+    H[step % cap] = r;
+    if (pushed && step >= 1) {
+      DiagRow *prev = H + (step - 1) % cap;
+      prev->KE = ke;
+      prev->momentum = mom;
+    }
+    Ip->step = step;
+    if ((a.flags & kBatchStep) && pushed && Ip->steps_left > 0) {
+      const int64_t left = Ip->steps_left - 1;
+      Ip->steps_left = left;
+      if (left == 0) {
+        Ip->active = 0;
+        a.done[slot] = 1;
+      }
+    }
+  }
+  return flags;
+}
+
+// ---------------------------------------------------------------------------
 // Tracer kernel
 // ---------------------------------------------------------------------------
 // Per-item LDS layout (bytes): P, D (and for linear segments R) accumulators
@@ -859,7 +1140,11 @@ __device__ __forceinline__ double tracer_mass(uint64_t left, uint64_t right, dou
   }
 }
 
-template <int PREC, int MODE, int ORDER, bool SEG>
+// SF > 0: a solve-first launch of a single simulation (push + deposit,
+// constant segments): before its work items the workgroup solves the
+// previous step's charge (SF cells per solve thread) for the field, as a
+// solve launch would, instead of reading it.
+template <int PREC, int MODE, int ORDER, bool SEG, int SF = 0>
 __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, unsigned long long>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -891,6 +1176,96 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
   // chunks whose state is in flight per wavefront (a deposit alone reads 8
   // bytes per tracer and keeps more of them in flight)
   constexpr int kPrefetch = kField ? 3 : 6;
+  static_assert(SF == 0 || (MODE == (kPush | kDeposit) && ORDER == 0), "solve-first: the fused step, constant segments");
+
+  if constexpr (SF > 0) {
+    // Every workgroup solves the same charge with the same arithmetic, so
+    // all hold the field the previous solve launch would have written; the
+    // first one writes it and the diagnostics row (with the previous
+    // launch's partials, summed in the order the solve launch sums them)
+    // and advances the step.  The accumulators of two steps back are
+    // cleared here, a slice per workgroup (no launch merges into them
+    // before the next one).
+    using sacc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+    const int slot = a.items[0].inst;
+    const InstDesc &I0 = a.inst[slot];
+    const SlotConst kc = slot_const(I0);
+    const bool writer = blockIdx.x == 0;
+    sacc_t pv[SF], dv[SF];
+    {
+      const sacc_t *gP = reinterpret_cast<const sacc_t *>(a.sf_P) + kc.mesh_off;
+      const sacc_t *gD = reinterpret_cast<const sacc_t *>(a.sf_D) + kc.mesh_off;
+      const int per = (kc.nc + kSolveThreads - 1) / kSolveThreads;
+      const int j0 = tid * per;
+#pragma unroll
+      for (int k = 0; k < SF; ++k) {
+        pv[k] = (sacc_t)0;
+        dv[k] = (sacc_t)0;
+        const int j = j0 + k;
+        if (k < per && j < kc.nc) {
+          pv[k] = gP[j];
+          dv[k] = gD[j];
+        }
+      }
+    }
+    {
+      const int z0 = (int)((int64_t)kc.nc * blockIdx.x / gridDim.x);
+      const int z1 = (int)((int64_t)kc.nc * (blockIdx.x + 1) / gridDim.x);
+      acc_t *zP = reinterpret_cast<acc_t *>(a.sf_zP) + kc.mesh_off;
+      acc_t *zD = reinterpret_cast<acc_t *>(a.sf_zD) + kc.mesh_off;
+      for (int i = z0 + tid; i < z1; i += blockDim.x) {
+        zP[i] = (acc_t)0;
+        zD[i] = (acc_t)0;
+      }
+    }
+    double ke = 0.0, mom = 0.0, ms = 0.0;
+    if (writer) {
+      // as the solve launch: threads tid < 256 sum the slot's items tid,
+      // tid + 256, ... (four at a time), then the wavefront sums and waves
+      // 0..3 in order
+      constexpr int kU = 4;
+      const int2 si = a.sf.slot_items[slot];
+      const Partial *pp = a.sf_partials + si.x;
+      if (tid < kSolveThreads) {
+        for (int i0 = tid; i0 < si.y; i0 += kU * kSolveThreads) {
+          Partial pr[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * kSolveThreads;
+            if (i < si.y) pr[u] = pp[i];
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            if (i0 + u * kSolveThreads < si.y) {
+              ke += pr[u].ke;
+              mom += pr[u].mom;
+              ms = nan_max(ms, pr[u].maxseg);
+            }
+          }
+        }
+      }
+      ke = wave_sum(ke);
+      mom = wave_sum(mom);
+      ms = wave_max(ms);
+      if (lane == 0) {
+        sRed[wave] = ke;
+        sRed[16 + wave] = mom;
+        sRed[32 + wave] = ms;
+      }
+      __syncthreads();
+      ke = sRed[0] + sRed[1] + sRed[2] + sRed[3];
+      mom = sRed[16] + sRed[17] + sRed[18] + sRed[19];
+      ms = nan_max(nan_max(sRed[32], sRed[33]), nan_max(sRed[34], sRed[35]));
+      __syncthreads();
+    }
+    solve_slot<PREC, SF>(a.sf, slot, kc, writer ? I0.step : 0, writer ? I0.flags : 0, pv, dv, (acc_t *)nullptr, ke,
+                         mom, ms, sE, writer, writer);
+    if (tid == 0) {
+      sE[-1] = sE[kc.nc - 1];
+      sE[kc.nc] = sE[0];
+    }
+    __syncthreads();
+  }
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item item = a.items[it];
@@ -944,9 +1319,9 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         sD[i] = (acc_t)0;
         if constexpr (kLin) sR[i] = (acc_t)0;
       }
-      if constexpr (kField) sE[i] = a.meshE[I.mesh_off + i];
+      if constexpr (kField && SF == 0) sE[i] = a.meshE[I.mesh_off + i];
     }
-    if constexpr (kField) {
+    if constexpr (kField && SF == 0) {
       if (tid == 0) {
         sE[-1] = a.meshE[I.mesh_off + g.nc - 1];
         sE[g.nc] = a.meshE[I.mesh_off];
@@ -1540,284 +1915,6 @@ k_deposit_faces(TracerArgs a) {
     }
     __syncthreads();
   }
-}
-
-// ---------------------------------------------------------------------------
-// Field solve
-// ---------------------------------------------------------------------------
-namespace {
-
-// Inclusive scan over the 256-thread block of one value per thread, in a
-// fixed order.  sWave holds 4 entries.
-template <class T>
-__device__ __forceinline__ T block_incl_scan(T v, T *sWave) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  v = wave_incl_scan(v, [](T x, T y) { return x + y; });
-  if (lane == 63) sWave[wave] = v;
-  __syncthreads();
-  T base = (T)0;
-  for (int w = 0; w < wave; ++w) base += sWave[w];
-  __syncthreads();
-  return v + base;
-}
-
-template <class T>
-__device__ __forceinline__ T block_sum(T v, T *sWave) {
-  v = wave_sum(v);
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sWave[wave] = v;
-  __syncthreads();
-  const T r = sWave[0] + sWave[1] + sWave[2] + sWave[3];
-  __syncthreads();
-  return r;
-}
-
-
-}  // namespace
-
-// The solve of one slot by one workgroup of kSolveThreads threads: charge
-// per cell from the P/D (and R) accumulators, which it clears; mean removal,
-// Gauss's law, cell-centre field, field energy; the diagnostics row and the
-// step count.  ke, mom, ms are the slot's kinetic-energy, momentum and
-// max-segment sums of the step.  The accumulators may be the slot's global
-// mesh (k_solve) or a workgroup's LDS copy (k_resident); with sE the field is
-// also left in LDS.
-// The slot's constants the solve needs, read once by its caller.
-struct SlotConst {
-  int nc;
-  double L, dx, dt, q_unit;
-  int64_t mesh_off, hist_off, hist_cap;
-};
-
-__device__ __forceinline__ SlotConst slot_const(const InstDesc &I) {
-  SlotConst k;
-  k.nc = I.n_cells;
-  k.L = I.L;
-  k.dx = I.dx;
-  k.dt = I.dt;
-  k.q_unit = I.q_unit;
-  k.mesh_off = I.mesh_off;
-  k.hist_off = I.hist_off;
-  k.hist_cap = I.hist_cap;
-  return k;
-}
-
-// The slot's point (P) and difference (D) accumulators of this thread's
-// cells, read and cleared: the first half of the solve, apart so that a
-// caller can have these loads in flight with others.
-template <int PREC, int CELLS, class Acc, class T>
-__device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD, T (&pv)[CELLS], T (&dv)[CELLS]) {
-  const int nc = kc.nc;
-  const int per = (nc + kSolveThreads - 1) / kSolveThreads;
-  const int j0 = threadIdx.x * per;
-#pragma unroll
-  for (int k = 0; k < CELLS; ++k) {
-    pv[k] = (T)0;
-    dv[k] = (T)0;
-    const int j = j0 + k;
-    if (k < per && j < nc) {
-      pv[k] = (T)gP[j];
-      dv[k] = (T)gD[j];
-      gP[j] = (Acc)0;
-      gD[j] = (Acc)0;
-    }
-  }
-}
-
-// step0 and flags0 are the slot's step and sticky flags before this solve;
-// pv, dv this thread's accumulators from solve_take; returns the flags after
-// it (the same value in every thread).  With write_field false the field and
-// density are left in sE only (the resident kernel writes them to global
-// memory on its last step).
-template <int PREC, int CELLS, class Acc, class T>
-__device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const SlotConst &kc, int64_t step0,
-                                          int flags0, const T (&pv)[CELLS], const T (&dv)[CELLS], Acc *gRamp,
-                                          double ke, double mom, double ms, double *sE, bool write_field) {
-  using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
-  static_assert(std::is_same<acc_t, T>::value, "accumulator type");
-  // The cells are partitioned over kSolveThreads threads; a wider workgroup
-  // (the resident kernel's) runs the same code, its other threads holding no
-  // cells and adding zeros, so the result has the same bits.
-  __shared__ double sWd[16];
-  __shared__ long long sWi[16];
-  __shared__ double sLastF[kSolveThreads];
-  InstDesc *Ip = a.inst + slot;
-  const int tid = threadIdx.x;
-  const int nc = kc.nc;
-  const double L = kc.L, dx = kc.dx, dt = kc.dt;
-  const double q_unit = kc.q_unit;
-
-  // 2. charge per cell: Q_j = P_j + sum_{m <= j} D_m
-  const int per = (nc + kSolveThreads - 1) / kSolveThreads;
-  const int j0 = tid * per;
-  double *gE = a.meshE + kc.mesh_off;
-  double *gR = a.meshRho + kc.mesh_off;
-  acc_t dsum = (acc_t)0;
-#pragma unroll
-  for (int k = 0; k < CELLS; ++k) dsum += dv[k];
-  auto scan = [&](acc_t v) -> acc_t {
-    if constexpr (PREC == kFP64) return block_incl_scan(v, sWd);
-    else return block_incl_scan(v, sWi);
-  };
-  const acc_t dbase = scan(dsum) - dsum;
-  // Linear ramps of piecewise-linear segments: the charge adds the second
-  // prefix sum of R (zero for piecewise-constant segments).
-  acc_t r2[CELLS];
-#pragma unroll
-  for (int k = 0; k < CELLS; ++k) r2[k] = (acc_t)0;
-  if (gRamp != nullptr) {  // only piecewise-linear segments have ramps
-    acc_t rsum = (acc_t)0;
-#pragma unroll
-    for (int k = 0; k < CELLS; ++k) {
-      const int j = j0 + k;
-      if (k < per && j < nc) {
-        r2[k] = (acc_t)gRamp[j];
-        gRamp[j] = (Acc)0;
-      }
-      rsum += r2[k];
-    }
-    const acc_t base1 = scan(rsum) - rsum;
-    acc_t run1 = base1, s1sum = (acc_t)0;
-#pragma unroll
-    for (int k = 0; k < CELLS; ++k) {
-      run1 += r2[k];
-      r2[k] = run1;
-      if ((k < per) && (j0 + k < nc)) s1sum += run1;
-    }
-    const acc_t base2 = scan(s1sum) - s1sum;
-    acc_t run2 = base2;
-#pragma unroll
-    for (int k = 0; k < CELLS; ++k) {
-      if ((k < per) && (j0 + k < nc)) run2 += r2[k];
-      r2[k] = run2;
-    }
-  }
-  double Q[CELLS];
-  acc_t qsum_acc = (acc_t)0;
-  {
-    acc_t run = dbase;
-#pragma unroll
-    for (int k = 0; k < CELLS; ++k) {
-      run += dv[k];
-      const acc_t qa = pv[k] + run + r2[k];
-      const bool in = (k < per) && (j0 + k < nc);
-      if constexpr (PREC == kFP64) Q[k] = in ? qa : 0.0;
-      else Q[k] = in ? (double)qa * q_unit : 0.0;
-      if (in) qsum_acc += qa;
-    }
-  }
-  double Qtot;
-  if constexpr (PREC == kFP64) Qtot = block_sum(qsum_acc, sWd);
-  else Qtot = (double)block_sum(qsum_acc, sWi) * q_unit;
-
-  // 3. Gauss's law on faces: F_{j+1/2} = F_{j-1/2} + (Q_j - Qtot/nc),
-  //    F shifted to zero mean; E_j = (F_{j-1/2} + F_{j+1/2}) / 2.
-  const double qmean = Qtot / (double)nc;
-  double F[CELLS];
-  double rsum = 0.0;
-#pragma unroll
-  for (int k = 0; k < CELLS; ++k) {
-    const bool in = (k < per) && (j0 + k < nc);
-    const double r = in ? (Q[k] - qmean) : 0.0;
-    rsum += r;
-    F[k] = r;
-  }
-  const double fbase = block_incl_scan(rsum, sWd) - rsum;
-  double fsum = 0.0;
-  {
-    double run = fbase;
-#pragma unroll
-    for (int k = 0; k < CELLS; ++k) {
-      const bool in = (k < per) && (j0 + k < nc);
-      run += F[k];
-      F[k] = in ? run : 0.0;
-      if (in) fsum += F[k];
-    }
-  }
-  const double fmean = block_sum(fsum, sWd) / (double)nc;
-  double lastF = 0.0;
-#pragma unroll
-  for (int k = 0; k < CELLS; ++k) {
-    if ((k < per) && (j0 + k < nc)) {
-      F[k] -= fmean;
-      lastF = F[k];
-    }
-  }
-  if (tid < kSolveThreads) sLastF[tid] = lastF;
-  __syncthreads();
-  double prevF = (tid == 0) ? sLastF[(nc - 1) / per] : (tid < kSolveThreads ? sLastF[tid - 1] : 0.0);
-  double w2 = 0.0;
-  bool finite = true;
-#pragma unroll
-  for (int k = 0; k < CELLS; ++k) {
-    const int j = j0 + k;
-    if ((k < per) && (j < nc)) {
-      const double e = 0.5 * (prevF + F[k]);
-      prevF = F[k];
-      if (sE) sE[j] = e;
-      if (write_field) {
-        gE[j] = e;
-        gR[j] = (Q[k] - qmean) / dx;
-      }
-      w2 += e * e;
-      finite = finite && (e - e == 0.0);
-    }
-  }
-  // the field energy and the count of non-finite values, in one pass
-  w2 = wave_sum(w2);
-  int nbad = wave_sum(finite ? 0 : 1);
-  if ((tid & 63) == 0) {
-    sWd[tid >> 6] = w2;
-    sWi[tid >> 6] = nbad;
-  }
-  __syncthreads();
-  const double W = 0.5 * dx * (sWd[0] + sWd[1] + sWd[2] + sWd[3]);
-  const int bad = (int)(sWi[0] + sWi[1] + sWi[2] + sWi[3]);
-  __syncthreads();
-
-  // 4. diagnostics and step bookkeeping
-  const bool pushed = (a.flags & kHavePush) != 0;
-  const int64_t step = pushed ? step0 + 1 : step0;
-  int f = 0;
-  if (bad || !(W - W == 0.0)) f |= 1;
-  // a move with a non-finite velocity (its kinetic energy or momentum)
-  if (pushed && !((ke - ke == 0.0) && (mom - mom == 0.0))) f |= 1;
-  if (a.flags & kHaveDeposit) {
-    if (ms != ms) f |= 1;
-    else if (ms > 0.45 * L) f |= 2;
-  }
-  const int flags = flags0 | f;
-  if (tid == 0) {
-    Ip->flags = flags;
-    const int64_t cap = kc.hist_cap;
-    DiagRow *H = a.hist + kc.hist_off;
-    DiagRow r;
-    r.step = step;
-    r.t = (double)step * dt;
-    r.W_E = W;
-    r.KE = __longlong_as_double(0x7ff8000000000000ll);
-    r.momentum = r.KE;
-    r.total_charge = Qtot;
-    r.max_segment = (a.flags & kHaveDeposit) ? ms : r.KE;
-    r.flags = flags;
-    H[step % cap] = r;
-    if (pushed && step >= 1) {
-      DiagRow *prev = H + (step - 1) % cap;
-      prev->KE = ke;
-      prev->momentum = mom;
-    }
-    Ip->step = step;
-    if ((a.flags & kBatchStep) && pushed && Ip->steps_left > 0) {
-      const int64_t left = Ip->steps_left - 1;
-      Ip->steps_left = left;
-      if (left == 0) {
-        Ip->active = 0;
-        a.done[slot] = 1;
-      }
-    }
-  }
-  return flags;
 }
 
 // CELLS: cells per thread the solve is unrolled for (at least the pool's
@@ -2586,6 +2683,48 @@ int set_tracer_lds_limit(int prec, int order, bool seg, size_t lds) {
   const hipError_t e = dispatch<SetLdsLimit>(prec, order, seg, lds);
   if (e == hipSuccess) g = lds;
   return (int)e;
+}
+
+// Solve-first launches (single simulations, constant segments).
+template <int PREC, bool SEG, int SF>
+static hipError_t tracers_sf_launch(const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
+  static bool limit_set = false;
+  if (!limit_set && lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void *)k_tracers<PREC, kPush | kDeposit, 0, SEG, SF>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    if (e != hipSuccess) return e;
+    limit_set = true;
+  }
+  hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit, 0, SEG, SF>), dim3(grid), dim3(block), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int PREC, bool SEG>
+static hipError_t tracers_sf_cells(const TracerArgs &a, int grid, int block, size_t lds, int max_cells,
+                                   hipStream_t st) {
+  const int per = (max_cells + kSolveThreads - 1) / kSolveThreads;
+  if (per <= 1) return tracers_sf_launch<PREC, SEG, 1>(a, grid, block, lds, st);
+  if (per <= 4) return tracers_sf_launch<PREC, SEG, 4>(a, grid, block, lds, st);
+  return tracers_sf_launch<PREC, SEG, 16>(a, grid, block, lds, st);
+}
+
+int launch_tracers_sf(int prec, bool seg, const TracerArgs &a, int grid, int block, size_t lds, int max_cells,
+                      void *stream) {
+  if (grid <= 0) return 0;
+  if (max_cells < 1 || max_cells > kMaxCells || block < kSolveThreads) return (int)hipErrorInvalidValue;
+  hipStream_t st = (hipStream_t)stream;
+  switch (prec) {
+    case kFP64:
+      return (int)(seg ? tracers_sf_cells<kFP64, true>(a, grid, block, lds, max_cells, st)
+                       : tracers_sf_cells<kFP64, false>(a, grid, block, lds, max_cells, st));
+    case kSplitF32:
+      return (int)(seg ? tracers_sf_cells<kSplitF32, true>(a, grid, block, lds, max_cells, st)
+                       : tracers_sf_cells<kSplitF32, false>(a, grid, block, lds, max_cells, st));
+    case kSplitU32:
+      return (int)(seg ? tracers_sf_cells<kSplitU32, true>(a, grid, block, lds, max_cells, st)
+                       : tracers_sf_cells<kSplitU32, false>(a, grid, block, lds, max_cells, st));
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 int launch_tracers(int prec, int mode, int order, bool seg, const TracerArgs &a, int grid, int block, size_t lds,

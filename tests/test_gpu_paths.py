@@ -41,10 +41,67 @@ def test_resident_and_fused_paths_agree(prec):
         assert np.array_equal(r[4]["history"]["W_E"], f[4]["history"]["W_E"])
 
 
-def test_larger_simulation_takes_the_fused_path():
+def test_larger_simulation_takes_the_solve_first_path():
     p = I.landau(n_sheets=64, n_tracers=256, n_cells=64)
     path, *_ = _run(p, B.SIC_FP64, 3, 0)
+    assert path == B.SIC_PATH_SOLVE_FIRST
+    path, *_ = _run(p, B.SIC_FP64, 3, 1)
     assert path == B.SIC_PATH_FUSED
+
+
+def _timed_classic(p, prec, steps):
+    """The same steps as tracer/solve launch pairs (timing mode)."""
+    with B.Simulation(p, precision=prec) as s:
+        B.sic_set_timing(s.h, True)
+        s.step(steps)
+        assert B.sic_last_step_path(s.h) == B.SIC_PATH_FUSED
+        x, v, st = s.state()
+        d = s.diagnostics()
+    return x, v, st, d
+
+
+SF_CASES = {
+    # 2048 chunks on 256 cells (one solve thread per cell)
+    "landau_256x512": lambda: I.landau(),
+    # ragged sheets, 100 cells
+    "ragged_37x300": lambda: I.landau(n_sheets=37, n_tracers=300, n_cells=100, alpha=0.05),
+    # 1024 cells (four cells per solve thread), two-stream
+    "two_stream_64x1024": lambda: I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=100),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SF_CASES))
+@pytest.mark.parametrize("prec", [B.SIC_SPLIT_U32, B.SIC_SPLIT_F32, B.SIC_FP64])
+def test_solve_first_steps_give_the_fused_bits(case, prec):
+    """Steps in calls of 1, 2, 33 and 9 (graphs of one step, of two, across
+    the 32-step graph size, and a remainder), then one launch pair, against
+    46 steps of launch pairs: the same state, history rows and step count."""
+    p = SF_CASES[case]()
+    print(f"case solve-first {case} prec={prec}", flush=True)
+    with B.Simulation(p, precision=prec) as s:
+        for n in (1, 2, 33, 9):
+            s.step(n)
+            assert B.sic_last_step_path(s.h) == B.SIC_PATH_SOLVE_FIRST
+        # one more step as a launch pair: it deposits into the pool's own
+        # accumulators, which the solve-first steps must have left clear
+        B.sic_set_timing(s.h, True)
+        s.step(1)
+        x, v, st = s.state()
+        d = s.diagnostics()
+    xr, vr, sr, dr = _timed_classic(p, prec, 46)
+    assert st == sr == 46
+    h, hr = d["history"], dr["history"]
+    assert np.array_equal(h["step"], hr["step"])
+    if prec == B.SIC_FP64:
+        # float64 atomics may add in another order
+        assert np.max(periodic_diff(x, xr, p.L)) < 1e-11 * p.L
+        np.testing.assert_allclose(h["W_E"], hr["W_E"], rtol=1e-10)
+        np.testing.assert_allclose(h["KE"][:-1], hr["KE"][:-1], rtol=1e-12)
+    else:
+        assert np.array_equal(x, xr) and np.array_equal(v, vr)
+        for col in ("W_E", "KE", "momentum", "total_charge", "max_segment"):
+            assert np.array_equal(h[col], hr[col], equal_nan=True), col
+        assert np.array_equal(h["flags"], hr["flags"])
 
 
 def test_refining_simulation_reports_its_path():
