@@ -145,9 +145,11 @@ struct Pool {
   InstDesc *inst = nullptr;
   int2 *slot_items = nullptr;
   Partial *partials = nullptr;
+  // P, D (and R) in rep copies of slot_cap * max_cells words each
   void *meshP = nullptr;
   void *meshD = nullptr;
   void *meshR = nullptr;  // order 1
+  int rep = 1;
   double *meshE = nullptr;
   double *meshRho = nullptr;
   DiagRow *hist = nullptr;
@@ -177,7 +179,7 @@ struct Pool {
   // solve-first steps of a single simulation (allocated on first use): two
   // more accumulator pairs (the pool's own is the third) and a second set of
   // work-item partials
-  void *sf_mesh = nullptr;     // P1, D1, P2, D2: max_cells words each
+  void *sf_mesh = nullptr;     // P1, D1, P2, D2: rep copies of mesh_words each
   Partial *sf_part = nullptr;  // item_cap
 
   std::vector<SlotHost> slots;
@@ -357,16 +359,17 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
     double *sp = nullptr;
     (void)scratch_address(p->device, &sp);
   }
+  p->rep = batch ? 1 : kSingleRep;
   {
     const size_t mc = (size_t)slot_cap * max_cells;
     long long *mp = nullptr, *md = nullptr;
-    ALLOC(mp, mc);
+    ALLOC(mp, mc * p->rep);
     p->meshP = mp;
-    ALLOC(md, mc);
+    ALLOC(md, mc * p->rep);
     p->meshD = md;
     if (order == 1) {
       long long *mr = nullptr;
-      ALLOC(mr, mc);
+      ALLOC(mr, mc * p->rep);
       p->meshR = mr;
     }
     ALLOC(p->meshE, mc);
@@ -380,9 +383,9 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
   if (e != hipSuccess) return bail(std::string("hipStreamCreate: ") + hipGetErrorString(e), SIC_EDEVICE);
   // zero-initialise everything the kernels accumulate into or read as tables
   const size_t mc = (size_t)slot_cap * max_cells;
-  e = hipMemsetAsync(p->meshP, 0, mc * 8, p->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(p->meshD, 0, mc * 8, p->stream);
-  if (e == hipSuccess && p->meshR) e = hipMemsetAsync(p->meshR, 0, mc * 8, p->stream);
+  e = hipMemsetAsync(p->meshP, 0, mc * 8 * p->rep, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->meshD, 0, mc * 8 * p->rep, p->stream);
+  if (e == hipSuccess && p->meshR) e = hipMemsetAsync(p->meshR, 0, mc * 8 * p->rep, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->meshE, 0, mc * 8, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->meshRho, 0, mc * 8, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->inst, 0, sizeof(InstDesc) * (size_t)slot_cap, p->stream);
@@ -591,9 +594,9 @@ sic_status snapshot_take(Pool *p, Snapshot &s) {
       {p->halo[1], (size_t)p->chunk_cap * sizeof(double2)},
       {p->halo3[0], p->halo3[0] ? 3 * (size_t)p->chunk_cap * sizeof(double2) : 0},
       {p->halo3[1], p->halo3[1] ? 3 * (size_t)p->chunk_cap * sizeof(double2) : 0},
-      {p->meshR, p->meshR ? mc : 0},
-      {p->meshP, mc},
-      {p->meshD, mc},
+      {p->meshR, p->meshR ? mc * p->rep : 0},
+      {p->meshP, mc * p->rep},
+      {p->meshD, mc * p->rep},
       {p->meshE, mc},
       {p->meshRho, mc},
       {p->inst, sizeof(InstDesc) * (size_t)p->slot_cap},
@@ -701,6 +704,9 @@ sic_status pool_autotune(Pool *p, int32_t steps, sic_tuning *best_out, double *b
   return SIC_OK;
 }
 
+// Words of one copy of a charge accumulator (every slot's mesh).
+int64_t mesh_words(const Pool *p) { return (int64_t)p->slot_cap * p->max_cells; }
+
 TracerArgs tracer_args(Pool *p, int mode, int slot) {
   TracerArgs a;
   const bool one = slot >= 0;
@@ -726,6 +732,8 @@ TracerArgs tracer_args(Pool *p, int mode, int slot) {
   a.cedge = p->cedge;
   a.mesh_cells = p->max_cells;
   a.tile_cap = p->tile;
+  a.rep = p->rep;
+  a.rep_stride = mesh_words(p);
   // batches skip finished slots; a single simulation refining on the device
   // is made inactive when a pass would exceed its capacity
   a.respect_active = ((p->batch || p->dev_refine) && !one) ? 1 : 0;
@@ -748,6 +756,8 @@ SolveArgs solve_args(Pool *p, int flags, int slot) {
   a.done = p->done;
   a.flags = flags;
   a.respect_active = ((p->batch || p->dev_refine) && slot < 0) ? 1 : 0;
+  a.rep = p->rep;
+  a.rep_stride = mesh_words(p);
   return a;
 }
 
@@ -826,10 +836,11 @@ sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
 // tracer/solve launch pairs: the same solve code, the same sums in the same
 // order.
 bool sf_ready(Pool *p) {
-  if (p->batch || p->order != 0 || p->timing || p->dev_refine || p->tune.fused_only || p->block < kSolveThreads)
+  if (p->batch || p->order != 0 || p->timing || p->dev_refine || p->tune.fused_only || p->block < kSolveThreads ||
+      p->rep != kSingleRep)
     return false;
   if (!p->sf_mesh) {
-    const size_t bytes = sizeof(double) * 4 * (size_t)p->max_cells;
+    const size_t bytes = sizeof(double) * 4 * (size_t)p->rep * mesh_words(p);
     if (hipMalloc(&p->sf_mesh, bytes) != hipSuccess) {
       p->sf_mesh = nullptr;
       return false;
@@ -846,8 +857,9 @@ bool sf_ready(Pool *p) {
 }
 
 sic_status enqueue_sf(Pool *p, int64_t k, hipStream_t st) {
+  // each pair's copies lie mesh_words apart, as the pool's own
   double *m = static_cast<double *>(p->sf_mesh);
-  const size_t mc = (size_t)p->max_cells;
+  const size_t mc = (size_t)p->rep * mesh_words(p);
   void *AP[3] = {p->meshP, m, m + 2 * mc};
   void *AD[3] = {p->meshD, m + mc, m + 3 * mc};
   Partial *PB[2] = {p->partials, p->sf_part};
@@ -876,7 +888,8 @@ sic_status enqueue_sf(Pool *p, int64_t k, hipStream_t st) {
   sa.partials = PB[(k - 1) % 2];
   LAUNCHCHK(p, launch_solve(p->prec, sa, p->solve_grid, p->max_cells, st));
   if (k >= 2)
-    LAUNCHCHK(p, launch_zero_mesh(p->prec, AP[(k - 2) % 3], AD[(k - 2) % 3], nullptr, p->inst, p->slot_ids, 1, st));
+    LAUNCHCHK(p, launch_zero_mesh(p->prec, AP[(k - 2) % 3], AD[(k - 2) % 3], nullptr, p->inst, p->slot_ids, 1, p->rep,
+                                  mesh_words(p), st));
   return SIC_OK;
 }
 
@@ -1290,7 +1303,8 @@ sic_status pool_admit(Pool *p, const sic_config *cfg, const sic_sheet *sheets, i
   update_solve_grid(p);
   // ingest: place tracers, deposit, solve, half back-kick
   int le = ingest_slot(p, slot, dx0, nullptr, dv0, dc0, nullptr);
-  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
+  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->rep,
+                                         mesh_words(p), p->stream);
   if (le != 0) {
     if (stage) hipFree(stage);
     return fail(p, SIC_EDEVICE, std::string("ingest: ") + hipGetErrorString((hipError_t)le));
@@ -1346,7 +1360,8 @@ sic_status pool_relayout(Pool *p, int32_t slot, const std::vector<int32_t> &nt, 
   }
   if (e != hipSuccess) return fail(p, SIC_EDEVICE, std::string("re-layout copies: ") + hipGetErrorString(e));
   int le = ingest_slot(p, slot, x, w, v, c, cw);
-  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
+  if (le == 0) le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->rep,
+                                         mesh_words(p), p->stream);
   if (le != 0) return fail(p, SIC_EDEVICE, std::string("re-layout ingest: ") + hipGetErrorString((hipError_t)le));
   sh.pending_push = sh.pending_dep = false;
   if (redeposit) {
@@ -1670,7 +1685,8 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
   // positions and velocities only: the layout and the charges stay
   int le = (e == hipSuccess) ? ingest_slot(p, slot, dx, nullptr, dv, nullptr, nullptr, true) : 0;
   if (le == 0 && e == hipSuccess)
-    le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->stream);
+    le = launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids + slot, 1, p->rep,
+                                         mesh_words(p), p->stream);
   hipError_t e2 = hipStreamSynchronize(p->stream);
   if (stage) hipFree(stage);
   if (e != hipSuccess || e2 != hipSuccess || le != 0) return fail(p, SIC_EDEVICE, "set_state failed");
@@ -1684,7 +1700,8 @@ sic_status pool_set_state(Pool *p, int32_t slot, int64_t step, const double *x, 
 sic_status sim_deposit(Pool *p) {
   SlotHost &sh = p->slots[0];
   if (sh.state == kDeposited) {
-    LAUNCHCHK(p, launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids, 1, p->stream));
+    LAUNCHCHK(p, launch_zero_mesh(p->prec, p->meshP, p->meshD, p->meshR, p->inst, p->slot_ids, 1, p->rep,
+                                  mesh_words(p), p->stream));
   }
   sic_status st = launch_tracer_mode(p, kDeposit, -1, p->stream);
   if (st != SIC_OK) return st;

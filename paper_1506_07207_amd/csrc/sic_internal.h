@@ -33,6 +33,11 @@ namespace sic {
 
 constexpr int kChunk = 64;          // tracer slots per chunk = wavefront width
 constexpr int kMaxCells = 4096;     // mirrors SIC_MAX_CELLS
+// Copies of a single simulation's charge accumulators (P, D, R): its work
+// items merge into copy (item mod kSingleRep), so each address takes a
+// quarter of the atomics, and the solve sums the copies in order.  Batches,
+// with few items per simulation, keep one copy.
+constexpr int kSingleRep = 4;
 constexpr int kSolveThreads = 256;  // field-solve workgroup
 
 enum Prec : int { kFP64 = 0, kSplitF32 = 1, kSplitU32 = 2 };
@@ -120,6 +125,10 @@ struct SolveArgs {
   int32_t respect_active;
   int32_t order;             // deposit order of the pool (0, 1 or 2); R exists only for 1
   const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
+  // P, D and R are held in rep copies rep_stride words apart; the solve
+  // sums them in copy order and clears each
+  int32_t rep = 1;
+  int64_t rep_stride = 0;
 };
 
 struct TracerArgs {
@@ -145,6 +154,11 @@ struct TracerArgs {
   int32_t tile_cap;        // LDS capacity in chunks per work item
   int32_t respect_active;  // skip slots with active == 0
   const int32_t *gate = nullptr;  // non-NULL: the launch does nothing unless *gate > 0
+  // copies of P, D and R, rep_stride words apart: work item i merges into
+  // copy i mod rep (fewer atomics on one address when many items share a
+  // mesh)
+  int32_t rep = 1;
+  int64_t rep_stride = 0;
   // Solve-first launches of a single simulation (launch_tracers_sf): every
   // workgroup solves the previous step's charge for the field it pushes
   // with, instead of reading meshE; the first also writes what a solve
@@ -264,8 +278,9 @@ size_t tracer_lds_size(int prec, int order, bool seg, int mesh_cells, int tile_c
 int launch_solve(int prec, const SolveArgs &a, int n_blocks, int max_cells, void *stream);
 int launch_ingest(int prec, const IngestArgs &a, void *stream);
 int launch_extract(int prec, const ExtractArgs &a, void *stream);
+// Clears the meshes of the listed slots in all rep copies (rep_stride words apart).
 int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
-                     const int32_t *slot_list, int n_blocks, void *stream);
+                     const int32_t *slot_list, int n_blocks, int rep, int64_t rep_stride, void *stream);
 // grid: workgroups of 256 threads
 int launch_copy_bench(const double *src, double *dst, int64_t n, int grid, void *stream);
 // Charge edges of chunks [chunk_begin, chunk_begin + n_chunks): prev_slot[c]

@@ -850,6 +850,33 @@ __device__ __forceinline__ T block_sum(T v, T *sWave) {
   return r;
 }
 
+// The solve's scan and sum over its kSolveThreads threads (four wavefronts;
+// wider workgroups' other wavefronts hold zeros and take no part), with the
+// sums in the order of block_incl_scan and block_sum.  Each call site passes
+// four LDS words of its own, so one barrier per call suffices (nothing
+// writes them again before the next solve).
+template <class T>
+__device__ __forceinline__ T solve_incl_scan(T v, T *slot4) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  v = wave_incl_scan(v, [](T x, T y) { return x + y; });
+  if (lane == 63 && wave < 4) slot4[wave] = v;
+  __syncthreads();
+  // wavefronts 0..wave-1 in order; the zeros added after them change no bits
+  T base = (T)0;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) base += (w < wave) ? slot4[w] : (T)0;
+  return v + base;
+}
+template <class T>
+__device__ __forceinline__ T solve_sum(T v, T *slot4) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0 && wave < 4) slot4[wave] = v;
+  __syncthreads();
+  return slot4[0] + slot4[1] + slot4[2] + slot4[3];
+}
+
 
 }  // namespace
 
@@ -881,10 +908,14 @@ __device__ __forceinline__ SlotConst slot_const(const InstDesc &I) {
 }
 
 // The slot's point (P) and difference (D) accumulators of this thread's
-// cells, read and cleared: the first half of the solve, apart so that a
-// caller can have these loads in flight with others.
-template <int PREC, int CELLS, class Acc, class T>
-__device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD, T (&pv)[CELLS], T (&dv)[CELLS]) {
+// cells, summed over their REP copies (rep_stride words apart) in copy
+// order and cleared: the first half of the solve, apart so that a caller can
+// have these loads in flight with others.  The loads are unconditional (a
+// thread past the mesh reads cell 0 and adds zero), so all of them are in
+// flight together; the clearing stores follow.
+template <int PREC, int CELLS, int REP, class Acc, class T>
+__device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD, int64_t rep_stride,
+                                           T (&pv)[CELLS], T (&dv)[CELLS]) {
   const int nc = kc.nc;
   const int per = (nc + kSolveThreads - 1) / kSolveThreads;
   const int j0 = threadIdx.x * per;
@@ -892,12 +923,29 @@ __device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD
   for (int k = 0; k < CELLS; ++k) {
     pv[k] = (T)0;
     dv[k] = (T)0;
-    const int j = j0 + k;
-    if (k < per && j < nc) {
-      pv[k] = (T)gP[j];
-      dv[k] = (T)gD[j];
-      gP[j] = (Acc)0;
-      gD[j] = (Acc)0;
+  }
+#pragma unroll
+  for (int r = 0; r < REP; ++r) {
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      const int j = j0 + k;
+      const bool own = k < per && j < nc;
+      const int64_t at = r * rep_stride + (own ? j : 0);
+      const T p = (T)gP[at];
+      const T d = (T)gD[at];
+      pv[k] += own ? p : (T)0;
+      dv[k] += own ? d : (T)0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < REP; ++r) {
+#pragma unroll
+    for (int k = 0; k < CELLS; ++k) {
+      const int j = j0 + k;
+      if (k < per && j < nc) {
+        gP[r * rep_stride + j] = (Acc)0;
+        gD[r * rep_stride + j] = (Acc)0;
+      }
     }
   }
 }
@@ -909,7 +957,7 @@ __device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD
 // memory on its last step); with writer false nothing at all is written to
 // global memory (the workgroups of a launch that each solve the same charge
 // for their own use, all but one).
-template <int PREC, int CELLS, class Acc, class T>
+template <int PREC, int CELLS, int REP = 1, class Acc, class T>
 __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const SlotConst &kc, int64_t step0,
                                           int flags0, const T (&pv)[CELLS], const T (&dv)[CELLS], Acc *gRamp,
                                           double ke, double mom, double ms, double *sE, bool write_field,
@@ -919,8 +967,10 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
   // The cells are partitioned over kSolveThreads threads; a wider workgroup
   // (the resident kernel's) runs the same code, its other threads holding no
   // cells and adding zeros, so the result has the same bits.
-  __shared__ double sWd[16];
-  __shared__ long long sWi[16];
+  // LDS words of the scans and sums, four per call site
+  __shared__ acc_t sA[4][4];
+  __shared__ double sF[3][4];
+  __shared__ int sBad[4];
   __shared__ double sLastF[kSolveThreads];
   InstDesc *Ip = a.inst + slot;
   const int tid = threadIdx.x;
@@ -936,28 +986,35 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
   acc_t dsum = (acc_t)0;
 #pragma unroll
   for (int k = 0; k < CELLS; ++k) dsum += dv[k];
-  auto scan = [&](acc_t v) -> acc_t {
-    if constexpr (PREC == kFP64) return block_incl_scan(v, sWd);
-    else return block_incl_scan(v, sWi);
-  };
-  const acc_t dbase = scan(dsum) - dsum;
+  const acc_t dbase = solve_incl_scan(dsum, sA[0]) - dsum;
   // Linear ramps of piecewise-linear segments: the charge adds the second
   // prefix sum of R (zero for piecewise-constant segments).
   acc_t r2[CELLS];
 #pragma unroll
   for (int k = 0; k < CELLS; ++k) r2[k] = (acc_t)0;
-  if (gRamp != nullptr) {  // only piecewise-linear segments have ramps
+  if (gRamp != nullptr) {  // only piecewise-linear segments have ramps; REP copies as P and D
+#pragma unroll
+    for (int r = 0; r < REP; ++r) {
+#pragma unroll
+      for (int k = 0; k < CELLS; ++k) {
+        const int j = j0 + k;
+        const bool own = k < per && j < nc;
+        const acc_t v = (acc_t)gRamp[r * a.rep_stride + (own ? j : 0)];
+        r2[k] += own ? v : (acc_t)0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < REP; ++r) {
+#pragma unroll
+      for (int k = 0; k < CELLS; ++k) {
+        const int j = j0 + k;
+        if (k < per && j < nc) gRamp[r * a.rep_stride + j] = (Acc)0;
+      }
+    }
     acc_t rsum = (acc_t)0;
 #pragma unroll
-    for (int k = 0; k < CELLS; ++k) {
-      const int j = j0 + k;
-      if (k < per && j < nc) {
-        r2[k] = (acc_t)gRamp[j];
-        gRamp[j] = (Acc)0;
-      }
-      rsum += r2[k];
-    }
-    const acc_t base1 = scan(rsum) - rsum;
+    for (int k = 0; k < CELLS; ++k) rsum += r2[k];
+    const acc_t base1 = solve_incl_scan(rsum, sA[1]) - rsum;
     acc_t run1 = base1, s1sum = (acc_t)0;
 #pragma unroll
     for (int k = 0; k < CELLS; ++k) {
@@ -965,7 +1022,7 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
       r2[k] = run1;
       if ((k < per) && (j0 + k < nc)) s1sum += run1;
     }
-    const acc_t base2 = scan(s1sum) - s1sum;
+    const acc_t base2 = solve_incl_scan(s1sum, sA[2]) - s1sum;
     acc_t run2 = base2;
 #pragma unroll
     for (int k = 0; k < CELLS; ++k) {
@@ -988,8 +1045,8 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
     }
   }
   double Qtot;
-  if constexpr (PREC == kFP64) Qtot = block_sum(qsum_acc, sWd);
-  else Qtot = (double)block_sum(qsum_acc, sWi) * q_unit;
+  if constexpr (PREC == kFP64) Qtot = solve_sum(qsum_acc, sA[3]);
+  else Qtot = (double)solve_sum(qsum_acc, sA[3]) * q_unit;
 
   // 3. Gauss's law on faces: F_{j+1/2} = F_{j-1/2} + (Q_j - Qtot/nc),
   //    F shifted to zero mean; E_j = (F_{j-1/2} + F_{j+1/2}) / 2.
@@ -1003,7 +1060,7 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
     rsum += r;
     F[k] = r;
   }
-  const double fbase = block_incl_scan(rsum, sWd) - rsum;
+  const double fbase = solve_incl_scan(rsum, sF[0]) - rsum;
   double fsum = 0.0;
   {
     double run = fbase;
@@ -1015,18 +1072,26 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
       if (in) fsum += F[k];
     }
   }
-  const double fmean = block_sum(fsum, sWd) / (double)nc;
+  // F's mean and each thread's last face value behind one barrier; the
+  // neighbour's value is shifted by the mean after the exchange (the same
+  // subtraction, the same bits)
   double lastF = 0.0;
 #pragma unroll
-  for (int k = 0; k < CELLS; ++k) {
-    if ((k < per) && (j0 + k < nc)) {
-      F[k] -= fmean;
-      lastF = F[k];
-    }
+  for (int k = 0; k < CELLS; ++k)
+    if ((k < per) && (j0 + k < nc)) lastF = F[k];
+  {
+    const double fw = wave_sum(fsum);
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0 && wave < 4) sF[1][wave] = fw;
+    if (tid < kSolveThreads) sLastF[tid] = lastF;
   }
-  if (tid < kSolveThreads) sLastF[tid] = lastF;
   __syncthreads();
-  double prevF = (tid == 0) ? sLastF[(nc - 1) / per] : (tid < kSolveThreads ? sLastF[tid - 1] : 0.0);
+  const double fmean = (sF[1][0] + sF[1][1] + sF[1][2] + sF[1][3]) / (double)nc;
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k)
+    if ((k < per) && (j0 + k < nc)) F[k] -= fmean;
+  double prevF =
+      (tid == 0) ? sLastF[(nc - 1) / per] - fmean : (tid < kSolveThreads ? sLastF[tid - 1] - fmean : 0.0);
   double w2 = 0.0;
   bool finite = true;
 #pragma unroll
@@ -1044,17 +1109,22 @@ __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const Sl
       finite = finite && (e - e == 0.0);
     }
   }
-  // the field energy and the count of non-finite values, in one pass
-  w2 = wave_sum(w2);
-  int nbad = wave_sum(finite ? 0 : 1);
-  if ((tid & 63) == 0) {
-    sWd[tid >> 6] = w2;
-    sWi[tid >> 6] = nbad;
+  // the field energy and the count of non-finite values, in one pass (only
+  // a workgroup that writes the diagnostics needs them)
+  double W = 0.0;
+  int bad = 0;
+  if (writer) {
+    w2 = wave_sum(w2);
+    const int nbad = wave_sum(finite ? 0 : 1);
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0 && wave < 4) {
+      sF[2][wave] = w2;
+      sBad[wave] = nbad;
+    }
+    __syncthreads();
+    W = 0.5 * dx * (sF[2][0] + sF[2][1] + sF[2][2] + sF[2][3]);
+    bad = sBad[0] + sBad[1] + sBad[2] + sBad[3];
   }
-  __syncthreads();
-  const double W = 0.5 * dx * (sWd[0] + sWd[1] + sWd[2] + sWd[3]);
-  const int bad = (int)(sWi[0] + sWi[1] + sWi[2] + sWi[3]);
-  __syncthreads();
 
   // 4. diagnostics and step bookkeeping
   const bool pushed = (a.flags & kHavePush) != 0;
@@ -1193,29 +1263,50 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     const bool writer = blockIdx.x == 0;
     sacc_t pv[SF], dv[SF];
     {
-      const sacc_t *gP = reinterpret_cast<const sacc_t *>(a.sf_P) + kc.mesh_off;
-      const sacc_t *gD = reinterpret_cast<const sacc_t *>(a.sf_D) + kc.mesh_off;
+      // the copies summed in copy order, as the solve launch sums them
       const int per = (kc.nc + kSolveThreads - 1) / kSolveThreads;
       const int j0 = tid * per;
 #pragma unroll
       for (int k = 0; k < SF; ++k) {
         pv[k] = (sacc_t)0;
         dv[k] = (sacc_t)0;
-        const int j = j0 + k;
-        if (k < per && j < kc.nc) {
-          pv[k] = gP[j];
-          dv[k] = gD[j];
+      }
+      // the loads are unconditional (a thread past the mesh reads cell 0 and
+      // adds zero), all copies' in flight together where the registers allow
+      auto take = [&](const void *base, int r, sacc_t(&acc)[SF]) {
+        const sacc_t *g = reinterpret_cast<const sacc_t *>(base) + kc.mesh_off + r * a.rep_stride;
+#pragma unroll
+        for (int k = 0; k < SF; ++k) {
+          const int j = j0 + k;
+          const bool own = k < per && j < kc.nc;
+          const sacc_t v = g[own ? j : 0];
+          acc[k] += own ? v : (sacc_t)0;
         }
+      };
+      if constexpr (SF * kSingleRep <= 16) {
+#pragma unroll
+        for (int r = 0; r < kSingleRep; ++r) {
+          take(a.sf_P, r, pv);
+          take(a.sf_D, r, dv);
+        }
+      } else {
+#pragma unroll 1
+        for (int r = 0; r < kSingleRep; ++r) take(a.sf_P, r, pv);
+#pragma unroll 1
+        for (int r = 0; r < kSingleRep; ++r) take(a.sf_D, r, dv);
       }
     }
     {
+      // this workgroup's slice of every copy
       const int z0 = (int)((int64_t)kc.nc * blockIdx.x / gridDim.x);
       const int z1 = (int)((int64_t)kc.nc * (blockIdx.x + 1) / gridDim.x);
-      acc_t *zP = reinterpret_cast<acc_t *>(a.sf_zP) + kc.mesh_off;
-      acc_t *zD = reinterpret_cast<acc_t *>(a.sf_zD) + kc.mesh_off;
-      for (int i = z0 + tid; i < z1; i += blockDim.x) {
-        zP[i] = (acc_t)0;
-        zD[i] = (acc_t)0;
+      for (int r = 0; r < kSingleRep; ++r) {
+        acc_t *zP = reinterpret_cast<acc_t *>(a.sf_zP) + kc.mesh_off + r * a.rep_stride;
+        acc_t *zD = reinterpret_cast<acc_t *>(a.sf_zD) + kc.mesh_off + r * a.rep_stride;
+        for (int i = z0 + tid; i < z1; i += blockDim.x) {
+          zP[i] = (acc_t)0;
+          zD[i] = (acc_t)0;
+        }
       }
     }
     double ke = 0.0, mom = 0.0, ms = 0.0;
@@ -1593,8 +1684,9 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
       if constexpr (kDep) a.partials[it].maxseg = x;
     }
     if constexpr (kDep) {
-      acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + I.mesh_off;
-      acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + I.mesh_off;
+      const int64_t roff = I.mesh_off + (int64_t)(it % a.rep) * a.rep_stride;
+      acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + roff;
+      acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + roff;
       for (int i = tid; i < g.nc; i += blockDim.x) {
         const acc_t p = sP[i];
         const acc_t d = sD[i];
@@ -1607,7 +1699,7 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           else atomicAdd(gD + i, d);
         }
         if constexpr (kLin) {
-          acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + I.mesh_off;
+          acc_t *gR = reinterpret_cast<acc_t *>(a.meshR) + roff;
           const acc_t r = sR[i];
           if (r != (acc_t)0) {
             if constexpr (PREC == kFP64) unsafeAtomicAdd(gR + i, r);
@@ -1899,8 +1991,9 @@ k_deposit_faces(TracerArgs a) {
       for (int w = 0; w < nwaves; ++w) x = nan_max(x, reinterpret_cast<const double *>(qBase + w * kDepQueue)[0]);
       a.partials[it].maxseg = x;
     }
-    acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + I.mesh_off;
-    acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + I.mesh_off;
+    const int64_t roff = I.mesh_off + (int64_t)(it % a.rep) * a.rep_stride;
+    acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + roff;
+    acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + roff;
     for (int i = tid; i < g.nc; i += blockDim.x) {
       const acc_t p = sP[i];
       const acc_t d = sD[i];
@@ -1920,7 +2013,7 @@ k_deposit_faces(TracerArgs a) {
 // CELLS: cells per thread the solve is unrolled for (at least the pool's
 // largest mesh over kSolveThreads; the unused ones add exact zeros, so every
 // instance gives the same bits).
-template <int PREC, int CELLS>
+template <int PREC, int CELLS, int REP>
 __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
   __shared__ double sWd[4];
@@ -1936,7 +2029,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   acc_t *gP = reinterpret_cast<acc_t *>(a.meshP) + kc.mesh_off;
   acc_t *gD = reinterpret_cast<acc_t *>(a.meshD) + kc.mesh_off;
   acc_t pv[CELLS], dv[CELLS];
-  solve_take<PREC, CELLS>(kc, gP, gD, pv, dv);  // in flight with the partial loads below
+  solve_take<PREC, CELLS, REP>(kc, gP, gD, a.rep_stride, pv, dv);  // in flight with the partial loads below
 
   // 1. work-item partials, in item order: each thread sums items tid,
   // tid + 256, ... (loads issued four at a time), then the wavefront and
@@ -1974,7 +2067,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(SolveArgs a) {
   mom = sMom[0] + sMom[1] + sMom[2] + sMom[3];
   ms = nan_max(nan_max(sMs[0], sMs[1]), nan_max(sMs[2], sMs[3]));
   acc_t *gRamp = (a.order == 1 && a.meshR) ? reinterpret_cast<acc_t *>(a.meshR) + kc.mesh_off : nullptr;
-  solve_slot<PREC, CELLS>(a, slot, kc, Ip->step, Ip->flags, pv, dv, gRamp, ke, mom, ms,
+  solve_slot<PREC, CELLS, REP>(a, slot, kc, Ip->step, Ip->flags, pv, dv, gRamp, ke, mom, ms,
                           (double *)nullptr, true);
 }
 
@@ -2155,7 +2248,7 @@ __global__ void __launch_bounds__(NT) k_resident(TracerArgs a, SolveArgs sa, int
     // memory too after the last step)
     using sacc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
     sacc_t pv[CELLS], dv[CELLS];
-    solve_take<PREC, CELLS>(kc, sP, sD, pv, dv);
+    solve_take<PREC, CELLS, 1>(kc, sP, sD, 0, pv, dv);
     flags = solve_slot<PREC, CELLS>(sa, slot, kc, step_now, flags, pv, dv, (acc_t *)nullptr, ke, mom, ms, sE,
                                     step == n_steps - 1);
     step_now += 1;
@@ -2542,17 +2635,20 @@ __global__ void __launch_bounds__(256) k_refine_layout(RefinePlanArgs a) {
 
 template <int PREC>
 __global__ void __launch_bounds__(256) k_zero_mesh(void *meshP, void *meshD, void *meshR, const InstDesc *inst,
-                                                   const int32_t *slot_list) {
+                                                   const int32_t *slot_list, int rep, int64_t rep_stride) {
   using acc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
   const int slot = slot_list ? slot_list[blockIdx.x] : (int)blockIdx.x;
   const InstDesc &I = inst[slot];
-  acc_t *P = reinterpret_cast<acc_t *>(meshP) + I.mesh_off;
-  acc_t *D = reinterpret_cast<acc_t *>(meshD) + I.mesh_off;
-  acc_t *R = meshR ? reinterpret_cast<acc_t *>(meshR) + I.mesh_off : nullptr;
-  for (int j = threadIdx.x; j < I.n_cells; j += blockDim.x) {
-    P[j] = (acc_t)0;
-    D[j] = (acc_t)0;
-    if (R) R[j] = (acc_t)0;
+  for (int r = 0; r < rep; ++r) {
+    const int64_t off = I.mesh_off + r * rep_stride;
+    acc_t *P = reinterpret_cast<acc_t *>(meshP) + off;
+    acc_t *D = reinterpret_cast<acc_t *>(meshD) + off;
+    acc_t *R = meshR ? reinterpret_cast<acc_t *>(meshR) + off : nullptr;
+    for (int j = threadIdx.x; j < I.n_cells; j += blockDim.x) {
+      P[j] = (acc_t)0;
+      D[j] = (acc_t)0;
+      if (R) R[j] = (acc_t)0;
+    }
   }
 }
 
@@ -2711,7 +2807,8 @@ static hipError_t tracers_sf_cells(const TracerArgs &a, int grid, int block, siz
 int launch_tracers_sf(int prec, bool seg, const TracerArgs &a, int grid, int block, size_t lds, int max_cells,
                       void *stream) {
   if (grid <= 0) return 0;
-  if (max_cells < 1 || max_cells > kMaxCells || block < kSolveThreads) return (int)hipErrorInvalidValue;
+  if (max_cells < 1 || max_cells > kMaxCells || block < kSolveThreads || a.rep != kSingleRep)
+    return (int)hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)stream;
   switch (prec) {
     case kFP64:
@@ -2794,30 +2891,39 @@ int launch_resident(int prec, bool seg, const TracerArgs &a, const SolveArgs &sa
   }
 }
 
-template <int CELLS>
+template <int CELLS, int REP>
 static hipError_t solve_cells_launch(int prec, const SolveArgs &a, int n_blocks, hipStream_t st) {
   switch (prec) {
-    case kFP64: hipLaunchKernelGGL((k_solve<kFP64, CELLS>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a); break;
+    case kFP64:
+      hipLaunchKernelGGL((k_solve<kFP64, CELLS, REP>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
+      break;
     case kSplitF32:
-      hipLaunchKernelGGL((k_solve<kSplitF32, CELLS>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
+      hipLaunchKernelGGL((k_solve<kSplitF32, CELLS, REP>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
       break;
     case kSplitU32:
-      hipLaunchKernelGGL((k_solve<kSplitU32, CELLS>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
+      hipLaunchKernelGGL((k_solve<kSplitU32, CELLS, REP>), dim3(n_blocks), dim3(kSolveThreads), 0, st, a);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int REP>
+static hipError_t solve_rep_launch(int prec, const SolveArgs &a, int n_blocks, int max_cells, hipStream_t st) {
+  switch (solve_cells(max_cells)) {
+    case 1: return solve_cells_launch<1, REP>(prec, a, n_blocks, st);
+    case 4: return solve_cells_launch<4, REP>(prec, a, n_blocks, st);
+    default: return solve_cells_launch<16, REP>(prec, a, n_blocks, st);
+  }
+}
+
 int launch_solve(int prec, const SolveArgs &a, int n_blocks, int max_cells, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n_blocks <= 0) return 0;
   if (max_cells < 1 || max_cells > kMaxCells) return (int)hipErrorInvalidValue;
-  switch (solve_cells(max_cells)) {
-    case 1: return (int)solve_cells_launch<1>(prec, a, n_blocks, st);
-    case 4: return (int)solve_cells_launch<4>(prec, a, n_blocks, st);
-    default: return (int)solve_cells_launch<16>(prec, a, n_blocks, st);
-  }
+  if (a.rep == 1) return (int)solve_rep_launch<1>(prec, a, n_blocks, max_cells, st);
+  if (a.rep == kSingleRep) return (int)solve_rep_launch<kSingleRep>(prec, a, n_blocks, max_cells, st);
+  return (int)hipErrorInvalidValue;
 }
 
 int launch_ingest(int prec, const IngestArgs &a, void *stream) {
@@ -2847,14 +2953,16 @@ int launch_extract(int prec, const ExtractArgs &a, void *stream) {
 }
 
 int launch_zero_mesh(int prec, void *meshP, void *meshD, void *meshR, const InstDesc *inst,
-                     const int32_t *slot_list, int n_blocks, void *stream) {
+                     const int32_t *slot_list, int n_blocks, int rep, int64_t rep_stride, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n_blocks <= 0) return 0;
+  if (rep < 1) return (int)hipErrorInvalidValue;
   if (prec == kFP64)
-    hipLaunchKernelGGL(k_zero_mesh<kFP64>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, meshR, inst, slot_list);
+    hipLaunchKernelGGL(k_zero_mesh<kFP64>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, meshR, inst, slot_list,
+                       rep, rep_stride);
   else
     hipLaunchKernelGGL(k_zero_mesh<kSplitF32>, dim3(n_blocks), dim3(256), 0, st, meshP, meshD, meshR, inst,
-                       slot_list);
+                       slot_list, rep, rep_stride);
   return (int)hipGetLastError();
 }
 
