@@ -414,14 +414,15 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
 // spend less on zeroing and merging the item's LDS mesh).  An item clears
 // and scans its whole LDS mesh, and once a sheet has folded over the box it
 // merges nearly every cell into the global mesh (one atomic each), so items
-// hold at least 4 tracers per mesh cell where that still leaves 128 items.
+// hold at least 4 tracers per mesh cell where that still leaves one item per
+// compute unit.
 int slot_tile(const Pool *p, int64_t n_chunks) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
   const int wave_min = p->block / kChunk;
   if (p->batch) return std::max(p->order == 1 ? kLinearBatchTile : kDefaultBatchTile, wave_min);
   const int64_t per = (n_chunks + 2047) / 2048;
   const int64_t mesh_min = (4 * (int64_t)p->max_cells + kChunk - 1) / kChunk;
-  const int64_t want = std::max(per, std::min(mesh_min, n_chunks / 128));
+  const int64_t want = std::max(per, std::min(mesh_min, n_chunks / 256));
   int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(kMaxTile, want));
   t = (t + 3) / 4 * 4;
   return std::max(t, wave_min);
@@ -437,8 +438,8 @@ void apply_launch_shape(Pool *p) {
     // those workgroups more waves so the CU still has enough loads in flight.
     const size_t lds = tracer_lds_size(p->prec, p->order, p->seg, p->max_cells, p->tile);
     const size_t per_cu = lds > 0 ? kLdsPerCU / lds : 8;
-    // items of 16 chunks or more have work for 8 wavefronts each
-    p->block = (p->batch || p->tile >= 16) ? kDefaultBatchBlock : kDefaultBlock;
+    // items of 8 chunks or more have work for 8 wavefronts each
+    p->block = (p->batch || p->tile >= 8) ? kDefaultBatchBlock : kDefaultBlock;
     if (per_cu <= 1) p->block = 1024;
     else if (per_cu == 2) p->block = std::max(p->block, 512);
   }

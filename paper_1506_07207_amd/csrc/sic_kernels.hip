@@ -173,31 +173,34 @@ __device__ __forceinline__ uint64_t advance_split(uint64_t w, double du, int nc)
   if (!(t - t == 0.0)) return w;
   const double k = floor(t);
   const double r = t - k;
-  long long step = (long long)k;
+  // a step of under 2^31 units converts through a 32-bit integer; longer
+  // ones (and their 64-bit conversion) take the rare branch below
+  const bool near = fabs(k) < 0x1p31;
+  long long carry = 0;
   uint32_t bits;
   if constexpr (PREC == kSplitF32) {
     float o = (float)r;
     if (o >= 1.0f) {
       o = 0.0f;
-      step += 1;
+      carry = 1;
     }
     bits = __float_as_uint(o);
   } else {
     double sc = rint(r * 4294967296.0);
     if (sc >= 4294967296.0) {
       sc = 0.0;
-      step += 1;
+      carry = 1;
     }
     bits = (uint32_t)sc;
   }
   const long long period = (long long)nc << (PREC == kSplitF32 ? kSubBits : 0);
-  long long idx = (long long)(uint32_t)w + step;
+  long long idx = (long long)(uint32_t)w + (long long)(int)(near ? k : 0.0) + carry;
   // a move of less than a period needs one conditional wrap; the (slow,
   // 64-bit) remainder only for longer ones
   if (idx >= period) idx -= period;
   else if (idx < 0) idx += period;
-  if ((unsigned long long)idx >= (unsigned long long)period) {
-    idx %= period;
+  if (!near || (unsigned long long)idx >= (unsigned long long)period) {
+    idx = ((long long)(uint32_t)w + (long long)k + carry) % period;
     if (idx < 0) idx += period;
   }
   return (uint64_t)(uint32_t)idx | ((uint64_t)bits << 32);
@@ -313,7 +316,12 @@ __device__ __forceinline__ double deposit_split(uint64_t wa, uint64_t wb, long l
     lds_add(sP + wrap_cell(c0, g.nc), (unsigned long long)qf);
     return ad;
   }
-  const double inv = 1.0 / len;
+  // 1 / len by the hardware reciprocal and two Newton steps (a correctly
+  // rounded quotient is not needed: the shares are rounded to fixed point
+  // and the last takes the rest, so the charge is conserved exactly)
+  double inv = __builtin_amdgcn_rcp(len);
+  inv = fma(inv, fma(-len, inv, 1.0), inv);
+  inv = fma(inv, fma(-len, inv, 1.0), inv);
   const double qd = (double)qf;
   const long long p0 = llrint(qd * (((f0 + 1.0) - u0) * inv));
   long long p1 = qf - p0;
