@@ -241,6 +241,15 @@ __device__ __forceinline__ void add_run(T *sD, int lo, int hi, T w, int nc) {
   }
 }
 
+// 1 / x (x finite, non-zero, normal) by the hardware reciprocal and two
+// Newton steps: within an ulp or so of the correctly rounded quotient, at
+// about half the instructions of a division.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 struct Geo {
   double L, half_L, dx, inv_dx, dt;
   int nc;
@@ -316,12 +325,10 @@ __device__ __forceinline__ double deposit_split(uint64_t wa, uint64_t wb, long l
     lds_add(sP + wrap_cell(c0, g.nc), (unsigned long long)qf);
     return ad;
   }
-  // 1 / len by the hardware reciprocal and two Newton steps (a correctly
-  // rounded quotient is not needed: the shares are rounded to fixed point
-  // and the last takes the rest, so the charge is conserved exactly)
-  double inv = __builtin_amdgcn_rcp(len);
-  inv = fma(inv, fma(-len, inv, 1.0), inv);
-  inv = fma(inv, fma(-len, inv, 1.0), inv);
+  // a correctly rounded quotient is not needed: the shares are rounded to
+  // fixed point and the last takes the rest, so the charge is conserved
+  // exactly
+  const double inv = recip(len);
   const double qd = (double)qf;
   const long long p0 = llrint(qd * (((f0 + 1.0) - u0) * inv));
   long long p1 = qf - p0;
@@ -520,34 +527,42 @@ __device__ __forceinline__ SegGeo lin_geo(uint64_t wa, uint64_t wb, const Geo &g
 
 // Mean density q / length of a segment (q in the accumulator's units), the
 // length taken over the extent the deposit integrates so that its pieces add
-// up to q; 0 for a zero-length segment.
+// up to q; 0 for a zero-length segment.  The quotient by the reciprocal
+// (recip): every density, a lane's own and the staged neighbours', comes
+// from this one function, so neighbours see the same bits.
 __device__ __forceinline__ double lin_density(const SegGeo &s, double q) {
   const double u0 = s.d > 0.0 ? s.u : s.u + s.d;
   const double u1 = s.d > 0.0 ? s.u + s.d : s.u;
   const double len = u1 - u0;
-  return len > 0.0 ? q / len : 0.0;
+  return len > 0.0 ? q * recip(len) : 0.0;
 }
 
-// Gradient of a segment with centroid c from its neighbours' centroids, signed
-// lengths and densities (m: the segment before, p: the one after): the
+// The density a neighbour's gradient takes from a segment: NaN marks a
+// missing segment or one of zero signed length, which drop the gradient.
+__device__ __forceinline__ double lin_nb_density(double d, double r) {
+  return d != 0.0 ? r : __longlong_as_double(0x7ff8000000000000ll);
+}
+
+// Gradient of a segment with centroid c from its neighbours' centroids and
+// densities (m: the segment before, p: the one after; lin_nb_density): the
 // central difference of the densities over the centroid separation, 0 at a
 // fold corner (centroids not monotone) or when a neighbour is missing or has
-// zero length (both passed as length 0).
-__device__ __forceinline__ double lin_gradient(double c, double cm, double dm_len, double rm, double cp,
-                                               double dp_len, double rp, double half_nc, double nc) {
+// zero length (density NaN).
+__device__ __forceinline__ double lin_gradient(double c, double cm, double rm, double cp, double rp, double half_nc,
+                                               double nc) {
   // without branches: a wavefront's lanes mostly take the quotient, and the
   // others select 0 (their divisor replaced by 1)
   const double dm = min_image_cells(cm - c, half_nc, nc);
   const double dp = min_image_cells(cp - c, half_nc, nc);
-  const bool ok = dm_len != 0.0 && dp_len != 0.0 && ((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0));
-  const double q = (rp - rm) / (ok ? dp - dm : 1.0);
+  const bool ok = rm == rm && rp == rp && ((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0));
+  const double q = (rp - rm) * recip(ok ? dp - dm : 1.0);
   return ok ? q : 0.0;
 }
 
-// A neighbouring segment as the gradient needs it: centroid, signed length
-// and density.
+// A neighbouring segment as the gradient needs it: centroid and density
+// (lin_nb_density).
 struct LinNb {
-  double c, d, r;
+  double c, r;
 };
 
 // FP64: deposit segment i given its geometry, gradient and density
@@ -1464,13 +1479,13 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
             else q = PREC == kFP64 ? sDesc[i].q : (double)sDesc[i].q_fix;
             LinNb nb;
             nb.c = sgn.c;
-            nb.d = sgn.d;
-            nb.r = lin_density(sgn, q);
+            nb.r = lin_nb_density(sgn.d, lin_density(sgn, q));
             return nb;
           };
           const int2 lk = a.links[cb + i];
           LinNb none;
-          none.c = none.d = none.r = 0.0;
+          none.c = 0.0;
+          none.r = lin_nb_density(0.0, 0.0);
           LinNb prev = none, next = none;
           uint64_t wn1 = 0;
           if (pc >= 0) wn1 = moved(a.halo3_in[3 * pc + kHaloFirst]);
@@ -1578,22 +1593,21 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           else q0_fix = (long long)cw;
         }
         const double r0 = lin_density(sg, PREC == kFP64 ? q0 : (double)q0_fix);
-        double cm = lane_up1(sg.c), dm = lane_up1(sg.d), rm = lane_up1(r0);
-        double cp = lane_down1(sg.c), dp = lane_down1(sg.d), rp = lane_down1(r0);
+        const double rv = lin_nb_density(sg.d, r0);
+        double cm = lane_up1(sg.c), rm = lane_up1(rv);
+        double cp = lane_down1(sg.c), rp = lane_down1(rv);
         if (lane == 0) {
           const LinNb nb = sPrevNb[kk];
           cm = nb.c;
-          dm = nb.d;
           rm = nb.r;
         }
         if (last) {
           const LinNb nb = sNextNb[kk];
           cp = nb.c;
-          dp = nb.d;
           rp = nb.r;
         }
         if (has_seg) {
-          const double grad = lin_gradient(sg.c, cm, dm, rm, cp, dp, rp, 0.5 * (double)g.nc, (double)g.nc);
+          const double grad = lin_gradient(sg.c, cm, rm, cp, rp, 0.5 * (double)g.nc, (double)g.nc);
           const double len = fabs(sg.d) * g.dx;
           if (len <= g.half_L) {
             if constexpr (PREC == kFP64) {
