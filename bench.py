@@ -175,10 +175,12 @@ def time_single_configs(B, I, torch):
     graphs of up to 32 steps), then the initial state is loaded again and
     the same run is timed (events on the launch stream; the cost of a step
     grows as the sheets stretch, so the timed run covers the set-up's own
-    steps).  Reports the time per step, the resulting tracer-updates/s, and
-    the kernel launches per step (2, the fused tracer kernel and the solve,
-    for graph-replayed steps; 1 / steps for a small simulation, whose steps
-    run in one resident launch)."""
+    steps).  Reports the time per step, the resulting tracer-updates/s, the
+    launch path of the steps and the kernel launches per step: one tracer
+    launch per step plus a solve and a clearing launch per graph of up to 32
+    steps on the solve-first path, 2 (tracer kernel and solve) on the fused
+    launch pairs, 1 / steps for a small simulation, whose steps run in one
+    resident launch."""
     cases = [
         ("cold oscillation, FP64 (1 x 1024 tracers, 128 cells)", I.cold_oscillation(), B.SIC_FP64),
         ("Landau damping, FP64 (256 x 512 tracers, 256 cells)", I.landau(), B.SIC_FP64),
@@ -220,15 +222,23 @@ def time_single_configs(B, I, torch):
                 over = np.nonzero(e > 1e-6)[0]
                 err = {"max_envelope_rel": float(e.max()), "first_step_over_1e-6": int(over[0]) if len(over) else None,
                        "against": "stored oracle history (tests/golden/two_stream_full_ensemble.txt)"}
+            path = B.sic_last_step_path(sim.h)
         finally:
             sim.close()
         n = p.total_tracers
-        chunks = int(np.sum((np.asarray(p.n_tracers, dtype=np.int64) + 63) // 64))
-        resident = chunks <= 32  # constant segments: the resident single-workgroup path
-        launches = math.ceil(p.n_steps / 8192) / p.n_steps if resident else 2
+        graphs = math.ceil(p.n_steps / 32)
+        if path == B.SIC_PATH_RESIDENT:
+            launches = math.ceil(p.n_steps / 8192) / p.n_steps
+        elif path == B.SIC_PATH_SOLVE_FIRST:
+            launches = (p.n_steps + 2 * graphs) / p.n_steps
+        else:
+            launches = 2
+        names = {B.SIC_PATH_FUSED: "fused launch pairs", B.SIC_PATH_RESIDENT: "resident",
+                 B.SIC_PATH_REFINING: "refining", B.SIC_PATH_SOLVE_FIRST: "solve-first"}
         out.append({"workload": name, "tracers": n, "cells": p.n_cells, "steps": p.n_steps, "ms": ms,
                     "us_per_step": 1e3 * ms / p.n_steps, "tracer_updates_per_s": n * p.n_steps / (ms * 1e-3),
-                    "kernel_launches_per_step": launches, "field_energy_error": err})
+                    "path": names.get(path, str(path)), "kernel_launches_per_step": launches,
+                    "field_energy_error": err})
         log(f"single: {name}: {1e3 * ms / p.n_steps:.1f} us/step, {n * p.n_steps / (ms * 1e-3):.3e} tracer-updates/s")
     torch.cuda.empty_cache()
     return out

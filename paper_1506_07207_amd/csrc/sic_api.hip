@@ -359,7 +359,7 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
     double *sp = nullptr;
     (void)scratch_address(p->device, &sp);
   }
-  p->rep = batch ? 1 : kSingleRep;
+  p->rep = batch ? 1 : single_rep(max_cells);
   {
     const size_t mc = (size_t)slot_cap * max_cells;
     long long *mp = nullptr, *md = nullptr;
@@ -838,7 +838,7 @@ sic_status get_graph(Pool *p, int64_t k, hipGraphExec_t *out) {
 // order.
 bool sf_ready(Pool *p) {
   if (p->batch || p->order != 0 || p->timing || p->dev_refine || p->tune.fused_only || p->block < kSolveThreads ||
-      p->rep != kSingleRep)
+      p->rep != single_rep(p->max_cells))
     return false;
   if (!p->sf_mesh) {
     const size_t bytes = sizeof(double) * 4 * (size_t)p->rep * mesh_words(p);

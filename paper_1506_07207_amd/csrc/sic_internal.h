@@ -34,10 +34,13 @@ namespace sic {
 constexpr int kChunk = 64;          // tracer slots per chunk = wavefront width
 constexpr int kMaxCells = 4096;     // mirrors SIC_MAX_CELLS
 // Copies of a single simulation's charge accumulators (P, D, R): its work
-// items merge into copy (item mod kSingleRep), so each address takes a
-// quarter of the atomics, and the solve sums the copies in order.  Batches,
-// with few items per simulation, keep one copy.
-constexpr int kSingleRep = 4;
+// items merge into copy (item mod copies), so each address takes that
+// fraction of the atomics, and the solve sums the copies in order.  Four for
+// meshes of up to kSolveThreads cells; two for larger ones, whose every
+// solve-first workgroup reads all copies of the whole mesh (the reads then
+// cost more than the contention saves).  Batches, with few items per
+// simulation, keep one copy.
+constexpr int single_rep(int max_cells) { return max_cells <= 256 ? 4 : 2; }
 constexpr int kSolveThreads = 256;  // field-solve workgroup
 
 enum Prec : int { kFP64 = 0, kSplitF32 = 1, kSplitU32 = 2 };

@@ -194,12 +194,24 @@ __device__ __forceinline__ uint64_t advance_split(uint64_t w, double du, int nc)
     bits = (uint32_t)sc;
   }
   const long long period = (long long)nc << (PREC == kSplitF32 ? kSubBits : 0);
-  long long idx = (long long)(uint32_t)w + (long long)(int)(near ? k : 0.0) + carry;
   // a move of less than a period needs one conditional wrap; the (slow,
   // 64-bit) remainder only for longer ones
-  if (idx >= period) idx -= period;
-  else if (idx < 0) idx += period;
-  if (!near || (unsigned long long)idx >= (unsigned long long)period) {
+  bool far = !near;
+  long long idx = 0;
+  if constexpr (PREC == kSplitU32) {
+    // the cell index is below 4096: a near move stays in 32-bit integers
+    int c = (int)(uint32_t)w + (int)(near ? k : 0.0) + (int)carry;
+    if (c >= nc) c -= nc;
+    else if (c < 0) c += nc;
+    far = far || (unsigned)c >= (unsigned)nc;
+    idx = c;
+  } else {
+    idx = (long long)(uint32_t)w + (long long)(int)(near ? k : 0.0) + carry;
+    if (idx >= period) idx -= period;
+    else if (idx < 0) idx += period;
+    far = far || (unsigned long long)idx >= (unsigned long long)period;
+  }
+  if (far) {
     idx = ((long long)(uint32_t)w + (long long)k + carry) % period;
     if (idx < 0) idx += period;
   }
@@ -1280,6 +1292,8 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     // cleared here, a slice per workgroup (no launch merges into them
     // before the next one).
     using sacc_t = typename std::conditional<PREC == kFP64, double, long long>::type;
+    // the accumulator copies of a mesh of up to SF * kSolveThreads cells
+    constexpr int kRep = single_rep(SF * kSolveThreads);
     const int slot = a.items[0].inst;
     const InstDesc &I0 = a.inst[slot];
     const SlotConst kc = slot_const(I0);
@@ -1306,24 +1320,24 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
           acc[k] += own ? v : (sacc_t)0;
         }
       };
-      if constexpr (SF * kSingleRep <= 16) {
+      if constexpr (SF * kRep <= 16) {
 #pragma unroll
-        for (int r = 0; r < kSingleRep; ++r) {
+        for (int r = 0; r < kRep; ++r) {
           take(a.sf_P, r, pv);
           take(a.sf_D, r, dv);
         }
       } else {
 #pragma unroll 1
-        for (int r = 0; r < kSingleRep; ++r) take(a.sf_P, r, pv);
+        for (int r = 0; r < kRep; ++r) take(a.sf_P, r, pv);
 #pragma unroll 1
-        for (int r = 0; r < kSingleRep; ++r) take(a.sf_D, r, dv);
+        for (int r = 0; r < kRep; ++r) take(a.sf_D, r, dv);
       }
     }
     {
       // this workgroup's slice of every copy
       const int z0 = (int)((int64_t)kc.nc * blockIdx.x / gridDim.x);
       const int z1 = (int)((int64_t)kc.nc * (blockIdx.x + 1) / gridDim.x);
-      for (int r = 0; r < kSingleRep; ++r) {
+      for (int r = 0; r < kRep; ++r) {
         acc_t *zP = reinterpret_cast<acc_t *>(a.sf_zP) + kc.mesh_off + r * a.rep_stride;
         acc_t *zD = reinterpret_cast<acc_t *>(a.sf_zD) + kc.mesh_off + r * a.rep_stride;
         for (int i = z0 + tid; i < z1; i += blockDim.x) {
@@ -2829,7 +2843,7 @@ static hipError_t tracers_sf_cells(const TracerArgs &a, int grid, int block, siz
 int launch_tracers_sf(int prec, bool seg, const TracerArgs &a, int grid, int block, size_t lds, int max_cells,
                       void *stream) {
   if (grid <= 0) return 0;
-  if (max_cells < 1 || max_cells > kMaxCells || block < kSolveThreads || a.rep != kSingleRep)
+  if (max_cells < 1 || max_cells > kMaxCells || block < kSolveThreads || a.rep != single_rep(max_cells))
     return (int)hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)stream;
   switch (prec) {
@@ -2944,7 +2958,8 @@ int launch_solve(int prec, const SolveArgs &a, int n_blocks, int max_cells, void
   if (n_blocks <= 0) return 0;
   if (max_cells < 1 || max_cells > kMaxCells) return (int)hipErrorInvalidValue;
   if (a.rep == 1) return (int)solve_rep_launch<1>(prec, a, n_blocks, max_cells, st);
-  if (a.rep == kSingleRep) return (int)solve_rep_launch<kSingleRep>(prec, a, n_blocks, max_cells, st);
+  if (a.rep == 2) return (int)solve_rep_launch<2>(prec, a, n_blocks, max_cells, st);
+  if (a.rep == 4) return (int)solve_rep_launch<4>(prec, a, n_blocks, max_cells, st);
   return (int)hipErrorInvalidValue;
 }
 
