@@ -2820,12 +2820,17 @@ int set_tracer_lds_limit(int prec, int order, bool seg, size_t lds) {
 // Solve-first launches (single simulations, constant segments).
 template <int PREC, bool SEG, int SF>
 static hipError_t tracers_sf_launch(const TracerArgs &a, int grid, int block, size_t lds, hipStream_t st) {
-  static bool limit_set = false;
-  if (!limit_set && lds > 65536) {
+  // the dynamic LDS limit is raised to what a launch asks for, not to the
+  // whole 160 KB: the solve's static LDS takes part of it
+  static size_t granted = 65536;
+  if (lds > granted) {
     const hipError_t e = hipFuncSetAttribute((const void *)k_tracers<PREC, kPush | kDeposit, 0, SEG, SF>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-    if (e != hipSuccess) return e;
-    limit_set = true;
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // not left for the next launch to report
+      return e;
+    }
+    granted = lds;
   }
   hipLaunchKernelGGL((k_tracers<PREC, kPush | kDeposit, 0, SEG, SF>), dim3(grid), dim3(block), lds, st, a);
   return hipGetLastError();

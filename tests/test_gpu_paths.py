@@ -67,6 +67,8 @@ SF_CASES = {
     "ragged_37x300": lambda: I.landau(n_sheets=37, n_tracers=300, n_cells=100, alpha=0.05),
     # 1024 cells (four cells per solve thread), two-stream
     "two_stream_64x1024": lambda: I.two_stream(n_sheets=64, n_tracers=1024, n_cells=1024, n_steps=100),
+    # 4096 cells (16 cells per solve thread; a work item's LDS above 64 KB)
+    "landau_32x1024_4096cells": lambda: I.landau(n_sheets=32, n_tracers=1024, n_cells=4096, n_steps=60),
 }
 
 
