@@ -172,9 +172,10 @@ sic_status sic_push(sic_sim *sim);
  * deposits the new positions and solves the new field, so on return the field
  * is current for the new step.  If the field is stale it is brought up to date
  * first.  Steps run as captured HIP graphs of a tracer launch and a solve
- * launch each (SIC_PATH_FUSED).  With constant segments a simulation's
- * tracer launches solve the previous step's charge themselves, in every
- * workgroup, and one solve launch closes each graph of up to 32 steps
+ * launch each (SIC_PATH_FUSED).  With constant segments and at most 512
+ * workgroups per launch (two per compute unit) a simulation's tracer
+ * launches solve the previous step's charge themselves, in every workgroup,
+ * and one solve launch closes each graph of up to 32 steps
  * (SIC_PATH_SOLVE_FIRST); a small simulation (at most 32 chunks of 64 tracer
  * slots) runs its steps in one launch of a single workgroup
  * (SIC_PATH_RESIDENT).  All give the bits of the fused path in the split

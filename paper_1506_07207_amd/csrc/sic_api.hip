@@ -33,6 +33,7 @@ using namespace sic;
 namespace {
 
 constexpr int kGraphSteps = 32;         // steps per captured graph
+constexpr int kSfMaxGrid = 512;         // solve-first steps up to this many workgroups (two per CU)
 constexpr int kDefaultGrid = 2048;       // grid of a pool before its first items are placed
 constexpr int kMinBatchGrid = 4096;      // smallest default batch grid (16 workgroups per CU)
 constexpr int kMaxGrid = 1 << 20;        // largest default grid (the kernels loop over any excess items)
@@ -840,6 +841,10 @@ bool sf_ready(Pool *p) {
   if (p->batch || p->order != 0 || p->timing || p->dev_refine || p->tune.fused_only || p->block < kSolveThreads ||
       p->rep != single_rep(p->max_cells))
     return false;
+  // every workgroup solves first: worth it while the workgroups run in one
+  // round on the machine, not when each CU works through several in turn
+  // (a 33.5M-tracer job's 2048 workgroups: 400 against 290 us per step)
+  if (grid_for(p, -1) > kSfMaxGrid) return false;
   if (!p->sf_mesh) {
     const size_t bytes = sizeof(double) * 4 * (size_t)p->rep * mesh_words(p);
     if (hipMalloc(&p->sf_mesh, bytes) != hipSuccess) {
