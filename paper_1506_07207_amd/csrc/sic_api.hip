@@ -416,14 +416,21 @@ sic_status pool_create(int prec, int order, bool seg, bool batch, int32_t slot_c
 // and scans its whole LDS mesh, and once a sheet has folded over the box it
 // merges nearly every cell into the global mesh (one atomic each), so items
 // hold at least 4 tracers per mesh cell where that still leaves one item per
-// compute unit.
-int slot_tile(const Pool *p, int64_t n_chunks) {
+// compute unit.  Atomics on one address serialise (about 22 ns each), so a
+// small mesh also caps the items that merge into one accumulator copy: at
+// most max(256, cells x copies / 2) items (a million tracers on 100 cells:
+// 256 items of 64 chunks, not 2048 of 8); not for the layout of a refining
+// simulation's whole reservation (cap_items false), whose items are mostly
+// empty while it grows.
+int slot_tile(const Pool *p, int64_t n_chunks, bool cap_items = true) {
   if (p->tune.tile_chunks > 0) return std::max(kMinTile, std::min(kMaxTile, (int)p->tune.tile_chunks));
   const int wave_min = p->block / kChunk;
   if (p->batch) return std::max(p->order == 1 ? kLinearBatchTile : kDefaultBatchTile, wave_min);
   const int64_t per = (n_chunks + 2047) / 2048;
   const int64_t mesh_min = (4 * (int64_t)p->max_cells + kChunk - 1) / kChunk;
-  const int64_t want = std::max(per, std::min(mesh_min, n_chunks / 256));
+  const int64_t max_items = std::max<int64_t>(256, (int64_t)p->max_cells * p->rep / 2);
+  const int64_t contention = cap_items ? (n_chunks + max_items - 1) / max_items : 1;
+  const int64_t want = std::max(std::max(per, contention), std::min(mesh_min, n_chunks / 256));
   int t = (int)std::max<int64_t>(kMinTile, std::min<int64_t>(kMaxTile, want));
   t = (t + 3) / 4 * 4;
   return std::max(t, wave_min);
@@ -1755,7 +1762,7 @@ sic_status place_slot_items_reserved(Pool *p, int32_t slot) {
   SlotHost &s = p->slots[slot];
   sic_status st = clear_slot_items(p, slot);
   if (st != SIC_OK) return st;
-  const int tile = slot_tile(p, s.n_chunks_res);
+  const int tile = slot_tile(p, s.n_chunks_res, false);
   p->tile = tile;
   const int32_t cap = (s.n_chunks_res + tile - 1) / tile;
   const int32_t now = (s.n_chunks + tile - 1) / tile;

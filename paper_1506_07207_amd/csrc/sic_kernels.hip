@@ -991,7 +991,9 @@ __device__ __forceinline__ void solve_take(const SlotConst &kc, Acc *gP, Acc *gD
 // density are left in sE only (the resident kernel writes them to global
 // memory on its last step); with writer false nothing at all is written to
 // global memory (the workgroups of a launch that each solve the same charge
-// for their own use, all but one).
+// for their own use, all but one).  The field in sE is complete only after a
+// barrier following the return (without writer the solve passes none after
+// its field loop).
 template <int PREC, int CELLS, int REP = 1, class Acc, class T>
 __device__ __forceinline__ int solve_slot(const SolveArgs &a, int slot, const SlotConst &kc, int64_t step0,
                                           int flags0, const T (&pv)[CELLS], const T (&dv)[CELLS], Acc *gRamp,
@@ -1388,6 +1390,10 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
     }
     solve_slot<PREC, SF>(a.sf, slot, kc, writer ? I0.step : 0, writer ? I0.flags : 0, pv, dv, (acc_t *)nullptr, ke,
                          mom, ms, sE, writer, writer);
+    // the ghost cells copy cells other threads wrote: a barrier first (a
+    // workgroup that writes nothing passes none in the solve after its field
+    // loop)
+    __syncthreads();
     if (tid == 0) {
       sE[-1] = sE[kc.nc - 1];
       sE[kc.nc] = sE[0];
@@ -2523,23 +2529,47 @@ __global__ void __launch_bounds__(1024) k_refine_plan(RefinePlanArgs a) {
   if (tid == 0) sOver = 0;
   const int n = st[kRefChunks];
   // each thread sums a contiguous run of chunks, one block scan places the
-  // runs, then each thread writes its run's offsets
+  // runs, then each thread writes its run's offsets.  A run's counts are
+  // read kB at a time (the loads in flight together; past the run's end a
+  // thread reads its last chunk again and adds nothing).
   const int per = (n + nth - 1) / nth;
   const int c0 = min(n, tid * per), c1 = min(n, c0 + per);
+  constexpr int kB = 8;
+  auto fetch = [&](int cb, long long (&kv)[kB], long long (&nv)[kB]) {
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int c = min(cb + u, c1 - 1);
+      kv[u] = a.cnt[c];
+      nv[u] = a.chunks[a.chunk_begin + c].n_valid;
+    }
+  };
   long long sv = 0, sk = 0;
-  for (int c = c0; c < c1; ++c) {
-    const long long k = a.cnt[c];
-    sv += (long long)a.chunks[a.chunk_begin + c].n_valid + k;
-    sk += k;
+  for (int cb = c0; cb < c1; cb += kB) {
+    long long kv[kB], nv[kB];
+    fetch(cb, kv, nv);
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      if (cb + u < c1) {
+        sv += nv[u] + kv[u];
+        sk += kv[u];
+      }
+    }
   }
   const long long iv = block_incl_scan(sv, sW);
   if (tid == nth - 1) sTot[0] = iv;
   const long long ik = block_incl_scan(sk, sW);
   if (tid == nth - 1) sTot[1] = ik;
   long long run = iv - sv;
-  for (int c = c0; c < c1; ++c) {
-    a.out_off[c] = run;
-    run += (long long)a.chunks[a.chunk_begin + c].n_valid + a.cnt[c];
+  for (int cb = c0; cb < c1; cb += kB) {
+    long long kv[kB], nv[kB];
+    fetch(cb, kv, nv);
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      if (cb + u < c1) {
+        a.out_off[cb + u] = run;
+        run += nv[u] + kv[u];
+      }
+    }
   }
   __syncthreads();
   const long long carry = sTot[0], inserted = sTot[1];
