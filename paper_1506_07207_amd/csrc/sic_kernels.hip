@@ -555,26 +555,28 @@ __device__ __forceinline__ double lin_nb_density(double d, double r) {
   return d != 0.0 ? r : __longlong_as_double(0x7ff8000000000000ll);
 }
 
-// Gradient of a segment with centroid c from its neighbours' centroids and
-// densities (m: the segment before, p: the one after; lin_nb_density): the
-// central difference of the densities over the centroid separation, 0 at a
-// fold corner (centroids not monotone) or when a neighbour is missing or has
-// zero length (density NaN).
-__device__ __forceinline__ double lin_gradient(double c, double cm, double rm, double cp, double rp, double half_nc,
-                                               double nc) {
+// Gradient of a segment of signed length d from its neighbours' signed
+// lengths and densities (m: the segment before, p: the one after;
+// lin_nb_density): the central difference of the densities over the centroid
+// separation, 0 at a fold corner (centroids not monotone) or when a neighbour
+// is missing or has zero length (density NaN).  Consecutive segments share an
+// end, so the centroid before lies (dm_len + d) / 2 behind this one and the
+// one after (d + dp_len) / 2 ahead, along the shorter way round the box
+// (each length is at most half the box).
+__device__ __forceinline__ double lin_gradient(double d, double dm_len, double rm, double dp_len, double rp) {
   // without branches: a wavefront's lanes mostly take the quotient, and the
   // others select 0 (their divisor replaced by 1)
-  const double dm = min_image_cells(cm - c, half_nc, nc);
-  const double dp = min_image_cells(cp - c, half_nc, nc);
+  const double dm = -0.5 * (dm_len + d);
+  const double dp = 0.5 * (d + dp_len);
   const bool ok = rm == rm && rp == rp && ((dm < 0.0 && dp > 0.0) || (dm > 0.0 && dp < 0.0));
   const double q = (rp - rm) * recip(ok ? dp - dm : 1.0);
   return ok ? q : 0.0;
 }
 
-// A neighbouring segment as the gradient needs it: centroid and density
+// A neighbouring segment as the gradient needs it: signed length and density
 // (lin_nb_density).
 struct LinNb {
-  double c, r;
+  double d, r;
 };
 
 // FP64: deposit segment i given its geometry, gradient and density
@@ -1498,13 +1500,13 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
             if constexpr (SEG) q = PREC == kFP64 ? __longlong_as_double((long long)cword) : (double)(long long)cword;
             else q = PREC == kFP64 ? sDesc[i].q : (double)sDesc[i].q_fix;
             LinNb nb;
-            nb.c = sgn.c;
+            nb.d = sgn.d;
             nb.r = lin_nb_density(sgn.d, lin_density(sgn, q));
             return nb;
           };
           const int2 lk = a.links[cb + i];
           LinNb none;
-          none.c = 0.0;
+          none.d = 0.0;
           none.r = lin_nb_density(0.0, 0.0);
           LinNb prev = none, next = none;
           uint64_t wn1 = 0;
@@ -1614,20 +1616,20 @@ __global__ void __launch_bounds__(1024) k_tracers(TracerArgs a) {
         }
         const double r0 = lin_density(sg, PREC == kFP64 ? q0 : (double)q0_fix);
         const double rv = lin_nb_density(sg.d, r0);
-        double cm = lane_up1(sg.c), rm = lane_up1(rv);
-        double cp = lane_down1(sg.c), rp = lane_down1(rv);
+        double dm = lane_up1(sg.d), rm = lane_up1(rv);
+        double dp = lane_down1(sg.d), rp = lane_down1(rv);
         if (lane == 0) {
           const LinNb nb = sPrevNb[kk];
-          cm = nb.c;
+          dm = nb.d;
           rm = nb.r;
         }
         if (last) {
           const LinNb nb = sNextNb[kk];
-          cp = nb.c;
+          dp = nb.d;
           rp = nb.r;
         }
         if (has_seg) {
-          const double grad = lin_gradient(sg.c, cm, rm, cp, rp, 0.5 * (double)g.nc, (double)g.nc);
+          const double grad = lin_gradient(sg.d, dm, rm, dp, rp);
           const double len = fabs(sg.d) * g.dx;
           if (len <= g.half_L) {
             if constexpr (PREC == kFP64) {
