@@ -2519,6 +2519,7 @@ __global__ void __launch_bounds__(256) k_refine_scatter(RefineArgs a) {
 // and halts the simulation (inactive; the host reports it).
 __global__ void __launch_bounds__(1024) k_refine_plan(RefinePlanArgs a) {
   __shared__ long long sW[16];
+  __shared__ long long sTk[16];
   __shared__ long long sTot[2];
   __shared__ int sOver;
   const int tid = threadIdx.x;
@@ -2530,48 +2531,53 @@ __global__ void __launch_bounds__(1024) k_refine_plan(RefinePlanArgs a) {
   }
   if (tid == 0) sOver = 0;
   const int n = st[kRefChunks];
-  // each thread sums a contiguous run of chunks, one block scan places the
-  // runs, then each thread writes its run's offsets.  A run's counts are
-  // read kB at a time (the loads in flight together; past the run's end a
-  // thread reads its last chunk again and adds nothing).
-  const int per = (n + nth - 1) / nth;
-  const int c0 = min(n, tid * per), c1 = min(n, c0 + per);
-  constexpr int kB = 8;
-  auto fetch = [&](int cb, long long (&kv)[kB], long long (&nv)[kB]) {
+  // Each wavefront takes a contiguous range of chunks and walks it 64 chunks
+  // (one per lane, coalesced) at a time, kB groups of loads in flight
+  // together: a wavefront scan gives each chunk its offset within the range
+  // (written to out_off), the ranges' totals are scanned across the
+  // wavefronts, and a second coalesced pass adds each range's base.
+  const int lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
+  const int per_w = (n + nw - 1) / nw;
+  const int w0 = min(n, wave * per_w), w1 = min(n, w0 + per_w);
+  constexpr int kB = 4;
+  long long run_v = 0, run_k = 0;  // the range so far (every lane)
+  for (int gb = w0; gb < w1; gb += kB * 64) {
+    long long kv[kB], vv[kB];
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
-      const int c = min(cb + u, c1 - 1);
-      kv[u] = a.cnt[c];
-      nv[u] = a.chunks[a.chunk_begin + c].n_valid;
+      const int c = gb + u * 64 + lane;
+      const int cc = min(c, w1 - 1);
+      const long long k = a.cnt[cc];
+      const long long v = (long long)a.chunks[a.chunk_begin + cc].n_valid + k;
+      kv[u] = c < w1 ? k : 0;
+      vv[u] = c < w1 ? v : 0;
     }
-  };
-  long long sv = 0, sk = 0;
-  for (int cb = c0; cb < c1; cb += kB) {
-    long long kv[kB], nv[kB];
-    fetch(cb, kv, nv);
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
-      if (cb + u < c1) {
-        sv += nv[u] + kv[u];
-        sk += kv[u];
-      }
+      const int c = gb + u * 64 + lane;
+      const long long iv = wave_incl_scan(vv[u], [](long long x, long long y) { return x + y; });
+      const long long ik = wave_incl_scan(kv[u], [](long long x, long long y) { return x + y; });
+      if (c < w1) a.out_off[c] = run_v + iv - vv[u];
+      run_v += from_lane63(iv);
+      run_k += from_lane63(ik);
     }
   }
-  const long long iv = block_incl_scan(sv, sW);
-  if (tid == nth - 1) sTot[0] = iv;
-  const long long ik = block_incl_scan(sk, sW);
-  if (tid == nth - 1) sTot[1] = ik;
-  long long run = iv - sv;
-  for (int cb = c0; cb < c1; cb += kB) {
-    long long kv[kB], nv[kB];
-    fetch(cb, kv, nv);
-#pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      if (cb + u < c1) {
-        a.out_off[cb + u] = run;
-        run += nv[u] + kv[u];
-      }
-    }
+  if (lane == 0) {
+    sW[wave] = run_v;
+    sTk[wave] = run_k;
+  }
+  __syncthreads();
+  long long base_v = 0, tot_v = 0, tot_k = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (w < wave) base_v += sW[w];
+    tot_v += sW[w];
+    tot_k += sTk[w];
+  }
+#pragma unroll 4
+  for (int c = w0 + lane; c < w1; c += 64) a.out_off[c] += base_v;
+  if (tid == 0) {
+    sTot[0] = tot_v;
+    sTot[1] = tot_k;
   }
   __syncthreads();
   const long long carry = sTot[0], inserted = sTot[1];
