@@ -111,3 +111,25 @@ def test_refining_simulation_reports_its_path():
     with B.Simulation(p, l_max=p.L / 16, max_tracers=16 * p.total_tracers) as s:
         s.step(3)
         assert B.sic_last_step_path(s.h) == B.SIC_PATH_REFINING
+
+
+def test_single_simulation_launch_shapes_and_paths():
+    """The item rules of a single simulation and the path they lead to:
+    256-cell Landau, 256 items of 8 chunks (one per CU); two-stream on 1024
+    cells, 512 items of 64 chunks; a million tracers on 100 cells, items
+    capped at 256 (contention on a small mesh) instead of 2048; a 4096-cell
+    simulation of 2048 workgroups keeps the launch pairs (solve-first only up
+    to 512)."""
+    cases = [
+        (I.landau(), 8, 512, 256, B.SIC_PATH_SOLVE_FIRST),
+        (I.two_stream(n_steps=2), 64, 512, 512, B.SIC_PATH_SOLVE_FIRST),
+        (I.landau(n_sheets=2, n_tracers=524288, n_cells=100, n_steps=2), 64, 512, 256, B.SIC_PATH_SOLVE_FIRST),
+        (I.landau(n_sheets=2048, n_tracers=16384, n_cells=4096, n_steps=2), 256, 1024, 2048, B.SIC_PATH_FUSED),
+    ]
+    for p, tile, block, grid, path in cases:
+        print(f"case shapes {p.n_sheets}x{int(p.n_tracers[0])} on {p.n_cells} cells", flush=True)
+        with B.Simulation(p, precision=B.SIC_FP64, history_rows=8) as s:
+            t = B.sic_get_tuning(s.h)
+            assert (t["tile_chunks"], t["block_threads"], t["grid_blocks"]) == (tile, block, grid)
+            s.step(2)
+            assert B.sic_last_step_path(s.h) == path
